@@ -1,0 +1,260 @@
+/*
+ * fte.h - C ABI of the MI355X focused-transport pseudo-particle library.
+ *
+ * The library integrates independent energetic test particles through the
+ * focused transport equation (FTE) written as Ito stochastic differential
+ * equations: streaming along the mean magnetic field plus solar-wind
+ * advection, magnetic focusing, adiabatic deceleration, pitch-angle
+ * scattering and optional cross-field diffusion (arXiv:2404.12164, section
+ * 2.1, Eqs. 1-5).  The solar-wind velocity V and field B come from snapshots
+ * on a stretched, block-AMR spherical grid (section 2.4); observer intensities
+ * j = p^2 f (section 2.3) are accumulated in time x energy bins.
+ *
+ * Conventions for every entry point:
+ *  - SI units throughout (m, s, kg, J, rad).
+ *  - Every call returns fte_status; FTE_OK == 0.  On failure a message is
+ *    available from fte_last_error() and the context is left unchanged
+ *    (argument errors) or must be destroyed (FTE_EDEVICE).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Device work is enqueued on it; fte_step_n and fte_inject return without
+ *    waiting.  fte_load_grid, fte_bin_observers, fte_get_stats and
+ *    fte_read_particles synchronise the stream before returning.
+ *  - Device buffers are owned by the caller (allocated with the sizes from
+ *    fte_query_sizes, e.g. as torch tensors) and must outlive the context.
+ *    The library never allocates or frees device memory.  Host arrays passed
+ *    in are only read during the call.
+ *  - One context is used from one thread at a time.
+ *  - Per-particle non-finite results are not errors: the particle is retired
+ *    with status FTE_PS_NUMERIC and counted in fte_stats.
+ */
+#ifndef FTE_H
+#define FTE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fte_ctx fte_ctx;
+typedef int fte_status;
+
+enum {
+    FTE_OK = 0,
+    FTE_EINVAL = -1,   /* invalid argument or inconsistent description          */
+    FTE_ESTATE = -2,   /* call out of order (e.g. step before load/inject)      */
+    FTE_ENOMEM = -3,   /* a bound buffer is too small for the request           */
+    FTE_EDEVICE = -4,  /* a HIP call failed                                     */
+    FTE_ERANGE = -5    /* the requested steps leave the grid's time range       */
+};
+
+/* arithmetic of the step kernel */
+enum {
+    FTE_FP64 = 0,      /* all arithmetic and grid records in double precision   */
+    FTE_MIXED = 1      /* float records and step arithmetic; position, time and
+                          the radial boundary tests stay in double             */
+};
+
+/* pitch-angle diffusion coefficient D_mumu(mu) = A g(mu) (section 2.1) */
+enum {
+    FTE_DMM_ISO = 0,     /* g = 1 - mu^2                                        */
+    FTE_DMM_EQ5 = 1,     /* g = (|mu|/(1+|mu|) + eps)(1 - mu^2), Eq. 5          */
+    FTE_DMM_POWER_Q = 2  /* g = (1 - mu^2)|mu|^(q-1), 1 < q < 2                 */
+};
+
+/* particle status codes in the state buffers */
+enum {
+    FTE_PS_ACTIVE = 0,
+    FTE_PS_ABSORBED_IN = 1,   /* crossed r < r_in                               */
+    FTE_PS_ABSORBED_OUT = 2,  /* crossed r > r_out                              */
+    FTE_PS_OUT_OF_DOMAIN = 3, /* colatitude left the grid's range               */
+    FTE_PS_NUMERIC = 4        /* non-finite state or vanishing b                */
+};
+
+#define FTE_MAX_OBS 8
+#define FTE_MAX_LEVELS 8
+#define FTE_MAX_BATCH 64
+
+/* Spherical-box observer volume: r, theta, phi centre and full widths. */
+typedef struct {
+    double r, theta, phi;
+    double dr, dtheta, dphi;
+} fte_observer;
+
+/* Physics and run parameters (fixed for the life of a context). */
+typedef struct {
+    double mass;          /* rest mass of the species, kg                          */
+    int dmm_model;        /* FTE_DMM_*                                             */
+    int dmm_norm;         /* 0: A = 3 v I / (8 lambda_par) so that lambda_par =
+                             3 kappa_par / v with kappa_par = (v^2/8) Int (1-mu^2)^2/D;
+                             1: A = v / lambda_par                                 */
+    double lambda_ref;    /* parallel mean free path at momentum p_ref, m          */
+    double p_ref;         /* reference momentum in units of m c                   */
+    double alpha;         /* lambda_par = lambda_ref (p / p_ref)^alpha             */
+    double q;             /* exponent of FTE_DMM_POWER_Q                           */
+    double eps;           /* resonance-gap parameter of FTE_DMM_EQ5 (Eq. 5)        */
+    double mu_floor;      /* |mu| floor inside |mu|^(q-2) of the POWER_Q drift     */
+    double kperp_ratio;   /* kappa_perp = ratio * v lambda_par / 3 when > 0        */
+    double lambda_perp;   /* otherwise kappa_perp = v lambda_perp / 3 when > 0     */
+    double dt;            /* global time step, s                                   */
+    double t0;            /* time of global step 0, s                              */
+    double r_in, r_out;   /* absorbing spheres, m                                  */
+    uint64_t seed;        /* Philox key                                            */
+    int run_id;           /* 0..65535, part of the Philox counter                  */
+    int precision;        /* FTE_FP64 or FTE_MIXED                                 */
+    int n_obs;            /* 0..FTE_MAX_OBS                                        */
+    fte_observer obs[FTE_MAX_OBS];
+    double e_min;         /* lower kinetic-energy edge of bin 0, J                 */
+    double dlne;          /* bin width in ln E                                     */
+    int n_e;              /* energy bins                                           */
+    double t_ref;         /* lower edge of time bin 0, s                           */
+    double dT;            /* time-bin width, s                                     */
+    int n_t;              /* time bins                                             */
+    int n_batch;          /* 1..FTE_MAX_BATCH; batch = pid mod n_batch             */
+} fte_params;
+
+/* Block-AMR spherical grid (section 2.4).  Coordinates (xi, theta, phi), with
+ * xi = r - r_lo (xi_map 0) or ln(r / r_lo) (xi_map 1, radial stretching).
+ * Level-1 cells are uniform in each coordinate; each level halves its parent
+ * block along all three coordinates; every block holds bx[0] x bx[1] x bx[2]
+ * cells.  Leaves must tile the domain and blocks touching face-wise or
+ * diagonally may differ by at most one level.  bx[a] must be even and >= 4,
+ * and divisible by 4 when n_levels >= 3; n1[a] must be a multiple of bx[a]. */
+typedef struct {
+    int xi_map;
+    double r_lo, dxi;     /* radial origin (m) and level-1 width in xi            */
+    double th_lo, dth;    /* colatitude origin and level-1 width, rad             */
+    double ph_lo, dph;    /* longitude origin and level-1 width, rad              */
+    int phi_periodic;     /* 1: n1[2] * dph spans 2 pi and phi wraps              */
+    int n1[3];            /* level-1 cells along xi, theta, phi                   */
+    int bx[3];            /* cells per block                                      */
+    int n_levels;         /* 1..FTE_MAX_LEVELS                                    */
+    int n_leaves;
+    const int32_t *leaves;/* host, [n_leaves][4] = level, I, J, K (block index at
+                             that level); list order defines leaf ids             */
+    int n_snap;           /* snapshots; 1 = steady                                */
+    double t_s0, dt_s;    /* snapshot k is at t_s0 + k dt_s                       */
+} fte_grid_desc;
+
+/* Particle source for fte_inject (the synthetic workloads' injection; with
+ * r_weight set it carries the r^-2 statistical weight of section 2.3, Eq. 6).
+ * Draws use the injection Philox stream of each pid: isotropic mu, position
+ * uniform in solid angle over [th_lo, th_hi] x [ph_lo, ph_hi] at radius r,
+ * kinetic energy log-uniform on [e_lo, e_hi] (monoenergetic if equal) with
+ * weight w0 (E/e_lo)^(1 - gamma_inj) (an E^-gamma_inj number spectrum),
+ * and first step k0 + floor((pid - pid0 + u) n_inj_steps / n_total)
+ * (stratified continuous injection; all at k0 when n_inj_steps == 0). */
+typedef struct {
+    double r;
+    double th_lo, th_hi, ph_lo, ph_hi;
+    double e_lo, e_hi;
+    double gamma_inj;
+    double w0;
+    int r_weight;         /* 1: multiply the weight by (r_ref / r)^2              */
+    double r_ref;
+    uint64_t pid0;        /* first pid of the whole injection                     */
+    uint64_t n_total;     /* particles of the whole injection (>= 1)              */
+    uint32_t k0;
+    uint32_t n_inj_steps;
+} fte_injection;
+
+/* Byte sizes of the caller-owned device buffers. */
+typedef struct {
+    uint64_t grid_bytes;   /* derived-field records of every snapshot             */
+    uint64_t index_bytes;  /* block index and leaf table                          */
+    uint64_t state_bytes;  /* one particle state buffer (two are bound)           */
+    uint64_t hist_bytes;   /* observer batch sums                                 */
+    uint64_t work_bytes;   /* counters, load-time workspace, finalize output      */
+} fte_sizes;
+
+/* Device pointers, each at least the matching fte_sizes bytes, 256-byte
+ * aligned. */
+typedef struct {
+    void *grid, *index, *state_a, *state_b, *hist, *work;
+} fte_buffers;
+
+typedef struct {
+    uint64_t n_live;          /* particles held (active or not yet started)     */
+    uint64_t n_injected;
+    uint64_t particle_steps;  /* steps taken by active particles                */
+    uint64_t n_retired[5];    /* by FTE_PS_* (index 0 unused)                   */
+    double w_injected;
+    double w_retired[5];
+    uint64_t global_step;     /* next global step index                         */
+    uint32_t device_flags;    /* nonzero: a kernel met an unsupported case      */
+} fte_stats;
+
+/* Record layout of the grid buffer (for readers of the raw buffer):
+ * record(snap, leaf, pcell) at element ((snap * n_leaves + leaf) * pcells +
+ * pcell) * FTE_RECORD_STRIDE, elements of double (FTE_FP64) or float
+ * (FTE_MIXED).  pcell = (i+1) + (bx+2) ((j+1) + (by+2)(k+1)) for local cell
+ * (i, j, k) in [-1, bx] x [-1, by] x [-1, bz]: a one-cell ghost layer.
+ * Record fields: 0-2 V (r, theta, phi components), 3-5 b = B/|B| (same),
+ * 6 div V, 7 bb:grad V, 8 div b, 9 b . (dV/dt + (V . grad)V), 10-12
+ * (b . grad) b (spherical components). */
+#define FTE_RECORD_STRIDE 16
+#define FTE_RECORD_FIELDS 13
+
+/* Particle state buffer layout for capacity n_max: arrays of n_max entries
+ * in this order: x, y, z, mu, lnp (ln of p / (m c)), w (all double), pid
+ * (uint64), kinj (uint32), status (int32). */
+
+fte_status fte_create(fte_ctx **out, const fte_params *p);
+void fte_destroy(fte_ctx *ctx);
+const char *fte_last_error(const fte_ctx *ctx);
+
+/* Buffer sizes for a grid and a particle capacity n_max (no device work). */
+fte_status fte_query_sizes(const fte_params *p, const fte_grid_desc *g, uint64_t n_max, fte_sizes *out);
+
+/* Attach the grid description (validated: tiling, 2:1 nesting, block shape)
+ * and the caller's device buffers.  Resets particles and histograms. */
+fte_status fte_bind_buffers(fte_ctx *ctx, const fte_grid_desc *g, uint64_t n_max, const fte_buffers *b);
+
+/* Load the wind snapshots (section 2.4): vb_sph is DEVICE memory holding
+ * double [n_snap][n_leaves][cells][6] = V_r, V_theta, V_phi, B_r, B_theta,
+ * B_phi at leaf cell centres, cells ordered xi fastest, then theta, then phi
+ * (cell centres at the midpoints in xi, theta, phi).  Builds the block index,
+ * fills the ghost layers by the block-boundary value rule, derives the fields
+ * of Eqs. 2-4 (gradients by central differences), and writes the records.
+ * vb_sph is only read during the call.  Synchronises `stream`.  Returns
+ * FTE_EINVAL if the data hold non-finite values or |B| = 0. */
+fte_status fte_load_grid(fte_ctx *ctx, const double *vb_sph, void *stream);
+
+/* Append n particles with pids first_pid .. first_pid+n-1 drawn from `inj`
+ * (see fte_injection).  Requires a loaded grid.  FTE_ENOMEM if the state
+ * capacity would be exceeded. */
+fte_status fte_inject(fte_ctx *ctx, const fte_injection *inj, uint64_t n, uint64_t first_pid, void *stream);
+
+/* Advance every held particle through the next n_steps global steps
+ * (Euler-Maruyama, lock-step clock t_n = t0 + n dt).  A particle takes step n
+ * only when n >= its kinj.  Observer sums are accumulated in the same pass.
+ * Retired particles are removed periodically.  FTE_ERANGE if a time-dependent
+ * grid does not cover t_n for every step. */
+fte_status fte_step_n(fte_ctx *ctx, uint32_t n_steps, void *stream);
+
+/* Intensities j[o][e][t] = S / (4 pi dV dT dE W_inj) and their standard errors
+ * from the n_batch batch sums, written to HOST arrays of n_obs*n_e*n_t doubles
+ * (either may be NULL).  reset != 0 clears the sums afterwards.  Synchronises. */
+fte_status fte_bin_observers(fte_ctx *ctx, double *j, double *sigma, int reset, void *stream);
+
+/* Raw batch sums S[o][e][t][batch] (host array of n_obs*n_e*n_t*n_batch) and
+ * the injected weight.  Synchronises. */
+fte_status fte_read_hist(fte_ctx *ctx, double *sums, double *w_injected, void *stream);
+
+fte_status fte_get_stats(fte_ctx *ctx, fte_stats *out, void *stream);
+
+/* Copy the held particles to HOST arrays of at least n_live entries (any may
+ * be NULL); x3 is [n][3].  *n_out receives n_live.  Order is the storage
+ * order (not pid order).  Synchronises. */
+fte_status fte_read_particles(fte_ctx *ctx, double *x3, double *mu, double *lnp, double *w, uint64_t *pid,
+                              uint32_t *kinj, int32_t *status, uint64_t cap, uint64_t *n_out, void *stream);
+
+/* Launch shape: threads per block (64..1024, multiple of 64), steps per
+ * kernel launch, and retired-particle removal every `compact_every` steps (a
+ * multiple of steps_per_launch; 0 = never).  Defaults 256 / 64 / 512. */
+fte_status fte_set_launch(fte_ctx *ctx, int block, int steps_per_launch, int compact_every);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

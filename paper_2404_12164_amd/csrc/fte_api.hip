@@ -1,0 +1,638 @@
+// Host side of the C ABI declared in include/fte.h: argument and grid
+// validation, the block-AMR index, buffer carving, and the ordering of the
+// kernel launches on the caller's stream.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <climits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fte.h"
+#include "fte_internal.hpp"
+
+using namespace fte;
+
+struct fte_ctx {
+    fte_params p{};
+    DevParams dp{};
+    bool bound = false, loaded = false;
+    fte_grid_desc g{};
+    std::vector<int32_t> leaves, base, child, info;
+    DevGrid dg{};
+    uint64_t n_max = 0;
+    fte_buffers b{};
+    DevState st[2]{};
+    int cur = 0;
+    DevCounters *cnt = nullptr;
+    double *fin_j = nullptr, *fin_s = nullptr, *cart = nullptr;
+    uint64_t hist_n = 0;
+    uint64_t n_upper = 0, injected_since = 0;
+    unsigned long long *pinned = nullptr;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+    uint64_t global_step = 0;
+    int block = 256, spl = 64, compact_every = 512;
+    uint64_t since_compact = 0;
+    std::string err;
+};
+
+namespace {
+
+fte_status fail(fte_ctx *c, fte_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(ctx, FTE_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
+
+std::string check_params(const fte_params *p) {
+    if (!p) return "params is NULL";
+    if (!finite_pos(p->mass)) return "mass must be > 0";
+    if (p->dmm_model < 0 || p->dmm_model > 2) return "unknown dmm_model";
+    if (p->dmm_norm < 0 || p->dmm_norm > 1) return "dmm_norm must be 0 or 1";
+    if (!finite_pos(p->lambda_ref)) return "lambda_ref must be > 0";
+    if (p->alpha != 0.0 && !finite_pos(p->p_ref)) return "p_ref must be > 0 when alpha != 0";
+    if (p->dmm_model == FTE_DMM_POWER_Q && !(p->q > 1.0 && p->q < 2.0)) return "power-law q must be in (1, 2)";
+    if (p->dmm_model == FTE_DMM_POWER_Q && !finite_pos(p->mu_floor)) return "mu_floor must be > 0";
+    if (p->dmm_model == FTE_DMM_EQ5 && !finite_pos(p->eps)) return "eps must be > 0 for Eq. 5";
+    if (p->kperp_ratio < 0.0 || p->lambda_perp < 0.0) return "kappa_perp parameters must be >= 0";
+    if (!finite_pos(p->dt)) return "dt must be > 0";
+    if (!isfinite(p->t0)) return "t0 must be finite";
+    if (!(p->r_in >= 0.0) || !(p->r_out > p->r_in)) return "need 0 <= r_in < r_out";
+    if (p->run_id < 0 || p->run_id > 0xFFFF) return "run_id must fit 16 bits";
+    if (p->precision != FTE_FP64 && p->precision != FTE_MIXED) return "unknown precision";
+    if (p->n_obs < 0 || p->n_obs > FTE_MAX_OBS) return "n_obs out of range";
+    if (p->n_batch < 1 || p->n_batch > FTE_MAX_BATCH) return "n_batch out of range";
+    if (p->n_obs > 0) {
+        if (!finite_pos(p->e_min) || !finite_pos(p->dlne) || p->n_e < 1) return "bad energy bins";
+        if (!finite_pos(p->dT) || p->n_t < 1 || !isfinite(p->t_ref)) return "bad time bins";
+        if ((double)p->n_obs * p->n_e * p->n_t * p->n_batch > 2e9) return "too many observer bins";
+        for (int o = 0; o < p->n_obs; ++o) {
+            const fte_observer &ob = p->obs[o];
+            if (!finite_pos(ob.r) || !finite_pos(ob.dr) || !finite_pos(ob.dtheta) || !finite_pos(ob.dphi) ||
+                ob.dr >= 2 * ob.r || !isfinite(ob.theta) || !isfinite(ob.phi) || ob.dphi > 2 * kPi)
+                return "bad observer box";
+        }
+    }
+    return "";
+}
+
+// Build the block index from the leaf list and check that the leaves tile the
+// domain and obey the 2:1 nesting rule.
+std::string build_index(const fte_grid_desc *g, std::vector<int32_t> &base, std::vector<int32_t> &child,
+                        std::vector<int32_t> &info) {
+    if (!g) return "grid description is NULL";
+    if (g->xi_map != 0 && g->xi_map != 1) return "xi_map must be 0 or 1";
+    if (!finite_pos(g->r_lo) || !finite_pos(g->dxi) || !finite_pos(g->dth) || !finite_pos(g->dph))
+        return "grid origin and widths must be > 0";
+    if (g->n_levels < 1 || g->n_levels > FTE_MAX_LEVELS) return "n_levels out of range";
+    for (int a = 0; a < 3; ++a) {
+        if (g->bx[a] < 4 || (g->bx[a] & 1)) return "block cells must be even and >= 4";
+        if (g->n_levels >= 3 && (g->bx[a] & 3)) return "block cells must be divisible by 4 with >= 3 levels";
+        if (g->n1[a] < g->bx[a] || g->n1[a] % g->bx[a]) return "n1 must be a positive multiple of bx";
+        if ((long)g->n1[a] << (g->n_levels - 1) > (1L << 26)) return "grid too fine";
+    }
+    if (!(g->th_lo >= 0.0) || !(g->th_lo + g->n1[1] * g->dth <= kPi + 1e-12)) return "colatitude range outside [0, pi]";
+    if (g->phi_periodic && fabs(g->n1[2] * g->dph - 2 * kPi) > 1e-9) return "periodic phi must span 2 pi";
+    if (g->n_snap < 1) return "n_snap must be >= 1";
+    if (g->n_snap >= 2 && !finite_pos(g->dt_s)) return "dt_s must be > 0";
+    if (g->n_leaves < 1 || !g->leaves) return "no leaves";
+    const int nb1[3] = {g->n1[0] / g->bx[0], g->n1[1] / g->bx[1], g->n1[2] / g->bx[2]};
+    const long nbase = (long)nb1[0] * nb1[1] * nb1[2];
+    const int32_t EMPTY = INT_MIN;
+    base.assign(nbase, EMPTY);
+    child.clear();
+    info.assign((size_t)g->n_leaves * 4, 0);
+    for (int l = 0; l < g->n_leaves; ++l) {
+        const int32_t *e = g->leaves + 4 * l;
+        const int L = e[0];
+        if (L < 1 || L > g->n_levels) return "leaf level out of range";
+        for (int a = 0; a < 3; ++a)
+            if (e[1 + a] < 0 || e[1 + a] >= (nb1[a] << (L - 1))) return "leaf block index out of range";
+        for (int a = 0; a < 4; ++a) info[4 * l + a] = e[a];
+        const int B0 = e[1] >> (L - 1), B1 = e[2] >> (L - 1), B2 = e[3] >> (L - 1);
+        // slot = (which table, index): child may grow, so no pointers into it
+        bool in_child = false;
+        size_t at = B0 + (size_t)nb1[0] * (B1 + (size_t)nb1[1] * B2);
+        for (int m = 1; m < L; ++m) {
+            int32_t v = in_child ? child[at] : base[at];
+            if (v >= 0) return "leaves overlap (a leaf covers a refined region)";
+            if (v == EMPTY) {
+                const int grp = (int)(child.size() / 8);
+                child.insert(child.end(), 8, EMPTY);
+                v = -(grp + 1);
+                (in_child ? child[at] : base[at]) = v;
+            }
+            const int grp = -v - 1;
+            const int sh = L - (m + 1);
+            const int s = ((e[1] >> sh) & 1) | (((e[2] >> sh) & 1) << 1) | (((e[3] >> sh) & 1) << 2);
+            in_child = true;
+            at = (size_t)grp * 8 + s;
+        }
+        int32_t &slot = in_child ? child[at] : base[at];
+        if (slot != EMPTY) return "leaves overlap";
+        slot = l;
+    }
+    for (auto v : base)
+        if (v == EMPTY) return "leaves do not cover the domain";
+    for (auto v : child)
+        if (v == EMPTY) return "leaves do not cover the domain";
+    // 2:1 nesting across faces, edges and corners
+    for (int l = 0; l < g->n_leaves; ++l) {
+        const int32_t *e = g->leaves + 4 * l;
+        const int L = e[0];
+        if (L < 3) continue;
+        const int nb[3] = {nb1[0] << (L - 1), nb1[1] << (L - 1), nb1[2] << (L - 1)};
+        for (int dI = -1; dI <= 1; ++dI)
+            for (int dJ = -1; dJ <= 1; ++dJ)
+                for (int dK = -1; dK <= 1; ++dK) {
+                    int q[3] = {e[1] + dI, e[2] + dJ, e[3] + dK};
+                    if (q[0] < 0 || q[0] >= nb[0] || q[1] < 0 || q[1] >= nb[1]) continue;
+                    if (q[2] < 0 || q[2] >= nb[2]) {
+                        if (!g->phi_periodic) continue;
+                        q[2] = (q[2] + nb[2]) % nb[2];
+                    }
+                    int32_t node = base[(q[0] >> (L - 1)) + (long)nb1[0] * ((q[1] >> (L - 1)) +
+                                                                            (long)nb1[1] * (q[2] >> (L - 1)))];
+                    int m = 1;
+                    while (node < 0 && m < L) {
+                        ++m;
+                        const int sh = L - m;
+                        const int s = ((q[0] >> sh) & 1) | (((q[1] >> sh) & 1) << 1) | (((q[2] >> sh) & 1) << 2);
+                        node = child[(size_t)(-node - 1) * 8 + s];
+                    }
+                    if (node >= 0 && m < L - 1) return "2:1 nesting violated between neighbouring blocks";
+                }
+    }
+    return "";
+}
+
+size_t rec_elem(const fte_params *p) { return p->precision == FTE_FP64 ? 8 : 4; }
+
+struct Layout {
+    size_t grid, index, state, hist, work;
+    size_t off_child, off_info;
+    size_t off_j, off_s, off_cart;
+    int pcells;
+};
+
+Layout layout(const fte_params *p, const fte_grid_desc *g, uint64_t n_max, size_t n_base, size_t n_child) {
+    Layout L{};
+    L.pcells = (g->bx[0] + 2) * (g->bx[1] + 2) * (g->bx[2] + 2);
+    L.grid = (size_t)g->n_snap * g->n_leaves * L.pcells * kRS * rec_elem(p);
+    L.off_child = align256(n_base * 4);
+    L.off_info = L.off_child + align256(std::max<size_t>(n_child, 8) * 4);
+    L.index = L.off_info + align256((size_t)g->n_leaves * 16);
+    L.state = state_bytes(n_max);
+    const size_t nbins = (size_t)p->n_obs * p->n_e * p->n_t;
+    L.hist = std::max<size_t>(nbins * p->n_batch * 8, 256);
+    L.off_j = align256(sizeof(DevCounters));
+    L.off_s = L.off_j + align256(std::max<size_t>(nbins, 1) * 8);
+    L.off_cart = L.off_s + align256(std::max<size_t>(nbins, 1) * 8);
+    L.work = L.off_cart + align256((size_t)g->n_leaves * L.pcells * 6 * 8);
+    return L;
+}
+
+void make_devparams(const fte_params *p, DevParams *d) {
+    memset(d, 0, sizeof(*d));
+    d->mass_c2 = p->mass * kC * kC;
+    d->dt = p->dt;
+    d->t0 = p->t0;
+    d->r_in = p->r_in;
+    d->r_out = p->r_out;
+    d->lambda_ref = p->lambda_ref;
+    d->inv_p_ref = p->alpha != 0.0 ? 1.0 / p->p_ref : 1.0;
+    d->alpha = p->alpha;
+    d->q = p->q;
+    d->eps = p->eps;
+    d->mu_floor = p->mu_floor;
+    // scale of D_mumu: A = dmm_scale * v / lambda_par
+    double I;
+    if (p->dmm_model == FTE_DMM_ISO) {
+        I = 4.0 / 3.0;
+    } else if (p->dmm_model == FTE_DMM_EQ5) {
+        // I = 2 Int_0^1 (1-m)(1+m)^2 / ((1+eps) m + eps) dm in closed form:
+        // substitute s = (1+eps) m + eps and integrate the resulting cubic / s
+        const double a = 1.0 + p->eps, b = p->eps;
+        // N(m) = 1 + m - m^2 - m^3 with m = (s - b)/a
+        // coefficients of N as a polynomial in s
+        const double ia = 1.0 / a;
+        const double c3 = -ia * ia * ia;
+        const double c2 = -ia * ia + 3.0 * b * ia * ia * ia;
+        const double c1 = ia + 2.0 * b * ia * ia - 3.0 * b * b * ia * ia * ia;
+        const double c0 = 1.0 - b * ia - b * b * ia * ia + b * b * b * ia * ia * ia;
+        const double s0 = b, s1 = a + b;
+        const double integ = c3 * (s1 * s1 * s1 - s0 * s0 * s0) / 3.0 + c2 * (s1 * s1 - s0 * s0) / 2.0 +
+                             c1 * (s1 - s0) + c0 * log(s1 / s0);
+        I = 2.0 * integ / a;
+    } else {
+        I = 4.0 / ((2.0 - p->q) * (4.0 - p->q));
+    }
+    d->dmm_scale = p->dmm_norm == 1 ? 1.0 : 3.0 * I / 8.0;
+    d->kperp_ratio = p->kperp_ratio;
+    d->lambda_perp = p->lambda_perp;
+    d->e_min = p->e_min;
+    d->dlne = p->dlne;
+    d->dT = p->dT;
+    d->e_min_ln = p->n_obs > 0 ? log(p->e_min) : 0.0;
+    d->inv_dlne = p->n_obs > 0 ? 1.0 / p->dlne : 0.0;
+    d->t_ref = p->t_ref;
+    d->inv_dT = p->n_obs > 0 ? 1.0 / p->dT : 0.0;
+    for (int o = 0; o < p->n_obs; ++o) {
+        const fte_observer &ob = p->obs[o];
+        d->obs[o][0] = ob.r - 0.5 * ob.dr;
+        d->obs[o][1] = ob.r + 0.5 * ob.dr;
+        d->obs[o][2] = ob.theta - 0.5 * ob.dtheta;
+        d->obs[o][3] = ob.theta + 0.5 * ob.dtheta;
+        d->obs[o][4] = ob.phi;
+        d->obs[o][5] = 0.5 * ob.dphi;
+    }
+    d->seed = p->seed;
+    d->dmm_model = p->dmm_model;
+    d->run_id = p->run_id;
+    d->n_obs = p->n_obs;
+    d->n_e = p->n_obs > 0 ? p->n_e : 1;
+    d->n_t = p->n_obs > 0 ? p->n_t : 1;
+    d->n_batch = p->n_batch;
+}
+
+}  // namespace
+
+namespace fte {
+
+size_t state_bytes(uint64_t n) {
+    return 6 * align256(n * 8) + align256(n * 8) + align256(n * 4) + align256(n * 4);
+}
+
+DevState state_view(void *base, uint64_t n) {
+    char *c = (char *)base;
+    DevState s;
+    const size_t a8 = align256(n * 8), a4 = align256(n * 4);
+    s.x = (double *)c;
+    s.y = (double *)(c + a8);
+    s.z = (double *)(c + 2 * a8);
+    s.mu = (double *)(c + 3 * a8);
+    s.lnp = (double *)(c + 4 * a8);
+    s.w = (double *)(c + 5 * a8);
+    s.pid = (uint64_t *)(c + 6 * a8);
+    s.kinj = (uint32_t *)(c + 7 * a8);
+    s.status = (int32_t *)(c + 7 * a8 + a4);
+    return s;
+}
+
+}  // namespace fte
+
+extern "C" {
+
+fte_status fte_create(fte_ctx **out, const fte_params *p) {
+    if (!out) return FTE_EINVAL;
+    *out = nullptr;
+    const std::string e = check_params(p);
+    if (!e.empty()) return FTE_EINVAL;
+    fte_ctx *c = new (std::nothrow) fte_ctx();
+    if (!c) return FTE_ENOMEM;
+    c->p = *p;
+    make_devparams(p, &c->dp);
+    if (hipHostMalloc((void **)&c->pinned, sizeof(unsigned long long)) != hipSuccess) {
+        delete c;
+        return FTE_EDEVICE;
+    }
+    if (hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(c->pinned);
+        delete c;
+        return FTE_EDEVICE;
+    }
+    *out = c;
+    return FTE_OK;
+}
+
+void fte_destroy(fte_ctx *c) {
+    if (!c) return;
+    if (c->ev) (void)hipEventDestroy(c->ev);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    delete c;
+}
+
+const char *fte_last_error(const fte_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+fte_status fte_query_sizes(const fte_params *p, const fte_grid_desc *g, uint64_t n_max, fte_sizes *out) {
+    if (!out) return FTE_EINVAL;
+    if (!check_params(p).empty()) return FTE_EINVAL;
+    std::vector<int32_t> base, child, info;
+    if (!build_index(g, base, child, info).empty()) return FTE_EINVAL;
+    const Layout L = layout(p, g, n_max, base.size(), child.size());
+    out->grid_bytes = L.grid;
+    out->index_bytes = L.index;
+    out->state_bytes = L.state;
+    out->hist_bytes = L.hist;
+    out->work_bytes = L.work;
+    return FTE_OK;
+}
+
+fte_status fte_bind_buffers(fte_ctx *c, const fte_grid_desc *g, uint64_t n_max, const fte_buffers *b) {
+    if (!c) return FTE_EINVAL;
+    if (!b) return fail(c, FTE_EINVAL, "buffers is NULL");
+    std::vector<int32_t> base, child, info;
+    const std::string e = build_index(g, base, child, info);
+    if (!e.empty()) return fail(c, FTE_EINVAL, e);
+    if (n_max == 0 || n_max > (1ull << 40)) return fail(c, FTE_EINVAL, "n_max out of range");
+    const void *ptrs[6] = {b->grid, b->index, b->state_a, b->state_b, b->hist, b->work};
+    for (int k = 0; k < 6; ++k)
+        if (!ptrs[k] || ((uintptr_t)ptrs[k] & 255)) return fail(c, FTE_EINVAL, "buffers must be non-NULL, 256-byte aligned");
+    const Layout L = layout(&c->p, g, n_max, base.size(), child.size());
+    c->g = *g;
+    c->leaves.assign(g->leaves, g->leaves + 4 * (size_t)g->n_leaves);
+    c->g.leaves = c->leaves.data();
+    c->base.swap(base);
+    c->child.swap(child);
+    c->info.swap(info);
+    c->n_max = n_max;
+    c->b = *b;
+    c->st[0] = state_view(b->state_a, n_max);
+    c->st[1] = state_view(b->state_b, n_max);
+    c->cur = 0;
+    char *w = (char *)b->work;
+    c->cnt = (DevCounters *)w;
+    c->fin_j = (double *)(w + L.off_j);
+    c->fin_s = (double *)(w + L.off_s);
+    c->cart = (double *)(w + L.off_cart);
+    c->hist_n = (uint64_t)c->p.n_obs * c->p.n_e * c->p.n_t * c->p.n_batch;
+
+    DevGrid &d = c->dg;
+    memset(&d, 0, sizeof(d));
+    d.r_lo = g->r_lo;
+    d.dxi = g->dxi;
+    d.dth = g->dth;
+    d.dph = g->dph;
+    d.inv_dxi = 1.0 / g->dxi;
+    d.th_lo = g->th_lo;
+    d.inv_dth = 1.0 / g->dth;
+    d.ph_lo = g->ph_lo;
+    d.inv_dph = 1.0 / g->dph;
+    d.th_hi = g->th_lo + g->n1[1] * g->dth;
+    d.t_s0 = g->t_s0;
+    d.dt_s = g->n_snap >= 2 ? g->dt_s : 1.0;
+    d.inv_dt_s = 1.0 / d.dt_s;
+    d.xi_map = g->xi_map;
+    d.periodic = g->phi_periodic;
+    for (int a = 0; a < 3; ++a) {
+        d.n1[a] = g->n1[a];
+        d.bx[a] = g->bx[a];
+        d.px[a] = g->bx[a] + 2;
+        d.nb1[a] = g->n1[a] / g->bx[a];
+    }
+    d.n_levels = g->n_levels;
+    d.n_leaves = g->n_leaves;
+    d.n_snap = g->n_snap;
+    d.n_base = (int)c->base.size();
+    d.n_child = (int)c->child.size();
+    d.pcells = L.pcells;
+    d.cells = g->bx[0] * g->bx[1] * g->bx[2];
+    char *ix = (char *)b->index;
+    d.base = (const int32_t *)ix;
+    d.child = (const int32_t *)(ix + L.off_child);
+    d.leaf_info = (const int32_t *)(ix + L.off_info);
+    d.rec = b->grid;
+    c->bound = true;
+    c->loaded = false;
+    c->global_step = 0;
+    c->n_upper = 0;
+    c->injected_since = 0;
+    c->pending = false;
+    c->since_compact = 0;
+    c->err.clear();
+    return FTE_OK;
+}
+
+fte_status fte_load_grid(fte_ctx *c, const double *vb, void *stream) {
+    if (!c) return FTE_EINVAL;
+    if (!c->bound) return fail(c, FTE_ESTATE, "bind buffers before loading the grid");
+    if (!vb) return fail(c, FTE_EINVAL, "wind data is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const DevGrid &d = c->dg;
+    char *ix = (char *)c->b.index;
+    HIPCHK(c, hipMemcpyAsync(ix, c->base.data(), c->base.size() * 4, hipMemcpyHostToDevice, s));
+    if (!c->child.empty())
+        HIPCHK(c, hipMemcpyAsync((void *)d.child, c->child.data(), c->child.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync((void *)d.leaf_info, c->info.data(), c->info.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, launch_zero_counters(c->cnt, s));
+    if (c->hist_n) HIPCHK(c, launch_zero((double *)c->b.hist, c->hist_n, s));
+    HIPCHK(c, launch_check_raw(d, vb, c->cnt, s));
+    const int fp32 = c->p.precision == FTE_MIXED;
+    for (int k = 0; k < d.n_snap; ++k) {
+        HIPCHK(c, launch_raw_ghost(d, vb, k, c->cart, c->cnt, s));
+        HIPCHK(c, launch_derive(d, vb, k, c->cart, c->b.grid, fp32, s));
+        HIPCHK(c, launch_record_ghost(d, k, c->b.grid, fp32, c->cnt, s));
+    }
+    unsigned int flags = 0;
+    HIPCHK(c, hipMemcpyAsync(&flags, &c->cnt->flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    c->cur = 0;
+    c->n_upper = 0;
+    c->injected_since = 0;
+    c->pending = false;
+    c->global_step = 0;
+    c->since_compact = 0;
+    if (flags & kFlagBadInput) {
+        c->loaded = false;
+        return fail(c, FTE_EINVAL, "wind data hold non-finite values or |B| = 0");
+    }
+    if (flags & kFlagAmrDepth) {
+        c->loaded = false;
+        return fail(c, FTE_EINVAL, "block-boundary rule needed more than one coarser level");
+    }
+    HIPCHK(c, launch_zero_counters(c->cnt, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    c->loaded = true;
+    return FTE_OK;
+}
+
+static fte_status refresh_exact(fte_ctx *c, hipStream_t s) {
+    unsigned long long n = 0;
+    HIPCHK(c, hipMemcpyAsync(&n, &c->cnt->n_live[c->cur], sizeof(n), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    c->n_upper = n;
+    c->pending = false;
+    c->injected_since = 0;
+    return FTE_OK;
+}
+
+fte_status fte_inject(fte_ctx *c, const fte_injection *inj, uint64_t n, uint64_t first_pid, void *stream) {
+    if (!c) return FTE_EINVAL;
+    if (!c->loaded) return fail(c, FTE_ESTATE, "load the grid before injecting");
+    if (!inj) return fail(c, FTE_EINVAL, "injection is NULL");
+    if (!finite_pos(inj->r) || !finite_pos(inj->e_lo) || !(inj->e_hi >= inj->e_lo) || !isfinite(inj->e_hi) ||
+        !isfinite(inj->th_lo) || !isfinite(inj->th_hi) || !isfinite(inj->ph_lo) || !isfinite(inj->ph_hi) ||
+        !isfinite(inj->gamma_inj) || !isfinite(inj->w0) || inj->n_total < 1 ||
+        (inj->r_weight && !finite_pos(inj->r_ref)))
+        return fail(c, FTE_EINVAL, "bad injection description");
+    if (first_pid + n < first_pid || first_pid + n > (1ull << 60)) return fail(c, FTE_EINVAL, "pid out of range");
+    if (inj->n_inj_steps > 0 && (first_pid < inj->pid0 || first_pid + n > inj->pid0 + inj->n_total))
+        return fail(c, FTE_EINVAL, "pids outside the injection's range");
+    if (n == 0) return FTE_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (c->n_upper + n > c->n_max) {
+        fte_status r = refresh_exact(c, s);
+        if (r != FTE_OK) return r;
+        if (c->n_upper + n > c->n_max) return fail(c, FTE_ENOMEM, "particle capacity exceeded");
+    }
+    HIPCHK(c, launch_inject(c->dp, *inj, c->st[c->cur], c->cnt, c->cur, n, first_pid, s));
+    HIPCHK(c, launch_add_live(c->cnt, c->cur, n, s));
+    c->n_upper += n;
+    c->injected_since += n;
+    return FTE_OK;
+}
+
+fte_status fte_step_n(fte_ctx *c, uint32_t n_steps, void *stream) {
+    if (!c) return FTE_EINVAL;
+    if (!c->loaded) return fail(c, FTE_ESTATE, "load the grid before stepping");
+    if (n_steps == 0) return FTE_OK;
+    const uint64_t last = c->global_step + n_steps - 1;
+    if (last >= (1ull << 48)) return fail(c, FTE_ERANGE, "global step index exceeds 48 bits");
+    if (c->g.n_snap >= 2) {
+        const double t_last = c->p.t0 + (double)last * c->p.dt;
+        const double t_end = c->g.t_s0 + (c->g.n_snap - 1) * c->g.dt_s;
+        const double t_first = c->p.t0 + (double)c->global_step * c->p.dt;
+        if (t_last > t_end * (1 + 1e-15) + 1e-9 || t_first < c->g.t_s0 - 1e-9)
+            return fail(c, FTE_ERANGE, "steps leave the snapshot time range");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t left = n_steps;
+    while (left > 0) {
+        if (c->pending && hipEventQuery(c->ev) == hipSuccess) {
+            c->n_upper = *c->pinned + c->injected_since;
+            c->pending = false;
+        }
+        const uint32_t chunk = left < (uint32_t)c->spl ? left : (uint32_t)c->spl;
+        HIPCHK(c, launch_step(c->dp, c->dg, c->st[c->cur], c->cnt, c->cur, (double *)c->b.hist, c->global_step,
+                              chunk, c->n_upper, c->block, c->p.precision == FTE_MIXED, s));
+        c->global_step += chunk;
+        left -= chunk;
+        c->since_compact += chunk;
+        if (c->compact_every > 0 && c->since_compact >= (uint64_t)c->compact_every) {
+            const int to = 1 - c->cur;
+            HIPCHK(c, launch_zero_live(c->cnt, to, s));
+            HIPCHK(c, launch_compact(c->st[c->cur], c->st[to], c->cnt, c->cur, c->n_upper, 256, s));
+            c->cur = to;
+            c->since_compact = 0;
+            HIPCHK(c, hipMemcpyAsync(c->pinned, &c->cnt->n_live[to], sizeof(unsigned long long),
+                                     hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipEventRecord(c->ev, s));
+            c->pending = true;
+            c->injected_since = 0;
+        }
+    }
+    return FTE_OK;
+}
+
+fte_status fte_bin_observers(fte_ctx *c, double *j, double *sigma, int reset, void *stream) {
+    if (!c) return FTE_EINVAL;
+    if (!c->loaded) return fail(c, FTE_ESTATE, "nothing to bin before the grid is loaded");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = (size_t)c->p.n_obs * c->p.n_e * c->p.n_t;
+    if (nb > 0) {
+        HIPCHK(c, launch_finalize(c->dp, (const double *)c->b.hist, c->cnt, c->fin_j, c->fin_s, s));
+        if (j) HIPCHK(c, hipMemcpyAsync(j, c->fin_j, nb * 8, hipMemcpyDeviceToHost, s));
+        if (sigma) HIPCHK(c, hipMemcpyAsync(sigma, c->fin_s, nb * 8, hipMemcpyDeviceToHost, s));
+        if (reset) HIPCHK(c, launch_zero((double *)c->b.hist, c->hist_n, s));
+    }
+    HIPCHK(c, hipStreamSynchronize(s));
+    return FTE_OK;
+}
+
+fte_status fte_read_hist(fte_ctx *c, double *sums, double *w_injected, void *stream) {
+    if (!c) return FTE_EINVAL;
+    if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
+    hipStream_t s = (hipStream_t)stream;
+    if (sums && c->hist_n) HIPCHK(c, hipMemcpyAsync(sums, c->b.hist, c->hist_n * 8, hipMemcpyDeviceToHost, s));
+    double w[FTE_MAX_BATCH];
+    HIPCHK(c, hipMemcpyAsync(w, c->cnt->w_inj, sizeof(w), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (w_injected) {
+        double t = 0.0;
+        for (int b = 0; b < c->p.n_batch; ++b) t += w[b];
+        *w_injected = t;
+    }
+    return FTE_OK;
+}
+
+fte_status fte_get_stats(fte_ctx *c, fte_stats *out, void *stream) {
+    if (!c || !out) return FTE_EINVAL;
+    if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
+    hipStream_t s = (hipStream_t)stream;
+    DevCounters h;
+    HIPCHK(c, hipMemcpyAsync(&h, c->cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    memset(out, 0, sizeof(*out));
+    out->n_live = h.n_live[c->cur];
+    out->n_injected = h.injected;
+    out->particle_steps = h.steps;
+    double wi = 0.0;
+    for (int b = 0; b < c->p.n_batch; ++b) wi += h.w_inj[b];
+    out->w_injected = wi;
+    for (int k = 0; k < 5; ++k) {
+        out->n_retired[k] = h.retired[k];
+        out->w_retired[k] = h.w_retired[k];
+    }
+    out->global_step = c->global_step;
+    out->device_flags = h.flags;
+    return FTE_OK;
+}
+
+fte_status fte_read_particles(fte_ctx *c, double *x3, double *mu, double *lnp, double *w, uint64_t *pid,
+                              uint32_t *kinj, int32_t *status, uint64_t cap, uint64_t *n_out, void *stream) {
+    if (!c) return FTE_EINVAL;
+    if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long n = 0;
+    HIPCHK(c, hipMemcpyAsync(&n, &c->cnt->n_live[c->cur], sizeof(n), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (n_out) *n_out = n;
+    if (n > cap) return fail(c, FTE_ENOMEM, "host arrays too small");
+    const DevState &d = c->st[c->cur];
+    if (x3) {
+        std::vector<double> tx(n), ty(n), tz(n);
+        HIPCHK(c, hipMemcpyAsync(tx.data(), d.x, n * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(ty.data(), d.y, n * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(tz.data(), d.z, n * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        for (size_t i = 0; i < n; ++i) {
+            x3[3 * i] = tx[i];
+            x3[3 * i + 1] = ty[i];
+            x3[3 * i + 2] = tz[i];
+        }
+    }
+    if (mu) HIPCHK(c, hipMemcpyAsync(mu, d.mu, n * 8, hipMemcpyDeviceToHost, s));
+    if (lnp) HIPCHK(c, hipMemcpyAsync(lnp, d.lnp, n * 8, hipMemcpyDeviceToHost, s));
+    if (w) HIPCHK(c, hipMemcpyAsync(w, d.w, n * 8, hipMemcpyDeviceToHost, s));
+    if (pid) HIPCHK(c, hipMemcpyAsync(pid, d.pid, n * 8, hipMemcpyDeviceToHost, s));
+    if (kinj) HIPCHK(c, hipMemcpyAsync(kinj, d.kinj, n * 4, hipMemcpyDeviceToHost, s));
+    if (status) HIPCHK(c, hipMemcpyAsync(status, d.status, n * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return FTE_OK;
+}
+
+fte_status fte_set_launch(fte_ctx *c, int block, int steps_per_launch, int compact_every) {
+    if (!c) return FTE_EINVAL;
+    if (block < 64 || block > 256 || (block & 63)) return fail(c, FTE_EINVAL, "block must be 64..256, multiple of 64");
+    if (steps_per_launch < 1) return fail(c, FTE_EINVAL, "steps_per_launch must be >= 1");
+    if (compact_every < 0 || (compact_every && compact_every % steps_per_launch))
+        return fail(c, FTE_EINVAL, "compact_every must be a multiple of steps_per_launch");
+    c->block = block;
+    c->spl = steps_per_launch;
+    c->compact_every = compact_every;
+    return FTE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Internal types shared by the host side of the library and its kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fte.h"
+
+namespace fte {
+
+constexpr double kC = 299792458.0;
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kRS = FTE_RECORD_STRIDE;
+constexpr int kNF = FTE_RECORD_FIELDS;
+
+// Device-side copy of the run parameters, pre-digested on the host.
+struct DevParams {
+    double mass_c2;          // m c^2, J
+    double dt, t0, r_in, r_out;
+    double lambda_ref, inv_p_ref, alpha;
+    double q, eps, mu_floor;
+    double dmm_scale;        // A = dmm_scale * v / lambda_par
+    double kperp_ratio, lambda_perp;
+    double e_min_ln, inv_dlne;   // ln(e_min), 1 / dlne
+    double e_min, dlne, dT;
+    double t_ref, inv_dT;
+    double obs[FTE_MAX_OBS][6];  // r1, r2, th1, th2, phi centre, half width phi
+    uint64_t seed;
+    int dmm_model;
+    int run_id;
+    int n_obs, n_e, n_t, n_batch;
+};
+
+// Block-AMR grid as the kernels see it.
+struct DevGrid {
+    double r_lo, inv_dxi, th_lo, inv_dth, ph_lo, inv_dph;
+    double dxi, dth, dph;        // level-1 widths
+    double th_hi;                // upper colatitude edge
+    double t_s0, inv_dt_s, dt_s;
+    int xi_map, periodic;
+    int n1[3], bx[3], px[3];     // level-1 cells, block cells, padded block cells
+    int nb1[3];                  // level-1 blocks per dimension
+    int n_levels, n_leaves, n_snap, n_base, n_child;
+    int pcells;                  // padded cells per block
+    int cells;                   // interior cells per block
+    const int32_t *base;         // [nb1 product] node codes (>=0 leaf, <0 -(group+1))
+    const int32_t *child;        // [n_groups][8] node codes
+    const int32_t *leaf_info;    // [n_leaves][4] level, I, J, K
+    const void *rec;             // records [snap][leaf][pcell][kRS]
+};
+
+// Particle state (struct of arrays, capacity n_max).
+struct DevState {
+    double *x, *y, *z, *mu, *lnp, *w;
+    uint64_t *pid;
+    uint32_t *kinj;
+    int32_t *status;
+};
+
+// Device counters (live in the work buffer).
+struct DevCounters {
+    unsigned long long n_live[2];
+    unsigned long long steps;
+    unsigned long long injected;
+    unsigned long long retired[5];
+    double w_retired[5];
+    unsigned int flags;
+    unsigned int pad;
+    double w_inj[FTE_MAX_BATCH];
+};
+
+enum : unsigned int { kFlagAmrDepth = 1u, kFlagBadInput = 2u, kFlagNoLeaf = 4u };
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+DevState state_view(void *base, uint64_t n_max);
+size_t state_bytes(uint64_t n_max);
+
+// Kernel launchers (fte_kernels.hip).
+hipError_t launch_raw_ghost(const DevGrid &g, const double *raw, int snap, double *work_cart, DevCounters *cnt,
+                            hipStream_t s);
+hipError_t launch_derive(const DevGrid &g, const double *raw, int snap, const double *work_cart, void *rec,
+                         int fp32, hipStream_t s);
+hipError_t launch_record_ghost(const DevGrid &g, int snap, void *rec, int fp32, DevCounters *cnt, hipStream_t s);
+hipError_t launch_check_raw(const DevGrid &g, const double *raw, DevCounters *cnt, hipStream_t s);
+hipError_t launch_inject(const DevParams &p, const fte_injection &inj, DevState st, DevCounters *cnt, int slot,
+                         uint64_t n, uint64_t first_pid, hipStream_t s);
+hipError_t launch_add_live(DevCounters *cnt, int slot, uint64_t n, hipStream_t s);
+hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevCounters *cnt, int slot, double *hist,
+                       uint64_t n0, uint32_t n_steps, uint64_t n_upper, int block, int fp32, hipStream_t s);
+hipError_t launch_compact(DevState src, DevState dst, DevCounters *cnt, int from, uint64_t n_upper, int block,
+                          hipStream_t s);
+hipError_t launch_zero_live(DevCounters *cnt, int slot, hipStream_t s);
+hipError_t launch_finalize(const DevParams &p, const double *hist, const DevCounters *cnt, double *j, double *sig,
+                           hipStream_t s);
+hipError_t launch_zero(double *p, uint64_t n, hipStream_t s);
+hipError_t launch_zero_counters(DevCounters *cnt, hipStream_t s);
+
+}  // namespace fte

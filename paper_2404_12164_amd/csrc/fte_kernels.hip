@@ -1,0 +1,856 @@
+// HIP kernels of the focused-transport pseudo-particle path (gfx950).
+//
+// Load time (once per snapshot): ghost-fill of the raw wind, derived fields,
+// ghost-fill of the records.  Run time: injection, the fused step kernel
+// (locate -> gather -> coefficients -> noise -> update -> boundaries ->
+// observers, many steps per launch with the state in registers), compaction of
+// retired particles, and the observer finalisation.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "fte_device.hpp"
+#include "fte_internal.hpp"
+
+namespace fte {
+
+// ===========================================================================
+// load time
+// ===========================================================================
+// raw input: [snap][leaf][cell][6] double, cell = i + bx (j + by k)
+struct RawSrc {
+    const double *p;
+    const int32_t *leaf_info;
+    int snap, n_leaves, cells, bx0, bx1, bx2;
+    __device__ void mean_cube(int leaf, const int cm[3], int k, double out[6]) const {
+        const int4 li = reinterpret_cast<const int4 *>(leaf_info)[leaf];
+        const int l0 = cm[0] - li.y * bx0, l1 = cm[1] - li.z * bx1, l2 = cm[2] - li.w * bx2;
+        for (int q = 0; q < 6; ++q) out[q] = 0.0;
+        if (l0 < 0 || l1 < 0 || l2 < 0 || l0 + k > bx0 || l1 + k > bx1 || l2 + k > bx2) {
+            for (int q = 0; q < 6; ++q) out[q] = __builtin_nan("");
+            return;
+        }
+        for (int c2 = 0; c2 < k; ++c2)
+            for (int c1 = 0; c1 < k; ++c1)
+                for (int c0 = 0; c0 < k; ++c0) {
+                    const size_t idx = (l0 + c0) + (size_t)bx0 * ((l1 + c1) + (size_t)bx1 * (l2 + c2));
+                    const double *src = p + (((size_t)snap * n_leaves + leaf) * cells + idx) * 6;
+                    for (int q = 0; q < 6; ++q) out[q] += src[q];
+                }
+        const double inv = 1.0 / (double)(k * k * k);
+        for (int q = 0; q < 6; ++q) out[q] *= inv;
+    }
+};
+
+// records: [snap][leaf][pcell][kRS] of R, interior at padded offset +1
+template <typename R>
+struct RecSrc {
+    const R *p;
+    const int32_t *leaf_info;
+    int snap, n_leaves, pcells, px0, px1, bx0, bx1, bx2;
+    __device__ void mean_cube(int leaf, const int cm[3], int k, double out[kNF]) const {
+        const int4 li = reinterpret_cast<const int4 *>(leaf_info)[leaf];
+        const int l0 = cm[0] - li.y * bx0, l1 = cm[1] - li.z * bx1, l2 = cm[2] - li.w * bx2;
+        for (int q = 0; q < kNF; ++q) out[q] = 0.0;
+        if (l0 < 0 || l1 < 0 || l2 < 0 || l0 + k > bx0 || l1 + k > bx1 || l2 + k > bx2) {
+            for (int q = 0; q < kNF; ++q) out[q] = __builtin_nan("");
+            return;
+        }
+        for (int c2 = 0; c2 < k; ++c2)
+            for (int c1 = 0; c1 < k; ++c1)
+                for (int c0 = 0; c0 < k; ++c0) {
+                    const size_t pc = (l0 + c0 + 1) + (size_t)px0 * ((l1 + c1 + 1) + (size_t)px1 * (l2 + c2 + 1));
+                    const R *src = p + (((size_t)snap * n_leaves + leaf) * pcells + pc) * kRS;
+                    for (int q = 0; q < kNF; ++q) out[q] += (double)src[q];
+                }
+        const double inv = 1.0 / (double)(k * k * k);
+        for (int q = 0; q < kNF; ++q) out[q] *= inv;
+    }
+};
+
+__device__ __forceinline__ void basis(double th, double ph, double e[3][3]) {
+    double st, ct, sp, cp;
+    ::sincos(th, &st, &ct);
+    ::sincos(ph, &sp, &cp);
+    e[0][0] = st * cp; e[0][1] = st * sp; e[0][2] = ct;
+    e[1][0] = ct * cp; e[1][1] = ct * sp; e[1][2] = -st;
+    e[2][0] = -sp;     e[2][1] = cp;      e[2][2] = 0.0;
+}
+
+__device__ __forceinline__ void centre(const DevGrid &G, int L, const int c[3], double *r, double *th, double *ph) {
+    const double h = ::ldexp(1.0, 1 - L);
+    const double xi = ((double)c[0] + 0.5) * G.dxi * h;
+    *r = G.xi_map ? G.r_lo * ::exp(xi) : G.r_lo + xi;
+    *th = G.th_lo + ((double)c[1] + 0.5) * G.dth * h;
+    *ph = G.ph_lo + ((double)c[2] + 0.5) * G.dph * h;
+}
+
+// decode (leaf, padded cell) -> level, global level-L index, local index
+__device__ __forceinline__ void decode_pcell(const DevGrid &G, int leaf, int pc, int *L, int c[3], int loc[3]) {
+    const int4 li = reinterpret_cast<const int4 *>(G.leaf_info)[leaf];
+    loc[0] = pc % G.px[0] - 1;
+    loc[1] = (pc / G.px[0]) % G.px[1] - 1;
+    loc[2] = pc / (G.px[0] * G.px[1]) - 1;
+    *L = li.x;
+    c[0] = li.y * G.bx[0] + loc[0];
+    c[1] = li.z * G.bx[1] + loc[1];
+    c[2] = li.w * G.bx[2] + loc[2];
+}
+
+// Flag non-finite values or a vanishing |B| in the raw input.
+__global__ void k_check_raw(const double *raw, size_t n_cells, DevCounters *cnt) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_cells) return;
+    const double *v = raw + i * 6;
+    bool bad = false;
+    for (int q = 0; q < 6; ++q) bad |= !isfinite(v[q]);
+    bad |= !(v[3] * v[3] + v[4] * v[4] + v[5] * v[5] > 0.0);
+    if (bad) atomicOr(&cnt->flags, kFlagBadInput);
+}
+
+// Padded Cartesian (V, b) of one snapshot: interior cells from the input,
+// ghost cells by the block-boundary rule, then rotated with the angles of the
+// (folded) cell centre.
+__global__ void k_raw_ghost(DevGrid G, const double *raw, int snap, double *cart, DevCounters *cnt) {
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (size_t)G.n_leaves * G.pcells) return;
+    const int leaf = (int)(gid / G.pcells), pc = (int)(gid % G.pcells);
+    int L, c[3], loc[3];
+    decode_pcell(G, leaf, pc, &L, c, loc);
+    double v[6];
+    const bool interior = loc[0] >= 0 && loc[0] < G.bx[0] && loc[1] >= 0 && loc[1] < G.bx[1] && loc[2] >= 0 &&
+                          loc[2] < G.bx[2];
+    if (interior) {
+        const size_t idx = loc[0] + (size_t)G.bx[0] * (loc[1] + (size_t)G.bx[1] * loc[2]);
+        const double *src = raw + (((size_t)snap * G.n_leaves + leaf) * G.cells + idx) * 6;
+        for (int q = 0; q < 6; ++q) v[q] = src[q];
+    } else {
+        RawSrc S{raw, G.leaf_info, snap, G.n_leaves, G.cells, G.bx[0], G.bx[1], G.bx[2]};
+        if (!virtual_value<6>(G, S, L, c, v)) {
+            atomicOr(&cnt->flags, kFlagAmrDepth);
+            for (int q = 0; q < 6; ++q) v[q] = __builtin_nan("");
+        }
+    }
+    fold(G, L, c);
+    double r, th, ph, e[3][3];
+    centre(G, L, c, &r, &th, &ph);
+    basis(th, ph, e);
+    const double Bn = ::sqrt(v[3] * v[3] + v[4] * v[4] + v[5] * v[5]);
+    const double bs[3] = {v[3] / Bn, v[4] / Bn, v[5] / Bn};
+    double *dst = cart + ((size_t)leaf * G.pcells + pc) * 6;
+    for (int a = 0; a < 3; ++a) {
+        dst[a] = v[0] * e[0][a] + v[1] * e[1][a] + v[2] * e[2][a];
+        dst[3 + a] = bs[0] * e[0][a] + bs[1] * e[1][a] + bs[2] * e[2][a];
+    }
+}
+
+// Cartesian V of an interior cell taken straight from the input of snapshot k.
+__device__ __forceinline__ void cart_v_input(const DevGrid &G, const double *raw, int k, int leaf, size_t idx,
+                                             const double e[3][3], double V[3]) {
+    const double *s = raw + (((size_t)k * G.n_leaves + leaf) * G.cells + idx) * 6;
+    for (int a = 0; a < 3; ++a) V[a] = s[0] * e[0][a] + s[1] * e[1][a] + s[2] * e[2][a];
+}
+
+// Derived fields of every interior cell of one snapshot (the quantities of
+// Eqs. 2-4): second-order central differences of the Cartesian (V, b) in the
+// uniform (xi, theta, phi) spacing (one-sided at physical edges), chain rule
+// with the analytic Jacobian at the centre, explicit dV/dt across snapshots.
+template <typename R>
+__global__ void k_derive(DevGrid G, const double *raw, int snap, const double *cart, R *rec) {
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (size_t)G.n_leaves * G.cells) return;
+    const int leaf = (int)(gid / G.cells);
+    const int idx = (int)(gid % G.cells);
+    const int loc[3] = {idx % G.bx[0], (idx / G.bx[0]) % G.bx[1], idx / (G.bx[0] * G.bx[1])};
+    const int4 li = reinterpret_cast<const int4 *>(G.leaf_info)[leaf];
+    const int L = li.x;
+    const int c[3] = {li.y * G.bx[0] + loc[0], li.z * G.bx[1] + loc[1], li.w * G.bx[2] + loc[2]};
+    const int pc = (loc[0] + 1) + G.px[0] * ((loc[1] + 1) + G.px[1] * (loc[2] + 1));
+    const int stride[3] = {1, G.px[0], G.px[0] * G.px[1]};
+    const double *U = cart + (size_t)leaf * G.pcells * 6;
+    const double hL = ::ldexp(1.0, 1 - L);
+    const double h[3] = {G.dxi * hL, G.dth * hL, G.dph * hL};
+
+    double dq[3][6];
+    for (int a = 0; a < 3; ++a) {
+        const int n = ncell(G, L, a);
+        const bool periodic = (a == 2) && G.periodic;
+        const double *u0 = U + (size_t)pc * 6;
+        if (!periodic && c[a] == 0) {
+            const double *u1 = U + (size_t)(pc + stride[a]) * 6, *u2 = U + (size_t)(pc + 2 * stride[a]) * 6;
+            for (int q = 0; q < 6; ++q) dq[a][q] = (-3.0 * u0[q] + 4.0 * u1[q] - u2[q]) / (2.0 * h[a]);
+        } else if (!periodic && c[a] == n - 1) {
+            const double *u1 = U + (size_t)(pc - stride[a]) * 6, *u2 = U + (size_t)(pc - 2 * stride[a]) * 6;
+            for (int q = 0; q < 6; ++q) dq[a][q] = (3.0 * u0[q] - 4.0 * u1[q] + u2[q]) / (2.0 * h[a]);
+        } else {
+            const double *up = U + (size_t)(pc + stride[a]) * 6, *um = U + (size_t)(pc - stride[a]) * 6;
+            for (int q = 0; q < 6; ++q) dq[a][q] = (up[q] - um[q]) / (2.0 * h[a]);
+        }
+    }
+    double r, th, ph, e[3][3];
+    centre(G, L, c, &r, &th, &ph);
+    basis(th, ph, e);
+    const double xip = G.xi_map ? 1.0 / r : 1.0;
+    const double st = ::sin(th);
+    double gq[3][3];
+    for (int d = 0; d < 3; ++d) {
+        gq[0][d] = xip * e[0][d];
+        gq[1][d] = e[1][d] / r;
+        gq[2][d] = e[2][d] / (r * st);
+    }
+    double GV[3][3], Gb[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int d = 0; d < 3; ++d) {
+            GV[a][d] = dq[0][a] * gq[0][d] + dq[1][a] * gq[1][d] + dq[2][a] * gq[2][d];
+            Gb[a][d] = dq[0][3 + a] * gq[0][d] + dq[1][3 + a] * gq[1][d] + dq[2][3 + a] * gq[2][d];
+        }
+    const double *u = U + (size_t)pc * 6;
+    const double V[3] = {u[0], u[1], u[2]}, b[3] = {u[3], u[4], u[5]};
+    const double divV = GV[0][0] + GV[1][1] + GV[2][2];
+    const double divb = Gb[0][0] + Gb[1][1] + Gb[2][2];
+    double bbgV = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int d = 0; d < 3; ++d) bbgV += b[a] * b[d] * GV[a][d];
+
+    double dVdt[3] = {0.0, 0.0, 0.0};
+    const int ns = G.n_snap;
+    if (ns == 2) {
+        double V0[3], V1[3];
+        cart_v_input(G, raw, 0, leaf, idx, e, V0);
+        cart_v_input(G, raw, 1, leaf, idx, e, V1);
+        for (int a = 0; a < 3; ++a) dVdt[a] = (V1[a] - V0[a]) / G.dt_s;
+    } else if (ns >= 3) {
+        double Va[3], Vb[3], Vc[3];
+        if (snap == 0) {
+            cart_v_input(G, raw, 0, leaf, idx, e, Va);
+            cart_v_input(G, raw, 1, leaf, idx, e, Vb);
+            cart_v_input(G, raw, 2, leaf, idx, e, Vc);
+            for (int a = 0; a < 3; ++a) dVdt[a] = (-3.0 * Va[a] + 4.0 * Vb[a] - Vc[a]) / (2.0 * G.dt_s);
+        } else if (snap == ns - 1) {
+            cart_v_input(G, raw, ns - 1, leaf, idx, e, Va);
+            cart_v_input(G, raw, ns - 2, leaf, idx, e, Vb);
+            cart_v_input(G, raw, ns - 3, leaf, idx, e, Vc);
+            for (int a = 0; a < 3; ++a) dVdt[a] = (3.0 * Va[a] - 4.0 * Vb[a] + Vc[a]) / (2.0 * G.dt_s);
+        } else {
+            cart_v_input(G, raw, snap + 1, leaf, idx, e, Vb);
+            cart_v_input(G, raw, snap - 1, leaf, idx, e, Vc);
+            for (int a = 0; a < 3; ++a) dVdt[a] = (Vb[a] - Vc[a]) / (2.0 * G.dt_s);
+        }
+    }
+    double bDV = 0.0;
+    for (int a = 0; a < 3; ++a) bDV += b[a] * (dVdt[a] + GV[a][0] * V[0] + GV[a][1] * V[1] + GV[a][2] * V[2]);
+    double curv[3];
+    for (int a = 0; a < 3; ++a) curv[a] = Gb[a][0] * b[0] + Gb[a][1] * b[1] + Gb[a][2] * b[2];
+
+    const double *s = raw + (((size_t)snap * G.n_leaves + leaf) * G.cells + idx) * 6;
+    const double Bn = ::sqrt(s[3] * s[3] + s[4] * s[4] + s[5] * s[5]);
+    R *out = rec + (((size_t)snap * G.n_leaves + leaf) * G.pcells + pc) * kRS;
+    out[0] = (R)s[0];
+    out[1] = (R)s[1];
+    out[2] = (R)s[2];
+    out[3] = (R)(s[3] / Bn);
+    out[4] = (R)(s[4] / Bn);
+    out[5] = (R)(s[5] / Bn);
+    out[6] = (R)divV;
+    out[7] = (R)bbgV;
+    out[8] = (R)divb;
+    out[9] = (R)bDV;
+    for (int a = 0; a < 3; ++a) out[10 + a] = (R)(curv[0] * e[a][0] + curv[1] * e[a][1] + curv[2] * e[a][2]);
+    for (int q = kNF; q < kRS; ++q) out[q] = (R)0;
+}
+
+// Ghost layer of the records by the block-boundary rule.
+template <typename R>
+__global__ void k_record_ghost(DevGrid G, int snap, R *rec, DevCounters *cnt) {
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (size_t)G.n_leaves * G.pcells) return;
+    const int leaf = (int)(gid / G.pcells), pc = (int)(gid % G.pcells);
+    int L, c[3], loc[3];
+    decode_pcell(G, leaf, pc, &L, c, loc);
+    const bool interior = loc[0] >= 0 && loc[0] < G.bx[0] && loc[1] >= 0 && loc[1] < G.bx[1] && loc[2] >= 0 &&
+                          loc[2] < G.bx[2];
+    if (interior) return;
+    RecSrc<R> S{rec, G.leaf_info, snap, G.n_leaves, G.pcells, G.px[0], G.px[1], G.bx[0], G.bx[1], G.bx[2]};
+    double v[kNF];
+    R *out = rec + (((size_t)snap * G.n_leaves + leaf) * G.pcells + pc) * kRS;
+    if (!virtual_value<kNF>(G, S, L, c, v)) {
+        atomicOr(&cnt->flags, kFlagAmrDepth);
+        for (int q = 0; q < kNF; ++q) v[q] = __builtin_nan("");
+    }
+    for (int q = 0; q < kNF; ++q) out[q] = (R)v[q];
+    for (int q = kNF; q < kRS; ++q) out[q] = (R)0;
+}
+
+static inline unsigned blocks_for(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_check_raw(const DevGrid &g, const double *raw, DevCounters *cnt, hipStream_t s) {
+    const size_t n = (size_t)g.n_snap * g.n_leaves * g.cells;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_raw, dim3(blocks_for(n, 256)), dim3(256), 0, s, raw, n, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_raw_ghost(const DevGrid &g, const double *raw, int snap, double *work_cart, DevCounters *cnt,
+                            hipStream_t s) {
+    const size_t n = (size_t)g.n_leaves * g.pcells;
+    hipLaunchKernelGGL(k_raw_ghost, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, raw, snap, work_cart, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_derive(const DevGrid &g, const double *raw, int snap, const double *work_cart, void *rec, int fp32,
+                         hipStream_t s) {
+    const size_t n = (size_t)g.n_leaves * g.cells;
+    if (fp32)
+        hipLaunchKernelGGL(k_derive<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, raw, snap, work_cart,
+                           (float *)rec);
+    else
+        hipLaunchKernelGGL(k_derive<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, raw, snap, work_cart,
+                           (double *)rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_record_ghost(const DevGrid &g, int snap, void *rec, int fp32, DevCounters *cnt, hipStream_t s) {
+    const size_t n = (size_t)g.n_leaves * g.pcells;
+    if (fp32)
+        hipLaunchKernelGGL(k_record_ghost<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, snap, (float *)rec,
+                           cnt);
+    else
+        hipLaunchKernelGGL(k_record_ghost<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, snap,
+                           (double *)rec, cnt);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// injection
+// ===========================================================================
+__global__ void k_inject(DevParams P, fte_injection inj, DevState st, DevCounters *cnt, int slot, uint64_t n,
+                         uint64_t first_pid) {
+    __shared__ double wsum[FTE_MAX_BATCH];
+    for (int b = threadIdx.x; b < FTE_MAX_BATCH; b += blockDim.x) wsum[b] = 0.0;
+    __syncthreads();
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const uint64_t base = cnt->n_live[slot];
+        const uint64_t pid = first_pid + i;
+        const U4 ka = philox_words(P.seed, P.run_id, 0, pid, 1u);
+        const U4 kb = philox_words(P.seed, P.run_id, 1, pid, 1u);
+        const double u0 = M<double>::u01(ka.a), u1 = M<double>::u01(ka.b);
+        const double u2 = M<double>::u01(ka.c), u3 = M<double>::u01(ka.d);
+        const double mu = 2.0 * u0 - 1.0;
+        const double c1 = ::cos(inj.th_lo), c2 = ::cos(inj.th_hi);
+        const double ct = c1 + u1 * (c2 - c1);
+        const double th = ::acos(ct);
+        const double ph = inj.ph_lo + u2 * (inj.ph_hi - inj.ph_lo);
+        double E, wt = inj.w0;
+        if (inj.e_hi > inj.e_lo) {
+            E = ::exp(::log(inj.e_lo) + u3 * (::log(inj.e_hi) - ::log(inj.e_lo)));
+            wt *= ::pow(E / inj.e_lo, 1.0 - inj.gamma_inj);
+        } else {
+            E = inj.e_lo;
+        }
+        if (inj.r_weight) wt *= (inj.r_ref / inj.r) * (inj.r_ref / inj.r);
+        const double eps = E / P.mass_c2;
+        const uint64_t j = base + i;
+        st.x[j] = inj.r * ::sin(th) * ::cos(ph);
+        st.y[j] = inj.r * ::sin(th) * ::sin(ph);
+        st.z[j] = inj.r * ct;
+        st.mu[j] = mu;
+        st.lnp[j] = ::log(::sqrt(eps * (eps + 2.0)));
+        st.w[j] = wt;
+        st.pid[j] = pid;
+        uint32_t k = inj.k0;
+        if (inj.n_inj_steps > 0) {
+            const double jj = (double)(pid - inj.pid0);
+            k = inj.k0 + (uint32_t)::floor((jj + M<double>::u01(kb.a)) * (double)inj.n_inj_steps /
+                                           (double)inj.n_total);
+        }
+        st.kinj[j] = k;
+        st.status[j] = FTE_PS_ACTIVE;
+        atomicAdd(&wsum[pid % (uint64_t)P.n_batch], wt);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < P.n_batch; b += blockDim.x)
+        if (wsum[b] != 0.0) atomicAdd(&cnt->w_inj[b], wsum[b]);
+}
+
+__global__ void k_add_live(DevCounters *cnt, int slot, uint64_t n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        cnt->n_live[slot] += n;
+        cnt->injected += n;
+    }
+}
+
+hipError_t launch_inject(const DevParams &p, const fte_injection &inj, DevState st, DevCounters *cnt, int slot,
+                         uint64_t n, uint64_t first_pid, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_inject, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, inj, st, cnt, slot, n, first_pid);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_live(DevCounters *cnt, int slot, uint64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_add_live, dim3(1), dim3(64), 0, s, cnt, slot, n);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// the step kernel
+// ===========================================================================
+template <typename R>
+struct Fields {
+    R V[3], b[3], divV, bbgV, divb, bDV, curv[3];
+};
+
+// Level-1 grid coordinates of a position already reduced to (r, theta, phi),
+// folded into the domain.
+template <typename R>
+__device__ __forceinline__ void grid_coords(const DevGrid &G, double r, R th, R ph, R s[3]);
+
+template <>
+__device__ __forceinline__ void grid_coords<double>(const DevGrid &G, double r, double th, double ph, double s[3]) {
+    s[0] = G.xi_map ? ::log(r / G.r_lo) * G.inv_dxi : (r - G.r_lo) * G.inv_dxi;
+    s[1] = (th - G.th_lo) * G.inv_dth;
+    s[2] = (ph - G.ph_lo) * G.inv_dph;
+}
+
+template <>
+__device__ __forceinline__ void grid_coords<float>(const DevGrid &G, double r, float th, float ph, float s[3]) {
+    s[0] = G.xi_map ? __logf((float)(r / G.r_lo)) * (float)G.inv_dxi : (float)((r - G.r_lo) * G.inv_dxi);
+    s[1] = (th - (float)G.th_lo) * (float)G.inv_dth;
+    s[2] = (ph - (float)G.ph_lo) * (float)G.inv_dph;
+}
+
+// Locate the leaf holding level-1 coordinates s and gather + interpolate the
+// records (trilinear in space, linear in time between snapshots k and k+1).
+template <typename R, bool KPERP>
+__device__ __forceinline__ bool gather(const DevGrid &G, R s[3], int ks, R alpha, R acc[kNF]) {
+    constexpr int NF = KPERP ? 13 : 10;
+    // fold into the domain
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const R n = (R)G.n1[a];
+        s[a] = (s[a] >= (R)0) ? (s[a] > n ? n : s[a]) : (R)0;   // NaN -> 0
+    }
+    {
+        const R n = (R)G.n1[2];
+        if (G.periodic) {
+            if (s[2] >= n) s[2] -= n;
+            if (s[2] < (R)0) s[2] += n;
+            if (!(s[2] >= (R)0 && s[2] < n)) s[2] = (R)0;
+        } else {
+            s[2] = (s[2] >= (R)0) ? (s[2] > n ? n : s[2]) : (R)0;
+        }
+    }
+    // descend the block index
+    int B[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int c = (int)M<R>::floor_(s[a]);
+        c = c > G.n1[a] - 1 ? G.n1[a] - 1 : c;
+        B[a] = c / G.bx[a];
+    }
+    int node = G.base[B[0] + G.nb1[0] * (B[1] + G.nb1[1] * B[2])];
+    int L = 1;
+    R S[3] = {s[0], s[1], s[2]};
+    while (node < 0) {
+        const int grp = -node - 1;
+        ++L;
+        int slot = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            S[a] = S[a] * (R)2;
+            int c = (int)M<R>::floor_(S[a]);
+            const int n = G.n1[a] << (L - 1);
+            c = c > n - 1 ? n - 1 : c;
+            B[a] = c / G.bx[a];
+            slot |= (B[a] & 1) << a;
+        }
+        node = G.child[grp * 8 + slot];
+        if (L >= G.n_levels && node < 0) return false;
+    }
+    const int leaf = node;
+    // local cell relative to the first centre of the block, padded index
+    int i[3];
+    R f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const R u = S[a] - (R)(B[a] * G.bx[a]) - (R)0.5;
+        const R fl = M<R>::floor_(u);
+        i[a] = (int)fl;
+        f[a] = u - fl;
+    }
+    const size_t pc = (size_t)(i[0] + 1) + (size_t)G.px[0] * ((i[1] + 1) + (size_t)G.px[1] * (i[2] + 1));
+    const size_t sx = 1, sy = G.px[0], sz = (size_t)G.px[0] * G.px[1];
+    const R *rec = reinterpret_cast<const R *>(G.rec);
+#pragma unroll
+    for (int q = 0; q < NF; ++q) acc[q] = (R)0;
+    const int nsn = G.n_snap >= 2 ? 2 : 1;
+    for (int sn = 0; sn < nsn; ++sn) {
+        const R ws = (G.n_snap >= 2) ? (sn == 0 ? (R)1 - alpha : alpha) : (R)1;
+        const R *base = rec + (((size_t)(ks + sn) * G.n_leaves + leaf) * G.pcells + pc) * kRS;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const int e0 = d & 1, e1 = (d >> 1) & 1, e2 = (d >> 2) & 1;
+            const R w = ws * (e0 ? f[0] : (R)1 - f[0]) * (e1 ? f[1] : (R)1 - f[1]) * (e2 ? f[2] : (R)1 - f[2]);
+            const R *p = base + (e0 * sx + e1 * sy + e2 * sz) * kRS;
+#pragma unroll
+            for (int q = 0; q < NF; ++q) acc[q] += w * p[q];
+        }
+    }
+    return true;
+}
+
+template <typename R>
+__device__ __forceinline__ R sgn(R x) {
+    return (R)((x > (R)0) - (x < (R)0));
+}
+
+// Rotate spherical components with the basis at the particle.
+template <typename R>
+__device__ __forceinline__ void to_cart(R st, R ct, R sp, R cp, const R s[3], R out[3]) {
+    out[0] = s[0] * st * cp + s[1] * ct * cp - s[2] * sp;
+    out[1] = s[0] * st * sp + s[1] * ct * sp + s[2] * cp;
+    out[2] = s[0] * ct - s[1] * st;
+}
+
+template <typename R, bool KPERP>
+__global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState st, DevCounters *cnt, int slot,
+                                              double *hist, uint64_t n0, uint32_t n_steps) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t n_live = cnt->n_live[slot];
+    unsigned long long my_steps = 0;
+    if (i < n_live && st.status[i] == FTE_PS_ACTIVE) {
+        double x = st.x[i], y = st.y[i], z = st.z[i];
+        R mu = (R)st.mu[i], lnp = (R)st.lnp[i];
+        const double w = st.w[i];
+        const uint64_t pid = st.pid[i];
+        const uint32_t kinj = st.kinj[i];
+        int status = FTE_PS_ACTIVE;
+        const R dt = (R)P.dt;
+        // spherical coordinates of the current position
+        double r = ::sqrt(x * x + y * y + z * z);
+        R th = M<R>::acos_((R)(z / r));
+        R ph = M<R>::atan2_((R)y, (R)x);
+        if (ph < (R)0) ph += (R)(2.0 * kPi);
+        const uint64_t n_end = n0 + n_steps;
+        uint64_t nstart = n0 > kinj ? n0 : kinj;
+        for (uint64_t n = nstart; n < n_end; ++n) {
+            // ---- clock and snapshot pair (identical for every particle)
+            const double t = P.t0 + (double)n * P.dt;
+            int ks = 0;
+            R alpha = (R)0;
+            if (G.n_snap >= 2) {
+                const double tau = (t - G.t_s0) * G.inv_dt_s;
+                double kf = ::floor(tau);
+                kf = kf < 0.0 ? 0.0 : (kf > (double)(G.n_snap - 2) ? (double)(G.n_snap - 2) : kf);
+                ks = (int)kf;
+                alpha = (R)(tau - kf);
+            }
+            // ---- locate + gather + interpolate
+            R s[3];
+            grid_coords<R>(G, r, th, ph, s);
+            R acc[kNF];
+            if (!gather<R, KPERP>(G, s, ks, alpha, acc)) {
+                status = FTE_PS_NUMERIC;
+                break;
+            }
+            R st_, ct_, sp_, cp_;
+            {
+                const R xf = (R)x, yf = (R)y, zf = (R)z;
+                const R rho = M<R>::sqrt_(xf * xf + yf * yf);
+                const R rr = (R)r;
+                st_ = rho / rr;
+                ct_ = zf / rr;
+                sp_ = yf / rho;
+                cp_ = xf / rho;
+            }
+            Fields<R> F;
+            to_cart<R>(st_, ct_, sp_, cp_, acc + 0, F.V);
+            R bt[3];
+            to_cart<R>(st_, ct_, sp_, cp_, acc + 3, bt);
+            const R bn = M<R>::sqrt_(bt[0] * bt[0] + bt[1] * bt[1] + bt[2] * bt[2]);
+            if (!(bn >= (R)1e-12)) {
+                status = FTE_PS_NUMERIC;
+                break;
+            }
+            F.b[0] = bt[0] / bn;
+            F.b[1] = bt[1] / bn;
+            F.b[2] = bt[2] / bn;
+            F.divV = acc[6];
+            F.bbgV = acc[7];
+            F.divb = acc[8];
+            F.bDV = acc[9];
+            if (KPERP) {
+                to_cart<R>(st_, ct_, sp_, cp_, acc + 10, F.curv);
+            } else {
+                F.curv[0] = F.curv[1] = F.curv[2] = (R)0;
+            }
+            // ---- coefficients (Eqs. 2-5)
+            const R Pm = M<R>::exp_(lnp);
+            const R gam = M<R>::sqrt_((R)1 + Pm * Pm);
+            const R v = (R)kC * Pm / gam;
+            R lam = (R)P.lambda_ref;
+            if (P.alpha != 0.0) lam *= M<R>::pow_(Pm * (R)P.inv_p_ref, (R)P.alpha);
+            const R A = (R)P.dmm_scale * v / lam;
+            const R am = mu < (R)0 ? -mu : mu;
+            const R om = (R)1 - mu * mu;
+            R D, dD;
+            if (P.dmm_model == FTE_DMM_ISO) {
+                D = A * om;
+                dD = (R)-2 * mu * A;
+            } else if (P.dmm_model == FTE_DMM_EQ5) {
+                const R g = am / ((R)1 + am) + (R)P.eps;
+                D = A * g * om;
+                dD = A * (sgn(mu) * om / (((R)1 + am) * ((R)1 + am)) - (R)2 * mu * g);
+            } else {
+                const R q = (R)P.q;
+                const R amf = am > (R)P.mu_floor ? am : (R)P.mu_floor;
+                const R g = M<R>::pow_(am, q - (R)1);
+                D = A * om * g;
+                dD = A * ((q - (R)1) * sgn(mu) * M<R>::pow_(amf, q - (R)2) * om - (R)2 * mu * g);
+            }
+            R kperp = (R)0;
+            if (KPERP) {
+                if (P.kperp_ratio > 0.0) kperp = (R)P.kperp_ratio * v * lam / (R)3;
+                else kperp = v * (R)P.lambda_perp / (R)3;
+            }
+            R a_x[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) a_x[a] = F.V[a] + mu * v * F.b[a] - kperp * (F.divb * F.b[a] + F.curv[a]);
+            const R a_mu = (R)0.5 * om * (v * F.divb + mu * F.divV - (R)3 * mu * F.bbgV - ((R)2 / v) * F.bDV) + dD;
+            const R a_lnp = (R)0.5 * ((R)1 - (R)3 * mu * mu) * F.bbgV - (R)0.5 * om * F.divV - (mu / v) * F.bDV;
+            // ---- Wiener increments: one Philox block, Box-Muller pairs
+            const U4 k4 = philox_words(P.seed, P.run_id, n, pid, 0u);
+            const R u0 = M<R>::u01(k4.a), u1 = M<R>::u01(k4.b), u2 = M<R>::u01(k4.c), u3 = M<R>::u01(k4.d);
+            const R ra = M<R>::sqrt_((R)-2 * M<R>::log_(u0));
+            const R rb = M<R>::sqrt_((R)-2 * M<R>::log_(u2));
+            R c1, s1, c3, s3;
+            M<R>::cs2pi(u1, &c1, &s1);
+            M<R>::cs2pi(u3, &c3, &s3);
+            const R z0 = ra * c1, z1 = ra * s1, z2 = rb * c3, z3 = rb * s3;
+            // ---- Euler-Maruyama update
+            double xn, yn, zn;
+            {
+                R dx[3];
+                if (KPERP) {
+                    const R xib = z1 * F.b[0] + z2 * F.b[1] + z3 * F.b[2];
+                    const R sx = M<R>::sqrt_((R)2 * kperp * dt);
+                    dx[0] = a_x[0] * dt + sx * (z1 - xib * F.b[0]);
+                    dx[1] = a_x[1] * dt + sx * (z2 - xib * F.b[1]);
+                    dx[2] = a_x[2] * dt + sx * (z3 - xib * F.b[2]);
+                } else {
+                    dx[0] = a_x[0] * dt;
+                    dx[1] = a_x[1] * dt;
+                    dx[2] = a_x[2] * dt;
+                }
+                xn = x + (double)dx[0];
+                yn = y + (double)dx[1];
+                zn = z + (double)dx[2];
+            }
+            R mun = mu + a_mu * dt + M<R>::sqrt_((R)2 * D * dt) * z0;
+            if (mun > (R)1) mun = (R)2 - mun;
+            if (mun < (R)-1) mun = (R)-2 - mun;
+            mun = mun > (R)1 ? (R)1 : (mun < (R)-1 ? (R)-1 : mun);
+            const R lnpn = lnp + a_lnp * dt;
+            ++my_steps;
+            if (!(isfinite(xn) && isfinite(yn) && isfinite(zn) && isfinite(mun) && isfinite(lnpn))) {
+                status = FTE_PS_NUMERIC;
+                break;
+            }
+            x = xn;
+            y = yn;
+            z = zn;
+            mu = mun;
+            lnp = lnpn;
+            // ---- boundaries (radius in double on both paths)
+            r = ::sqrt(x * x + y * y + z * z);
+            if (r < P.r_in) {
+                status = FTE_PS_ABSORBED_IN;
+                break;
+            }
+            if (r > P.r_out) {
+                status = FTE_PS_ABSORBED_OUT;
+                break;
+            }
+            th = M<R>::acos_((R)(z / r));
+            ph = M<R>::atan2_((R)y, (R)x);
+            if (ph < (R)0) ph += (R)(2.0 * kPi);
+            if (th < (R)G.th_lo || th > (R)G.th_hi) {
+                status = FTE_PS_OUT_OF_DOMAIN;
+                break;
+            }
+            // ---- residence-time observer estimator, post-step state
+            if (P.n_obs > 0) {
+                const R Pn = M<R>::exp_(lnp);
+                const R gn = M<R>::sqrt_((R)1 + Pn * Pn);
+                const R vn = (R)kC * Pn / gn;
+                const R lnE = M<R>::log_((R)P.mass_c2 * Pn * Pn / (gn + (R)1));
+                const R ue = (lnE - (R)P.e_min_ln) * (R)P.inv_dlne;
+                const double ut = (t + P.dt - P.t_ref) * P.inv_dT;
+                if (ue >= (R)0 && ue < (R)P.n_e && ut >= 0.0 && ut < (double)P.n_t) {
+                    const int ie = (int)M<R>::floor_(ue);
+                    const int it = (int)::floor(ut);
+                    const int ib = (int)(pid % (uint64_t)P.n_batch);
+                    for (int o = 0; o < P.n_obs; ++o) {
+                        const double *ob = P.obs[o];
+                        R dph = ph - (R)ob[4];
+                        while (dph >= (R)kPi) dph -= (R)(2.0 * kPi);
+                        while (dph < (R)-kPi) dph += (R)(2.0 * kPi);
+                        if (r >= ob[0] && r < ob[1] && th >= (R)ob[2] && th < (R)ob[3] && dph >= (R)-ob[5] &&
+                            dph < (R)ob[5]) {
+                            const size_t hidx = (((size_t)o * P.n_e + ie) * P.n_t + it) * P.n_batch + ib;
+                            atomicAdd(&hist[hidx], w * (double)vn * P.dt);
+                        }
+                    }
+                }
+            }
+        }
+        st.x[i] = x;
+        st.y[i] = y;
+        st.z[i] = z;
+        st.mu[i] = (double)mu;
+        st.lnp[i] = (double)lnp;
+        if (status != FTE_PS_ACTIVE) {
+            st.status[i] = status;
+            atomicAdd(&cnt->retired[status], 1ull);
+            atomicAdd(&cnt->w_retired[status], w);
+        }
+    }
+    // block total of particle-steps, one atomic per block
+    __shared__ unsigned long long red[1024 / 64];
+    unsigned long long v = my_steps;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long tot = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) tot += red[k];
+        if (tot) atomicAdd(&cnt->steps, tot);
+    }
+}
+
+hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevCounters *cnt, int slot, double *hist,
+                       uint64_t n0, uint32_t n_steps, uint64_t n_upper, int block, int fp32, hipStream_t s) {
+    if (n_upper == 0 || n_steps == 0) return hipSuccess;
+    const bool kp = p.kperp_ratio > 0.0 || p.lambda_perp > 0.0;
+    dim3 grid(blocks_for(n_upper, block)), blk(block);
+    if (fp32) {
+        if (kp)
+            hipLaunchKernelGGL((k_step<float, true>), grid, blk, 0, s, p, g, st, cnt, slot, hist, n0, n_steps);
+        else
+            hipLaunchKernelGGL((k_step<float, false>), grid, blk, 0, s, p, g, st, cnt, slot, hist, n0, n_steps);
+    } else {
+        if (kp)
+            hipLaunchKernelGGL((k_step<double, true>), grid, blk, 0, s, p, g, st, cnt, slot, hist, n0, n_steps);
+        else
+            hipLaunchKernelGGL((k_step<double, false>), grid, blk, 0, s, p, g, st, cnt, slot, hist, n0, n_steps);
+    }
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// compaction: wavefront ballot + in-wave prefix, one atomic per wave
+// ===========================================================================
+__global__ void k_zero_live(DevCounters *cnt, int slot) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) cnt->n_live[slot] = 0;
+}
+
+__global__ void k_compact(DevState src, DevState dst, DevCounters *cnt, int from) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t n_live = cnt->n_live[from];
+    const bool alive = i < n_live && src.status[i] == FTE_PS_ACTIVE;
+    const unsigned long long mask = __ballot(alive);
+    const int lane = threadIdx.x & 63;
+    const int prefix = __popcll(mask & ((1ull << lane) - 1ull));
+    const int total = __popcll(mask);
+    unsigned long long base = 0;
+    if (lane == 0 && total > 0) base = atomicAdd(&cnt->n_live[1 - from], (unsigned long long)total);
+    base = __shfl(base, 0, 64);
+    if (alive) {
+        const uint64_t j = base + prefix;
+        dst.x[j] = src.x[i];
+        dst.y[j] = src.y[i];
+        dst.z[j] = src.z[i];
+        dst.mu[j] = src.mu[i];
+        dst.lnp[j] = src.lnp[i];
+        dst.w[j] = src.w[i];
+        dst.pid[j] = src.pid[i];
+        dst.kinj[j] = src.kinj[i];
+        dst.status[j] = FTE_PS_ACTIVE;
+    }
+}
+
+hipError_t launch_zero_live(DevCounters *cnt, int slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_live, dim3(1), dim3(64), 0, s, cnt, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(DevState src, DevState dst, DevCounters *cnt, int from, uint64_t n_upper, int block,
+                          hipStream_t s) {
+    if (n_upper == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compact, dim3(blocks_for(n_upper, block)), dim3(block), 0, s, src, dst, cnt, from);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// finalisation: j = S / (4 pi dV dT dE W_inj), standard error from batches
+// ===========================================================================
+__global__ void k_finalize(DevParams P, const double *hist, const DevCounters *cnt, double *j, double *sig) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = P.n_obs * P.n_e * P.n_t;
+    if (idx >= n) return;
+    const int o = idx / (P.n_e * P.n_t);
+    const int e = (idx / P.n_t) % P.n_e;
+    double W = 0.0;
+    for (int b = 0; b < P.n_batch; ++b) W += cnt->w_inj[b];
+    const double *ob = P.obs[o];
+    const double dV = (ob[1] * ob[1] * ob[1] - ob[0] * ob[0] * ob[0]) / 3.0 * (::cos(ob[2]) - ::cos(ob[3])) *
+                      (2.0 * ob[5]);
+    const double dE = P.e_min * (::exp((e + 1) * P.dlne) - ::exp(e * P.dlne));
+    const double norm = 4.0 * kPi * dV * P.dT * dE * W;
+    const double *h = hist + (size_t)idx * P.n_batch;
+    double s = 0.0;
+    for (int b = 0; b < P.n_batch; ++b) s += h[b];
+    const double jm = s / norm;
+    double var = 0.0;
+    for (int b = 0; b < P.n_batch; ++b) {
+        const double jb = P.n_batch * h[b] / norm;
+        var += (jb - jm) * (jb - jm);
+    }
+    j[idx] = jm;
+    sig[idx] = P.n_batch > 1 ? ::sqrt(var / ((double)P.n_batch * (P.n_batch - 1))) : 0.0;
+}
+
+hipError_t launch_finalize(const DevParams &p, const double *hist, const DevCounters *cnt, double *j, double *sig,
+                           hipStream_t s) {
+    const int n = p.n_obs * p.n_e * p.n_t;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, hist, cnt, j, sig);
+    return hipGetLastError();
+}
+
+__global__ void k_zero(double *p, uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+hipError_t launch_zero(double *p, uint64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+__global__ void k_zero_counters(DevCounters *cnt) {
+    const int t = threadIdx.x;
+    unsigned int *w = reinterpret_cast<unsigned int *>(cnt);
+    const int nw = (int)(sizeof(DevCounters) / sizeof(unsigned int));
+    for (int k = t; k < nw; k += blockDim.x) w[k] = 0u;
+}
+
+hipError_t launch_zero_counters(DevCounters *cnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(256), 0, s, cnt);
+    return hipGetLastError();
+}
+
+}  // namespace fte

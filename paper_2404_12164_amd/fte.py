@@ -1,0 +1,385 @@
+"""Python binding of the C ABI in ``include/fte.h`` (argument marshalling only).
+
+Every step of the path runs in the HIP kernels of ``libfte.so``; this module
+only converts plain workload descriptions into the C structures, owns the
+device buffers as torch tensors (torch is used for device memory and streams),
+and forwards calls.  If the library is missing the import fails: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfte.so")
+
+FTE_OK, FTE_EINVAL, FTE_ESTATE, FTE_ENOMEM, FTE_EDEVICE, FTE_ERANGE = 0, -1, -2, -3, -4, -5
+FTE_FP64, FTE_MIXED = 0, 1
+DMM = {"iso": 0, "eq5": 1, "power_q": 2}
+MAX_OBS = 8
+RECORD_STRIDE = 16
+RECORD_FIELDS = 13
+STATUS = {"active": 0, "absorbed_in": 1, "absorbed_out": 2, "out_of_domain": 3, "numeric": 4}
+SYMBOLS = ["fte_create", "fte_destroy", "fte_last_error", "fte_query_sizes", "fte_bind_buffers", "fte_load_grid",
+           "fte_inject", "fte_step_n", "fte_bin_observers", "fte_read_hist", "fte_get_stats", "fte_read_particles",
+           "fte_set_launch"]
+
+
+class fte_observer(C.Structure):
+    _fields_ = [("r", C.c_double), ("theta", C.c_double), ("phi", C.c_double),
+                ("dr", C.c_double), ("dtheta", C.c_double), ("dphi", C.c_double)]
+
+
+class fte_params(C.Structure):
+    _fields_ = [("mass", C.c_double), ("dmm_model", C.c_int), ("dmm_norm", C.c_int),
+                ("lambda_ref", C.c_double), ("p_ref", C.c_double), ("alpha", C.c_double),
+                ("q", C.c_double), ("eps", C.c_double), ("mu_floor", C.c_double),
+                ("kperp_ratio", C.c_double), ("lambda_perp", C.c_double),
+                ("dt", C.c_double), ("t0", C.c_double), ("r_in", C.c_double), ("r_out", C.c_double),
+                ("seed", C.c_uint64), ("run_id", C.c_int), ("precision", C.c_int),
+                ("n_obs", C.c_int), ("obs", fte_observer * MAX_OBS),
+                ("e_min", C.c_double), ("dlne", C.c_double), ("n_e", C.c_int),
+                ("t_ref", C.c_double), ("dT", C.c_double), ("n_t", C.c_int), ("n_batch", C.c_int)]
+
+
+class fte_grid_desc(C.Structure):
+    _fields_ = [("xi_map", C.c_int), ("r_lo", C.c_double), ("dxi", C.c_double),
+                ("th_lo", C.c_double), ("dth", C.c_double), ("ph_lo", C.c_double), ("dph", C.c_double),
+                ("phi_periodic", C.c_int), ("n1", C.c_int * 3), ("bx", C.c_int * 3), ("n_levels", C.c_int),
+                ("n_leaves", C.c_int), ("leaves", C.POINTER(C.c_int32)), ("n_snap", C.c_int),
+                ("t_s0", C.c_double), ("dt_s", C.c_double)]
+
+
+class fte_injection(C.Structure):
+    _fields_ = [("r", C.c_double), ("th_lo", C.c_double), ("th_hi", C.c_double), ("ph_lo", C.c_double),
+                ("ph_hi", C.c_double), ("e_lo", C.c_double), ("e_hi", C.c_double), ("gamma_inj", C.c_double),
+                ("w0", C.c_double), ("r_weight", C.c_int), ("r_ref", C.c_double), ("pid0", C.c_uint64),
+                ("n_total", C.c_uint64), ("k0", C.c_uint32), ("n_inj_steps", C.c_uint32)]
+
+
+class fte_sizes(C.Structure):
+    _fields_ = [("grid_bytes", C.c_uint64), ("index_bytes", C.c_uint64), ("state_bytes", C.c_uint64),
+                ("hist_bytes", C.c_uint64), ("work_bytes", C.c_uint64)]
+
+
+class fte_buffers(C.Structure):
+    _fields_ = [("grid", C.c_void_p), ("index", C.c_void_p), ("state_a", C.c_void_p), ("state_b", C.c_void_p),
+                ("hist", C.c_void_p), ("work", C.c_void_p)]
+
+
+class fte_stats(C.Structure):
+    _fields_ = [("n_live", C.c_uint64), ("n_injected", C.c_uint64), ("particle_steps", C.c_uint64),
+                ("n_retired", C.c_uint64 * 5), ("w_injected", C.c_double), ("w_retired", C.c_double * 5),
+                ("global_step", C.c_uint64), ("device_flags", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfte.so (built by ``paper_2404_12164_amd.build``); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2404_12164_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp, u64, u32 = C.c_void_p, C.c_uint64, C.c_uint32
+        dp = C.POINTER(C.c_double)
+        L.fte_create.argtypes = [C.POINTER(vp), C.POINTER(fte_params)]
+        L.fte_destroy.argtypes = [vp]
+        L.fte_destroy.restype = None
+        L.fte_last_error.argtypes = [vp]
+        L.fte_last_error.restype = C.c_char_p
+        L.fte_query_sizes.argtypes = [C.POINTER(fte_params), C.POINTER(fte_grid_desc), u64, C.POINTER(fte_sizes)]
+        L.fte_bind_buffers.argtypes = [vp, C.POINTER(fte_grid_desc), u64, C.POINTER(fte_buffers)]
+        L.fte_load_grid.argtypes = [vp, vp, vp]
+        L.fte_inject.argtypes = [vp, C.POINTER(fte_injection), u64, u64, vp]
+        L.fte_step_n.argtypes = [vp, u32, vp]
+        L.fte_bin_observers.argtypes = [vp, dp, dp, C.c_int, vp]
+        L.fte_read_hist.argtypes = [vp, dp, dp, vp]
+        L.fte_get_stats.argtypes = [vp, C.POINTER(fte_stats), vp]
+        L.fte_read_particles.argtypes = [vp, dp, dp, dp, dp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32),
+                                         C.POINTER(C.c_int32), u64, C.POINTER(C.c_uint64), vp]
+        L.fte_set_launch.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+        for name in SYMBOLS:
+            if name not in ("fte_destroy", "fte_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class FteError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fte status {status}: {msg}")
+        self.status = status
+
+
+# ----------------------------------------------------------------------------
+# marshalling of plain workload descriptions
+# ----------------------------------------------------------------------------
+def make_params(p: dict) -> fte_params:
+    o = fte_params()
+    o.mass = p["mass"]
+    dm = p.get("dmm_model", "power_q")
+    o.dmm_model = DMM[dm] if isinstance(dm, str) else int(dm)
+    o.dmm_norm = int(p.get("dmm_norm", 0))
+    o.lambda_ref = p["lambda_ref"]
+    o.p_ref = p.get("p_ref", 1.0)
+    o.alpha = p.get("alpha", 0.0)
+    o.q = p.get("q", 5.0 / 3.0)
+    o.eps = p.get("eps", 0.0)
+    o.mu_floor = p.get("mu_floor", 1e-4)
+    o.kperp_ratio = p.get("kperp_ratio", 0.0)
+    o.lambda_perp = p.get("lambda_perp", 0.0)
+    o.dt = p["dt"]
+    o.t0 = p.get("t0", 0.0)
+    o.r_in = p.get("r_in", 0.0)
+    o.r_out = p.get("r_out", 1e300)
+    o.seed = int(p.get("seed", 0))
+    o.run_id = int(p.get("run_id", 0))
+    prec = p.get("precision", "fp64")
+    o.precision = {"fp64": FTE_FP64, "mixed": FTE_MIXED}[prec] if isinstance(prec, str) else int(prec)
+    obs = p.get("observers", [])
+    o.n_obs = len(obs)
+    for i, ob in enumerate(obs):
+        o.obs[i] = fte_observer(*[float(v) for v in ob])
+    o.e_min = p.get("e_min", 1.0)
+    o.dlne = p.get("dlne", 1.0)
+    o.n_e = int(p.get("n_e", 1))
+    o.t_ref = p.get("t_ref", 0.0)
+    o.dT = p.get("dT", 1.0)
+    o.n_t = int(p.get("n_t", 1))
+    o.n_batch = int(p.get("n_batch", 32))
+    return o
+
+
+def make_grid_desc(g: dict):
+    leaves = np.ascontiguousarray(g["leaves"], dtype=np.int32)
+    d = fte_grid_desc()
+    d.xi_map = int(g["xi_map"])
+    d.r_lo, d.dxi = g["r_lo"], g["dxi"]
+    d.th_lo, d.dth = g["th_lo"], g["dth"]
+    d.ph_lo, d.dph = g["ph_lo"], g["dph"]
+    d.phi_periodic = int(g["phi_periodic"])
+    for a in range(3):
+        d.n1[a] = int(g["n1"][a])
+        d.bx[a] = int(g["bx"][a])
+    d.n_levels = int(g["n_levels"])
+    d.n_leaves = int(leaves.shape[0])
+    d.leaves = leaves.ctypes.data_as(C.POINTER(C.c_int32))
+    d.n_snap = int(g["n_snap"])
+    d.t_s0 = g.get("t_s0", 0.0)
+    d.dt_s = g.get("dt_s", 1.0)
+    return d, leaves
+
+
+def make_injection(inj: dict) -> fte_injection:
+    o = fte_injection()
+    o.r = inj["r"]
+    o.th_lo, o.th_hi = inj["th_lo"], inj["th_hi"]
+    o.ph_lo, o.ph_hi = inj["ph_lo"], inj["ph_hi"]
+    o.e_lo = inj["e_lo"]
+    o.e_hi = inj.get("e_hi", inj["e_lo"])
+    o.gamma_inj = inj.get("gamma_inj", 1.0)
+    o.w0 = inj.get("w0", 1.0)
+    o.r_weight = int(inj.get("r_weight", 0))
+    o.r_ref = inj.get("r_ref", 1.0)
+    o.pid0 = int(inj.get("pid0", 0))
+    o.n_total = int(inj["n_total"])
+    o.k0 = int(inj.get("k0", 0))
+    o.n_inj_steps = int(inj.get("n_inj_steps", 0))
+    return o
+
+
+# ----------------------------------------------------------------------------
+# thin wrappers with the C names
+# ----------------------------------------------------------------------------
+def _check(ctx, st):
+    if st != FTE_OK:
+        msg = lib().fte_last_error(ctx).decode() if ctx else ""
+        raise FteError(st, msg)
+
+
+def fte_create(params: dict):
+    h = C.c_void_p()
+    pp = make_params(params)
+    st = lib().fte_create(C.byref(h), C.byref(pp))
+    if st != FTE_OK:
+        raise FteError(st, "invalid parameters")
+    return h
+
+
+def fte_destroy(ctx):
+    lib().fte_destroy(ctx)
+
+
+def fte_query_sizes(params: dict, grid: dict, n_max: int) -> fte_sizes:
+    pp = make_params(params)
+    gd, _keep = make_grid_desc(grid)
+    out = fte_sizes()
+    st = lib().fte_query_sizes(C.byref(pp), C.byref(gd), int(n_max), C.byref(out))
+    if st != FTE_OK:
+        raise FteError(st, "invalid parameters or grid")
+    return out
+
+
+def fte_bind_buffers(ctx, grid: dict, n_max: int, bufs: fte_buffers):
+    gd, _keep = make_grid_desc(grid)
+    _check(ctx, lib().fte_bind_buffers(ctx, C.byref(gd), int(n_max), C.byref(bufs)))
+
+
+def fte_load_grid(ctx, vb_sph_ptr: int, stream: int):
+    _check(ctx, lib().fte_load_grid(ctx, C.c_void_p(vb_sph_ptr), C.c_void_p(stream)))
+
+
+def fte_inject(ctx, inj: dict, n: int, first_pid: int, stream: int):
+    io = make_injection(inj)
+    _check(ctx, lib().fte_inject(ctx, C.byref(io), int(n), int(first_pid), C.c_void_p(stream)))
+
+
+def fte_step_n(ctx, n_steps: int, stream: int):
+    _check(ctx, lib().fte_step_n(ctx, int(n_steps), C.c_void_p(stream)))
+
+
+def fte_bin_observers(ctx, shape, reset: bool, stream: int):
+    n = int(np.prod(shape))
+    j = np.zeros(max(n, 1))
+    s = np.zeros(max(n, 1))
+    dp = C.POINTER(C.c_double)
+    _check(ctx, lib().fte_bin_observers(ctx, j.ctypes.data_as(dp), s.ctypes.data_as(dp), int(bool(reset)),
+                                        C.c_void_p(stream)))
+    return j[:n].reshape(shape), s[:n].reshape(shape)
+
+
+def fte_read_hist(ctx, n: int, stream: int):
+    h = np.zeros(max(n, 1))
+    w = C.c_double()
+    _check(ctx, lib().fte_read_hist(ctx, h.ctypes.data_as(C.POINTER(C.c_double)), C.byref(w), C.c_void_p(stream)))
+    return h[:n], w.value
+
+
+def fte_get_stats(ctx, stream: int) -> fte_stats:
+    out = fte_stats()
+    _check(ctx, lib().fte_get_stats(ctx, C.byref(out), C.c_void_p(stream)))
+    return out
+
+
+def fte_read_particles(ctx, cap: int, stream: int) -> dict:
+    x = np.zeros((cap, 3))
+    mu = np.zeros(cap)
+    lnp = np.zeros(cap)
+    w = np.zeros(cap)
+    pid = np.zeros(cap, dtype=np.uint64)
+    kinj = np.zeros(cap, dtype=np.uint32)
+    status = np.zeros(cap, dtype=np.int32)
+    n = C.c_uint64()
+    dp = C.POINTER(C.c_double)
+    _check(ctx, lib().fte_read_particles(ctx, x.ctypes.data_as(dp), mu.ctypes.data_as(dp), lnp.ctypes.data_as(dp),
+                                         w.ctypes.data_as(dp), pid.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                         kinj.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                         status.ctypes.data_as(C.POINTER(C.c_int32)), int(cap), C.byref(n),
+                                         C.c_void_p(stream)))
+    k = n.value
+    return dict(x=x[:k], mu=mu[:k], lnp=lnp[:k], w=w[:k], pid=pid[:k], kinj=kinj[:k], status=status[:k])
+
+
+def fte_set_launch(ctx, block: int, steps_per_launch: int, compact_every: int):
+    _check(ctx, lib().fte_set_launch(ctx, int(block), int(steps_per_launch), int(compact_every)))
+
+
+# ----------------------------------------------------------------------------
+# convenience: a context with torch-owned device buffers
+# ----------------------------------------------------------------------------
+class Simulation:
+    """One context plus its device buffers (torch uint8 tensors on ``device``)."""
+
+    def __init__(self, params: dict, grid: dict, n_max: int, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.params = params
+        self.grid = grid
+        self.n_max = int(n_max)
+        self.device = torch.device(device)
+        self.sizes = fte_query_sizes(params, grid, n_max)
+        s = self.sizes
+
+        def buf(nbytes):
+            return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+
+        self.t_grid = buf(s.grid_bytes)
+        self.t_index = buf(s.index_bytes)
+        self.t_state_a = buf(s.state_bytes)
+        self.t_state_b = buf(s.state_bytes)
+        self.t_hist = buf(s.hist_bytes)
+        self.t_work = buf(s.work_bytes)
+        self.bufs = fte_buffers(self.t_grid.data_ptr(), self.t_index.data_ptr(), self.t_state_a.data_ptr(),
+                                self.t_state_b.data_ptr(), self.t_hist.data_ptr(), self.t_work.data_ptr())
+        self.ctx = fte_create(params)
+        fte_bind_buffers(self.ctx, grid, n_max, self.bufs)
+        self.n_bins = (len(params.get("observers", [])), int(params.get("n_e", 1)), int(params.get("n_t", 1)))
+
+    @property
+    def stream(self) -> int:
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def load_grid(self, vb_sph):
+        """vb_sph: float64 array [n_snap][n_leaves][cells][6] (numpy or torch)."""
+        t = self.torch
+        g = self.grid
+        bx = g["bx"]
+        want = (int(g["n_snap"]), len(g["leaves"]), bx[0] * bx[1] * bx[2], 6)
+        if tuple(vb_sph.shape) != want:
+            raise ValueError(f"wind data shape {tuple(vb_sph.shape)} != {want}")
+        if isinstance(vb_sph, np.ndarray):
+            vb = t.from_numpy(np.ascontiguousarray(vb_sph, dtype=np.float64)).to(self.device)
+        else:
+            vb = vb_sph.to(device=self.device, dtype=t.float64).contiguous()
+        fte_load_grid(self.ctx, vb.data_ptr(), self.stream)
+        del vb
+
+    def set_launch(self, block=256, steps_per_launch=64, compact_every=512):
+        fte_set_launch(self.ctx, block, steps_per_launch, compact_every)
+
+    def inject(self, inj: dict, n: int, first_pid: int):
+        fte_inject(self.ctx, inj, n, first_pid, self.stream)
+
+    def step(self, n_steps: int):
+        fte_step_n(self.ctx, n_steps, self.stream)
+
+    def bin_observers(self, reset=False):
+        return fte_bin_observers(self.ctx, self.n_bins, reset, self.stream)
+
+    def read_hist(self):
+        n = int(np.prod(self.n_bins)) * int(self.params.get("n_batch", 32))
+        return fte_read_hist(self.ctx, n, self.stream)
+
+    def stats(self) -> fte_stats:
+        return fte_get_stats(self.ctx, self.stream)
+
+    def particles(self) -> dict:
+        return fte_read_particles(self.ctx, self.n_max, self.stream)
+
+    def records(self):
+        """Grid records as a float tensor view [n_snap][n_leaves][pcells][16]."""
+        t = self.torch
+        bx = self.grid["bx"]
+        pc = (bx[0] + 2) * (bx[1] + 2) * (bx[2] + 2)
+        dt = t.float64 if make_params(self.params).precision == FTE_FP64 else t.float32
+        nl = len(self.grid["leaves"])
+        return self.t_grid.view(dt)[: self.grid["n_snap"] * nl * pc * RECORD_STRIDE].view(
+            self.grid["n_snap"], nl, pc, RECORD_STRIDE)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            fte_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,123 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every symbol include/fte.h declares, and its grid validation and buffer sizing
+(pure host logic) accept valid descriptions and reject broken ones."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import fte_workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2404_12164_amd import fte
+    if not os.path.exists(fte.LIB_PATH):
+        from paper_2404_12164_amd import build
+        build.build()
+    fte.lib()
+    return fte
+
+
+def test_exports_every_declared_symbol(F):
+    hdr = open(os.path.join(ROOT, "include", "fte.h")).read()
+    declared = set(re.findall(r"\b(fte_[a-z_]+)\s*\(", hdr))
+    assert declared == set(F.SYMBOLS)
+    L = F.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_struct_sizes_match_header_layout(F):
+    import ctypes as C
+    # the binding's structures are laid out like the C ones (natural alignment)
+    assert C.sizeof(F.fte_observer) == 48
+    assert C.sizeof(F.fte_sizes) == 40
+    assert C.sizeof(F.fte_buffers) == 48
+    assert C.sizeof(F.fte_injection) == 8 * 9 + 8 + 8 + 8 + 8 + 4 + 4
+
+
+def test_query_sizes_valid(F):
+    cfg = W.tiny_parker()
+    s = F.fte_query_sizes(cfg["params"], cfg["grid"], 2000)
+    pc = 18 ** 3
+    assert s.grid_bytes == 1 * 32 * pc * 16 * 8
+    mixed = dict(cfg["params"], precision="mixed")
+    assert F.fte_query_sizes(mixed, cfg["grid"], 2000).grid_bytes == s.grid_bytes // 2
+    assert s.hist_bytes == 1 * 10 * 60 * 32 * 8
+    assert s.state_bytes >= 2000 * 64
+
+
+def test_query_sizes_amr_cir(F):
+    cfg = W.cir_time_dependent(n_particles=1000, n_snap=3)
+    s = F.fte_query_sizes(cfg["params"], cfg["grid"], 1000)
+    nl = len(cfg["grid"]["leaves"])
+    assert s.grid_bytes == 3 * nl * 18 * 14 * 18 * 16 * 4
+
+
+def _tiny_grid(**over):
+    n1, bx = (16, 8, 16), (4, 4, 4)
+    g = W.grid_desc(0, 0.1 * W.AU, 0.1 * W.AU, 30 * W.DEG, 15 * W.DEG, 0.0, 2 * np.pi / 16, n1, bx,
+                    W.uniform_leaves(n1, bx), 1)
+    g.update(over)
+    return g
+
+
+def test_rejects_broken_grids(F):
+    p = W.tiny_parker()["params"]
+    ok = _tiny_grid()
+    F.fte_query_sizes(p, ok, 10)
+    bad = []
+    bad.append(_tiny_grid(leaves=ok["leaves"][:-1]))                       # hole
+    dup = np.concatenate([ok["leaves"], ok["leaves"][:1]])
+    bad.append(_tiny_grid(leaves=dup))                                      # overlap
+    bad.append(_tiny_grid(bx=[3, 4, 4], n1=[15, 8, 16]))                   # odd block
+    bad.append(_tiny_grid(dph=0.1))                                         # periodic span wrong
+    bad.append(_tiny_grid(dxi=-1.0))
+    bad.append(_tiny_grid(n_snap=0))
+    lv = ok["leaves"].copy()
+    lv[0, 0] = 2
+    bad.append(_tiny_grid(leaves=lv))                                       # level out of range
+    for g in bad:
+        with pytest.raises(F.FteError):
+            F.fte_query_sizes(p, g, 10)
+
+
+def test_rejects_unbalanced_amr(F):
+    p = W.tiny_parker()["params"]
+    n1, bx = (16, 8, 16), (4, 4, 4)
+    # refine one level-1 block twice without refining its neighbours
+    leaves = []
+    nb = [n1[a] // bx[a] for a in range(3)]
+    for K in range(nb[2]):
+        for J in range(nb[1]):
+            for I in range(nb[0]):
+                if (I, J, K) != (1, 0, 1):
+                    leaves.append((1, I, J, K))
+    for d in range(8):
+        a, b, c = 2 + (d & 1), 0 + ((d >> 1) & 1), 2 + ((d >> 2) & 1)
+        if d != 7:
+            leaves.append((2, a, b, c))
+        else:
+            for e in range(8):
+                leaves.append((3, 2 * a + (e & 1), 2 * b + ((e >> 1) & 1), 2 * c + ((e >> 2) & 1)))
+    g = W.grid_desc(0, 0.1 * W.AU, 0.1 * W.AU, 30 * W.DEG, 15 * W.DEG, 0.0, 2 * np.pi / 16, n1, bx,
+                    np.array(leaves, np.int32), 3)
+    with pytest.raises(F.FteError):
+        F.fte_query_sizes(p, g, 10)
+    # the balanced version of the same refinement is accepted
+    marks = {(1, 1, 0, 1), (2, 3, 1, 3)}
+    g2 = W.grid_desc(0, 0.1 * W.AU, 0.1 * W.AU, 30 * W.DEG, 15 * W.DEG, 0.0, 2 * np.pi / 16, n1, bx,
+                     W.amr_leaves(n1, bx, 3, lambda L, I, J, K: (L, I, J, K) in marks), 3)
+    F.fte_query_sizes(p, g2, 10)
+
+
+def test_rejects_bad_params(F):
+    cfg = W.tiny_parker()
+    for over in (dict(dt=0.0), dict(mass=-1.0), dict(n_batch=0), dict(n_batch=65), dict(dmm_model=7),
+                 dict(q=2.5), dict(r_out=0.0), dict(run_id=70000), dict(precision=3)):
+        with pytest.raises(F.FteError):
+            F.fte_query_sizes(dict(cfg["params"], **over), cfg["grid"], 10)
