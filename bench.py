@@ -1,0 +1,277 @@
+"""Throughput benchmark of the focused-transport pseudo-particle path on one MI355X.
+
+Workload (default): the time-dependent CIR wind - 48 hourly snapshots on a
+stretched 256 x 60 x 192 grid with one extra AMR level in the compression band,
+10^7 protons of 5-50 keV (E^-4) injected continuously at 0.1 au over 47 h,
+16,920 steps of 10 s, three observers at 1 au, mixed precision (float records
+and step arithmetic, double position/time/radial tests).  A bench "step" is one
+fte_step_n call of `chunk` global steps (including the injection of the
+particles that start in it, observer accumulation and compaction); the default
+30 steps cover the whole 16,920-step run.  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("fte_kernels.hip", "fte_device.hpp", "fte_internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2404_12164_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(name, algo_bytes_per_launch):
+    """HBM bytes per step-kernel launch from the committed counter summary,
+    if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+class Run:
+    """One context on the workload plus its lazy continuous-injection plan."""
+
+    def __init__(self, F, cfg, raw, precision, block, spl, compact):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        self.p = dict(cfg["params"], precision=precision)
+        self.inj = cfg["injection"]
+        self.N = int(cfg["n_particles"])
+        self.S = int(self.inj["n_inj_steps"])
+        self.sim = F.Simulation(self.p, cfg["grid"], self.N)
+        torch.cuda.synchronize()
+        t = time.time()
+        self.sim.load_grid(raw)
+        self.load_s = time.time() - t
+        self.sim.set_launch(block, spl, compact)
+        self.sim.set_timing(True)
+        self.injected = 0
+        self.n0 = 0
+
+    def reset(self):
+        self.sim.reset()
+        self.injected = 0
+        self.n0 = 0
+
+    def chunk(self, n):
+        """Inject every pid whose first step can fall before n0 + n, then step."""
+        n1 = self.n0 + n
+        if self.S > 0:
+            j_max = min(self.N, int(math.ceil(n1 * self.N / self.S)) + 1)
+        else:
+            j_max = self.N
+        if j_max > self.injected:
+            self.sim.inject(self.inj, j_max - self.injected, self.inj.get("pid0", 0) + self.injected)
+            self.injected = j_max
+        self.sim.step(n)
+        self.n0 = n1
+
+    def close(self):
+        self.sim.close()
+
+
+def timed(run, K, chunk):
+    torch = run.torch
+    st0 = run.sim.stats()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.time()
+    e0.record()
+    for k in range(K):
+        run.chunk(chunk)
+        if (k + 1) % max(1, K // 6) == 0:
+            log(f"  chunk {k + 1}/{K} enqueued")
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.time() - t0
+    ms = e0.elapsed_time(e1)
+    st1 = run.sim.stats()
+    steps = st1.particle_steps - st0.particle_steps
+    kms = st1.step_kernel_ms - st0.step_kernel_ms
+    nl = st1.step_launches - st0.step_launches
+    return dict(ms=ms, wall=wall, particle_steps=int(steps), kernel_ms=kms, launches=int(nl), stats=st1)
+
+
+def cpu_baseline(cfg, raw_gpu, n_pids, n_steps, n_threads):
+    """The FP64 oracle on the first n_pids particles over the first n_steps
+    steps, with the snapshots those steps touch copied to the host."""
+    import oracle
+    g = cfg["grid"]
+    p = dict(cfg["params"], precision="fp64")
+    t_last = p["t0"] + (n_steps - 1) * p["dt"]
+    k_hi = min(g["n_snap"] - 1, int(math.floor((t_last - g["t_s0"]) / g["dt_s"])) + 2)
+    raw = raw_gpu[: k_hi + 1].cpu().numpy()
+    G = oracle.Grid(g, raw, snap0=0)
+    parts = oracle.inject(p, cfg["injection"], n_pids, cfg["injection"].get("pid0", 0))
+    # only the snapshots held are valid: the grid description keeps its full
+    # snapshot count so the time derivative uses the run's own stencil
+    h = np.zeros(oracle.hist_size(p))
+    t = time.time()
+    steps = oracle.run(p, G, parts, 0, n_steps, h, n_threads)
+    dt = time.time() - t
+    return dict(value=steps / dt, unit="particle-steps/s", cores=n_threads, kind="oracle",
+                sample=f"pids 0..{n_pids - 1} (the first injected) x global steps 0..{n_steps - 1} "
+                       f"of the same workload, FP64, {steps} particle-steps in {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--chunk", type=int, default=564)
+    ap.add_argument("--particles", type=int, default=10_000_000)
+    ap.add_argument("--precision", default="mixed")
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--spl", type=int, default=64)
+    ap.add_argument("--compact", type=int, default=512)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-pids", type=int, default=4000)
+    ap.add_argument("--cpu-steps", type=int, default=2800)
+    ap.add_argument("--calib-copy", action="store_true", help="also run a 2 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described, not run",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import fte_workloads as W
+    from paper_2404_12164_amd import fte as F
+
+    dev = torch.device("cuda:0")
+    cfg = W.cir_time_dependent(n_particles=args.particles, precision=args.precision)
+    g = cfg["grid"]
+    total_steps = cfg["n_steps"]
+    if args.chunk * (args.steps + 0) > total_steps:
+        log(f"note: {args.steps} x {args.chunk} steps exceed the run's {total_steps}; clipping the chunk")
+        args.chunk = total_steps // args.steps
+    log(f"workload {cfg['name']}: {len(g['leaves'])} leaves, {g['n_snap']} snapshots, {args.particles} particles")
+
+    t = time.time()
+    raw = W.make_raw(g, cfg["wind"], xp=torch, device=dev)
+    torch.cuda.synchronize()
+    gen_s = time.time() - t
+    log(f"wind generated on the GPU in {gen_s:.1f} s ({raw.numel() * 8 / 1e9:.1f} GB)")
+
+    if args.calib_copy:
+        a = torch.empty(2 ** 28, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    run = Run(F, cfg, raw, args.precision, args.block, args.spl, args.compact)
+    log(f"grid loaded in {run.load_s:.2f} s")
+    if args.warmup > 0:
+        for _ in range(args.warmup):
+            run.chunk(args.chunk)
+        torch.cuda.synchronize()
+        run.reset()
+    log("timed region")
+    res = timed(run, args.steps, args.chunk)
+    value = res["particle_steps"] / (res["ms"] / 1e3)
+    js, _ = run.sim.bin_observers()
+    st = res["stats"]
+    grid_load_s = run.load_s
+    run.close()
+    del run
+
+    # roofline of the step kernel: algorithmic bytes per particle-step
+    F_fields = 13 if (cfg["params"].get("kperp_ratio", 0) > 0 or cfg["params"].get("lambda_perp", 0) > 0) else 10
+    T_s = 2 if g["n_snap"] >= 2 else 1
+    s_f = 4 if args.precision == "mixed" else 8
+    b_step = 8 * T_s * F_fields * s_f + 2 * 64 / args.spl
+    kernel_s = res["kernel_ms"] / 1e3
+    achieved = b_step * res["particle_steps"] / kernel_s / 1e9
+    per_launch_bytes = b_step * res["particle_steps"] / max(res["launches"], 1)
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=read_traffic("k_step_cir_traffic.txt", per_launch_bytes),
+                kernel="k_step<float,false>" if args.precision == "mixed" else "k_step<double,false>",
+                bytes_per_particle_step=b_step, launches=res["launches"],
+                avg_launch_ms=round(res["kernel_ms"] / max(res["launches"], 1), 4),
+                algo_bytes_per_launch=round(per_launch_bytes))
+
+    extra = {}
+    if not args.no_fp64 and args.precision == "mixed":
+        log("FP64 path on the same workload")
+        r64 = Run(F, cfg, raw, "fp64", args.block, args.spl, args.compact)
+        res64 = timed(r64, args.steps, args.chunk)
+        r64.close()
+        del r64
+        extra["fp64_value"] = res64["particle_steps"] / (res64["ms"] / 1e3)
+        extra["mixed_over_fp64"] = round(value / extra["fp64_value"], 3)
+        b64 = 8 * T_s * F_fields * 8 + 2 * 64 / args.spl
+        extra["fp64_roofline_frac"] = round(b64 * res64["particle_steps"] / (res64["kernel_ms"] / 1e3) / 1e9
+                                            / HBM_PEAK_GBS, 4)
+
+    cpu = None
+    if not args.no_cpu:
+        n_threads = min(16, len(os.sched_getaffinity(0)))
+        log(f"oracle CPU baseline on {n_threads} threads")
+        cpu = cpu_baseline(cfg, raw, args.cpu_pids, args.cpu_steps, n_threads)
+
+    out = {
+        "metric": "pseudo-particle steps/s on 1 MI355X (mixed vs FP64); adjoint/forward cost",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "particles": args.particles, "global_steps": args.steps * args.chunk,
+                   "chunk": args.chunk, "snapshots": g["n_snap"], "leaves": int(len(g["leaves"])),
+                   "levels": g["n_levels"], "precision": args.precision, "block": args.block,
+                   "steps_per_launch": args.spl, "compact_every": args.compact},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "particle_steps": res["particle_steps"],
+        "wind_gen_s": round(gen_s, 2),
+        "grid_load_s": round(grid_load_s, 2),
+        "observer_counts_nonzero": int((js > 0).sum()),
+        "retired": [int(v) for v in st.n_retired],
+    }
+    out.update(extra)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -182,6 +182,8 @@ typedef struct {
     double w_retired[5];
     uint64_t global_step;     /* next global step index                         */
     uint32_t device_flags;    /* nonzero: a kernel met an unsupported case      */
+    uint32_t step_launches;   /* step-kernel launches timed since the last reset */
+    double step_kernel_ms;    /* their summed duration (HIP events on `stream`) */
 } fte_stats;
 
 /* Record layout of the grid buffer (for readers of the raw buffer):
@@ -248,6 +250,14 @@ fte_status fte_get_stats(fte_ctx *ctx, fte_stats *out, void *stream);
  * order (not pid order).  Synchronises. */
 fte_status fte_read_particles(fte_ctx *ctx, double *x3, double *mu, double *lnp, double *w, uint64_t *pid,
                               uint32_t *kinj, int32_t *status, uint64_t cap, uint64_t *n_out, void *stream);
+
+/* Drop all particles, observer sums, counters and timings and rewind the
+ * global clock to step 0; the loaded grid stays.  Synchronises. */
+fte_status fte_reset(fte_ctx *ctx, void *stream);
+
+/* Record a HIP event pair around every step-kernel launch (on the stream the
+ * launch uses); fte_get_stats then reports their summed duration. */
+fte_status fte_set_timing(fte_ctx *ctx, int enable);
 
 /* Launch shape: threads per block (64..1024, multiple of 64), steps per
  * kernel launch, and retired-particle removal every `compact_every` steps (a

@@ -38,6 +38,11 @@ struct fte_ctx {
     uint64_t global_step = 0;
     int block = 256, spl = 64, compact_every = 512;
     uint64_t since_compact = 0;
+    bool timing = false;
+    std::vector<hipEvent_t> tev;   // pairs: start, stop of each timed launch
+    size_t tev_used = 0;
+    double timed_ms = 0.0;
+    uint32_t timed_launches = 0;
     std::string err;
 };
 
@@ -320,6 +325,7 @@ fte_status fte_create(fte_ctx **out, const fte_params *p) {
 void fte_destroy(fte_ctx *c) {
     if (!c) return;
     if (c->ev) (void)hipEventDestroy(c->ev);
+    for (auto e : c->tev) (void)hipEventDestroy(e);
     if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;
 }
@@ -468,6 +474,26 @@ static fte_status refresh_exact(fte_ctx *c, hipStream_t s) {
     return FTE_OK;
 }
 
+// Sum the durations of the recorded launch pairs (waits for them).
+static fte_status drain_timing(fte_ctx *c, hipStream_t s) {
+    if (c->tev.empty()) {
+        c->tev.resize(512);
+        for (auto &e : c->tev) HIPCHK(c, hipEventCreate(&e));
+        c->tev_used = 0;
+        return FTE_OK;
+    }
+    if (c->tev_used == 0) return FTE_OK;
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (size_t k = 0; k + 1 < c->tev_used; k += 2) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->tev[k], c->tev[k + 1]));
+        c->timed_ms += ms;
+        c->timed_launches += 1;
+    }
+    c->tev_used = 0;
+    return FTE_OK;
+}
+
 fte_status fte_inject(fte_ctx *c, const fte_injection *inj, uint64_t n, uint64_t first_pid, void *stream) {
     if (!c) return FTE_EINVAL;
     if (!c->loaded) return fail(c, FTE_ESTATE, "load the grid before injecting");
@@ -515,8 +541,19 @@ fte_status fte_step_n(fte_ctx *c, uint32_t n_steps, void *stream) {
             c->pending = false;
         }
         const uint32_t chunk = left < (uint32_t)c->spl ? left : (uint32_t)c->spl;
+        if (c->timing) {
+            if (c->tev_used + 2 > c->tev.size()) {
+                fte_status r = drain_timing(c, s);
+                if (r != FTE_OK) return r;
+            }
+            HIPCHK(c, hipEventRecord(c->tev[c->tev_used], s));
+        }
         HIPCHK(c, launch_step(c->dp, c->dg, c->st[c->cur], c->cnt, c->cur, (double *)c->b.hist, c->global_step,
                               chunk, c->n_upper, c->block, c->p.precision == FTE_MIXED, s));
+        if (c->timing) {
+            HIPCHK(c, hipEventRecord(c->tev[c->tev_used + 1], s));
+            c->tev_used += 2;
+        }
         c->global_step += chunk;
         left -= chunk;
         c->since_compact += chunk;
@@ -571,6 +608,10 @@ fte_status fte_get_stats(fte_ctx *c, fte_stats *out, void *stream) {
     if (!c || !out) return FTE_EINVAL;
     if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
     hipStream_t s = (hipStream_t)stream;
+    if (c->timing) {
+        fte_status r = drain_timing(c, s);
+        if (r != FTE_OK) return r;
+    }
     DevCounters h;
     HIPCHK(c, hipMemcpyAsync(&h, c->cnt, sizeof(h), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
@@ -587,6 +628,39 @@ fte_status fte_get_stats(fte_ctx *c, fte_stats *out, void *stream) {
     }
     out->global_step = c->global_step;
     out->device_flags = h.flags;
+    out->step_launches = c->timed_launches;
+    out->step_kernel_ms = c->timed_ms;
+    return FTE_OK;
+}
+
+fte_status fte_reset(fte_ctx *c, void *stream) {
+    if (!c) return FTE_EINVAL;
+    if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, launch_zero_counters(c->cnt, s));
+    if (c->hist_n) HIPCHK(c, launch_zero((double *)c->b.hist, c->hist_n, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    c->cur = 0;
+    c->n_upper = 0;
+    c->injected_since = 0;
+    c->pending = false;
+    c->global_step = 0;
+    c->since_compact = 0;
+    c->tev_used = 0;
+    c->timed_ms = 0.0;
+    c->timed_launches = 0;
+    return FTE_OK;
+}
+
+fte_status fte_set_timing(fte_ctx *c, int enable) {
+    if (!c) return FTE_EINVAL;
+    if (c->tev_used) return fail(c, FTE_ESTATE, "read the stats before switching timing");
+    c->timing = enable != 0;
+    if (c->timing && c->tev.empty()) {
+        c->tev.resize(512);
+        for (auto &e : c->tev) HIPCHK(c, hipEventCreate(&e));
+    }
     return FTE_OK;
 }
 

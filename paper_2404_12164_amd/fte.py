@@ -26,7 +26,7 @@ RECORD_FIELDS = 13
 STATUS = {"active": 0, "absorbed_in": 1, "absorbed_out": 2, "out_of_domain": 3, "numeric": 4}
 SYMBOLS = ["fte_create", "fte_destroy", "fte_last_error", "fte_query_sizes", "fte_bind_buffers", "fte_load_grid",
            "fte_inject", "fte_step_n", "fte_bin_observers", "fte_read_hist", "fte_get_stats", "fte_read_particles",
-           "fte_set_launch"]
+           "fte_set_launch", "fte_reset", "fte_set_timing"]
 
 
 class fte_observer(C.Structure):
@@ -74,7 +74,8 @@ class fte_buffers(C.Structure):
 class fte_stats(C.Structure):
     _fields_ = [("n_live", C.c_uint64), ("n_injected", C.c_uint64), ("particle_steps", C.c_uint64),
                 ("n_retired", C.c_uint64 * 5), ("w_injected", C.c_double), ("w_retired", C.c_double * 5),
-                ("global_step", C.c_uint64), ("device_flags", C.c_uint32)]
+                ("global_step", C.c_uint64), ("device_flags", C.c_uint32), ("step_launches", C.c_uint32),
+                ("step_kernel_ms", C.c_double)]
 
 
 _lib = None
@@ -105,6 +106,8 @@ def lib():
         L.fte_read_particles.argtypes = [vp, dp, dp, dp, dp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32),
                                          C.POINTER(C.c_int32), u64, C.POINTER(C.c_uint64), vp]
         L.fte_set_launch.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+        L.fte_reset.argtypes = [vp, vp]
+        L.fte_set_timing.argtypes = [vp, C.c_int]
         for name in SYMBOLS:
             if name not in ("fte_destroy", "fte_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -291,6 +294,14 @@ def fte_set_launch(ctx, block: int, steps_per_launch: int, compact_every: int):
     _check(ctx, lib().fte_set_launch(ctx, int(block), int(steps_per_launch), int(compact_every)))
 
 
+def fte_reset(ctx, stream: int):
+    _check(ctx, lib().fte_reset(ctx, C.c_void_p(stream)))
+
+
+def fte_set_timing(ctx, enable: bool):
+    _check(ctx, lib().fte_set_timing(ctx, int(bool(enable))))
+
+
 # ----------------------------------------------------------------------------
 # convenience: a context with torch-owned device buffers
 # ----------------------------------------------------------------------------
@@ -343,6 +354,12 @@ class Simulation:
 
     def set_launch(self, block=256, steps_per_launch=64, compact_every=512):
         fte_set_launch(self.ctx, block, steps_per_launch, compact_every)
+
+    def reset(self):
+        fte_reset(self.ctx, self.stream)
+
+    def set_timing(self, enable=True):
+        fte_set_timing(self.ctx, enable)
 
     def inject(self, inj: dict, n: int, first_pid: int):
         fte_inject(self.ctx, inj, n, first_pid, self.stream)
