@@ -58,7 +58,7 @@ def read_traffic(name, algo_bytes_per_launch):
 class Run:
     """One context on the workload plus its lazy continuous-injection plan."""
 
-    def __init__(self, F, cfg, raw, precision, block, spl, compact):
+    def __init__(self, F, cfg, raw, precision, block, spl, compact, sort=1):
         import torch
         self.torch = torch
         self.cfg = cfg
@@ -71,7 +71,7 @@ class Run:
         t = time.time()
         self.sim.load_grid(raw)
         self.load_s = time.time() - t
-        self.sim.set_launch(block, spl, compact)
+        self.sim.set_launch(block, spl, compact, sort)
         self.sim.set_timing(True)
         self.injected = 0
         self.n0 = 0
@@ -153,6 +153,7 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--spl", type=int, default=64)
     ap.add_argument("--compact", type=int, default=512)
+    ap.add_argument("--sort", type=int, default=1)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-pids", type=int, default=4000)
@@ -193,7 +194,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    run = Run(F, cfg, raw, args.precision, args.block, args.spl, args.compact)
+    run = Run(F, cfg, raw, args.precision, args.block, args.spl, args.compact, args.sort)
     log(f"grid loaded in {run.load_s:.2f} s")
     if args.warmup > 0:
         for _ in range(args.warmup):
@@ -228,7 +229,7 @@ def main():
     extra = {}
     if not args.no_fp64 and args.precision == "mixed":
         log("FP64 path on the same workload")
-        r64 = Run(F, cfg, raw, "fp64", args.block, args.spl, args.compact)
+        r64 = Run(F, cfg, raw, "fp64", args.block, args.spl, args.compact, args.sort)
         res64 = timed(r64, args.steps, args.chunk)
         r64.close()
         del r64
@@ -260,7 +261,7 @@ def main():
         "config": {"workload": cfg["name"], "particles": args.particles, "global_steps": args.steps * args.chunk,
                    "chunk": args.chunk, "snapshots": g["n_snap"], "leaves": int(len(g["leaves"])),
                    "levels": g["n_levels"], "precision": args.precision, "block": args.block,
-                   "steps_per_launch": args.spl, "compact_every": args.compact},
+                   "steps_per_launch": args.spl, "compact_every": args.compact, "spatial_sort": args.sort},
         "roofline": roof,
         "cpu_baseline": cpu,
         "particle_steps": res["particle_steps"],

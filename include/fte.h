@@ -259,10 +259,13 @@ fte_status fte_reset(fte_ctx *ctx, void *stream);
  * launch uses); fte_get_stats then reports their summed duration. */
 fte_status fte_set_timing(fte_ctx *ctx, int enable);
 
-/* Launch shape: threads per block (64..1024, multiple of 64), steps per
- * kernel launch, and retired-particle removal every `compact_every` steps (a
- * multiple of steps_per_launch; 0 = never).  Defaults 256 / 64 / 512. */
-fte_status fte_set_launch(fte_ctx *ctx, int block, int steps_per_launch, int compact_every);
+/* Launch shape: threads per block (64..256, multiple of 64), steps per
+ * kernel launch, removal of retired particles every `compact_every` steps (a
+ * multiple of steps_per_launch; 0 = never), and whether that removal also
+ * regroups the live particles by (leaf, 2x2x2-cell sub-block) so that a
+ * wavefront gathers from neighbouring records (1) or keeps their order (0).
+ * Defaults 256 / 64 / 512 / 1. */
+fte_status fte_set_launch(fte_ctx *ctx, int block, int steps_per_launch, int compact_every, int spatial_sort);
 
 #ifdef __cplusplus
 }

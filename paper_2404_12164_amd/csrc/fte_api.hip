@@ -30,6 +30,9 @@ struct fte_ctx {
     int cur = 0;
     DevCounters *cnt = nullptr;
     double *fin_j = nullptr, *fin_s = nullptr, *cart = nullptr;
+    uint32_t *keys = nullptr, *counts = nullptr;
+    uint32_t n_keys = 0;
+    int sort = 1;
     uint64_t hist_n = 0;
     uint64_t n_upper = 0, injected_since = 0;
     unsigned long long *pinned = nullptr;
@@ -188,7 +191,8 @@ size_t rec_elem(const fte_params *p) { return p->precision == FTE_FP64 ? 8 : 4; 
 struct Layout {
     size_t grid, index, state, hist, work;
     size_t off_child, off_info;
-    size_t off_j, off_s, off_cart;
+    size_t off_j, off_s, off_cart, off_keys, off_counts;
+    uint32_t n_keys;
     int pcells;
 };
 
@@ -205,7 +209,10 @@ Layout layout(const fte_params *p, const fte_grid_desc *g, uint64_t n_max, size_
     L.off_j = align256(sizeof(DevCounters));
     L.off_s = L.off_j + align256(std::max<size_t>(nbins, 1) * 8);
     L.off_cart = L.off_s + align256(std::max<size_t>(nbins, 1) * 8);
-    L.work = L.off_cart + align256((size_t)g->n_leaves * L.pcells * 6 * 8);
+    L.off_keys = L.off_cart + align256((size_t)g->n_leaves * L.pcells * 6 * 8);
+    L.n_keys = (uint32_t)((size_t)g->n_leaves * (g->bx[0] / 2) * (g->bx[1] / 2) * (g->bx[2] / 2));
+    L.off_counts = L.off_keys + align256(n_max * 4);
+    L.work = L.off_counts + align256(((size_t)L.n_keys + 1) * 4);
     return L;
 }
 
@@ -373,6 +380,9 @@ fte_status fte_bind_buffers(fte_ctx *c, const fte_grid_desc *g, uint64_t n_max, 
     c->fin_j = (double *)(w + L.off_j);
     c->fin_s = (double *)(w + L.off_s);
     c->cart = (double *)(w + L.off_cart);
+    c->keys = (uint32_t *)(w + L.off_keys);
+    c->counts = (uint32_t *)(w + L.off_counts);
+    c->n_keys = L.n_keys;
     c->hist_n = (uint64_t)c->p.n_obs * c->p.n_e * c->p.n_t * c->p.n_batch;
 
     DevGrid &d = c->dg;
@@ -559,8 +569,13 @@ fte_status fte_step_n(fte_ctx *c, uint32_t n_steps, void *stream) {
         c->since_compact += chunk;
         if (c->compact_every > 0 && c->since_compact >= (uint64_t)c->compact_every) {
             const int to = 1 - c->cur;
-            HIPCHK(c, launch_zero_live(c->cnt, to, s));
-            HIPCHK(c, launch_compact(c->st[c->cur], c->st[to], c->cnt, c->cur, c->n_upper, 256, s));
+            if (c->sort) {
+                HIPCHK(c, launch_compact_sorted(c->dg, c->st[c->cur], c->st[to], c->cnt, c->cur, c->n_upper, c->keys,
+                                                c->counts, c->n_keys, s));
+            } else {
+                HIPCHK(c, launch_zero_live(c->cnt, to, s));
+                HIPCHK(c, launch_compact(c->st[c->cur], c->st[to], c->cnt, c->cur, c->n_upper, 256, s));
+            }
             c->cur = to;
             c->since_compact = 0;
             HIPCHK(c, hipMemcpyAsync(c->pinned, &c->cnt->n_live[to], sizeof(unsigned long long),
@@ -697,15 +712,17 @@ fte_status fte_read_particles(fte_ctx *c, double *x3, double *mu, double *lnp, d
     return FTE_OK;
 }
 
-fte_status fte_set_launch(fte_ctx *c, int block, int steps_per_launch, int compact_every) {
+fte_status fte_set_launch(fte_ctx *c, int block, int steps_per_launch, int compact_every, int spatial_sort) {
     if (!c) return FTE_EINVAL;
     if (block < 64 || block > 256 || (block & 63)) return fail(c, FTE_EINVAL, "block must be 64..256, multiple of 64");
     if (steps_per_launch < 1) return fail(c, FTE_EINVAL, "steps_per_launch must be >= 1");
     if (compact_every < 0 || (compact_every && compact_every % steps_per_launch))
         return fail(c, FTE_EINVAL, "compact_every must be a multiple of steps_per_launch");
+    if (spatial_sort != 0 && spatial_sort != 1) return fail(c, FTE_EINVAL, "spatial_sort must be 0 or 1");
     c->block = block;
     c->spl = steps_per_launch;
     c->compact_every = compact_every;
+    c->sort = spatial_sort;
     return FTE_OK;
 }
 

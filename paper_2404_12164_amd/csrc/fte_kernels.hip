@@ -420,41 +420,24 @@ __device__ __forceinline__ void grid_coords<float>(const DevGrid &G, double r, f
     s[2] = (ph - (float)G.ph_lo) * (float)G.inv_dph;
 }
 
-// Locate the leaf holding level-1 coordinates s and gather + interpolate the
-// records (trilinear in space, linear in time between snapshots k and k+1).
-template <typename R, bool KPERP>
-__device__ __forceinline__ bool gather(const DevGrid &G, R s[3], int ks, R alpha, R acc[kNF]) {
-    constexpr int NF = KPERP ? 13 : 10;
-    // fold into the domain
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        const R n = (R)G.n1[a];
-        s[a] = (s[a] >= (R)0) ? (s[a] > n ? n : s[a]) : (R)0;   // NaN -> 0
-    }
-    {
-        const R n = (R)G.n1[2];
-        if (G.periodic) {
-            if (s[2] >= n) s[2] -= n;
-            if (s[2] < (R)0) s[2] += n;
-            if (!(s[2] >= (R)0 && s[2] < n)) s[2] = (R)0;
-        } else {
-            s[2] = (s[2] >= (R)0) ? (s[2] > n ? n : s[2]) : (R)0;
-        }
-    }
-    // descend the block index
-    int B[3];
+// Walk the block index from level 1 down to the leaf that holds the folded
+// level-1 coordinates s.  S receives the coordinates in cells of the leaf's
+// level and B the leaf's block index; returns the leaf id or -1.
+template <typename R>
+__device__ __forceinline__ int descend(const DevGrid &G, const R s[3], R S[3], int B[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         int c = (int)M<R>::floor_(s[a]);
         c = c > G.n1[a] - 1 ? G.n1[a] - 1 : c;
         B[a] = c / G.bx[a];
+        S[a] = s[a];
     }
     int node = G.base[B[0] + G.nb1[0] * (B[1] + G.nb1[1] * B[2])];
     int L = 1;
-    R S[3] = {s[0], s[1], s[2]};
     while (node < 0) {
         const int grp = -node - 1;
         ++L;
+        if (L > G.n_levels) return -1;
         int slot = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -466,9 +449,39 @@ __device__ __forceinline__ bool gather(const DevGrid &G, R s[3], int ks, R alpha
             slot |= (B[a] & 1) << a;
         }
         node = G.child[grp * 8 + slot];
-        if (L >= G.n_levels && node < 0) return false;
     }
-    const int leaf = node;
+    return node;
+}
+
+// Fold level-1 coordinates into the domain: clamp xi and theta (NaN -> 0),
+// wrap a periodic phi.
+template <typename R>
+__device__ __forceinline__ void fold_s(const DevGrid &G, R s[3]) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const R n = (R)G.n1[a];
+        s[a] = (s[a] >= (R)0) ? (s[a] > n ? n : s[a]) : (R)0;
+    }
+    const R n = (R)G.n1[2];
+    if (G.periodic) {
+        if (s[2] >= n) s[2] -= n;
+        if (s[2] < (R)0) s[2] += n;
+        if (!(s[2] >= (R)0 && s[2] < n)) s[2] = (R)0;
+    } else {
+        s[2] = (s[2] >= (R)0) ? (s[2] > n ? n : s[2]) : (R)0;
+    }
+}
+
+// Locate the leaf holding level-1 coordinates s and gather + interpolate the
+// records (trilinear in space, linear in time between snapshots k and k+1).
+template <typename R, bool KPERP>
+__device__ __forceinline__ bool gather(const DevGrid &G, R s[3], int ks, R alpha, R acc[kNF]) {
+    constexpr int NF = KPERP ? 13 : 10;
+    fold_s<R>(G, s);
+    int B[3];
+    R S[3];
+    const int leaf = descend<R>(G, s, S, B);
+    if (leaf < 0) return false;
     // local cell relative to the first centre of the block, padded index
     int i[3];
     R f[3];
@@ -790,6 +803,107 @@ hipError_t launch_compact(DevState src, DevState dst, DevCounters *cnt, int from
                           hipStream_t s) {
     if (n_upper == 0) return hipSuccess;
     hipLaunchKernelGGL(k_compact, dim3(blocks_for(n_upper, block)), dim3(block), 0, s, src, dst, cnt, from);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// compaction with a spatial counting sort: live particles are regrouped by
+// (leaf, 2x2x2-cell sub-block) so that a wavefront gathers from neighbouring
+// records; order inside a key is arbitrary (results depend only on pid).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t cell_key(const DevGrid &G, double x, double y, double z) {
+    const double r = ::sqrt(x * x + y * y + z * z);
+    double s[3];
+    grid_coords<double>(G, r, ::acos(z / r), ::atan2(y, x) < 0.0 ? ::atan2(y, x) + 2.0 * kPi : ::atan2(y, x), s);
+    fold_s<double>(G, s);
+    double S[3];
+    int B[3];
+    const int leaf = descend<double>(G, s, S, B);
+    if (leaf < 0) return 0u;
+    int sub[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int l = (int)::floor(S[a]) - B[a] * G.bx[a];
+        l = l < 0 ? 0 : (l > G.bx[a] - 1 ? G.bx[a] - 1 : l);
+        sub[a] = l >> 1;
+    }
+    const int h0 = G.bx[0] >> 1, h1 = G.bx[1] >> 1;
+    const uint32_t nsub = (uint32_t)h0 * h1 * (G.bx[2] >> 1);
+    return (uint32_t)leaf * nsub + (uint32_t)(sub[0] + h0 * (sub[1] + h1 * sub[2]));
+}
+
+__global__ void k_sort_key(DevGrid G, DevState src, const DevCounters *cnt, int from, uint32_t *keys,
+                           uint32_t *counts) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt->n_live[from]) return;
+    if (src.status[i] != FTE_PS_ACTIVE) {
+        keys[i] = 0xFFFFFFFFu;
+        return;
+    }
+    const uint32_t k = cell_key(G, src.x[i], src.y[i], src.z[i]);
+    keys[i] = k;
+    atomicAdd(&counts[k], 1u);
+}
+
+// Exclusive scan of counts[0..nk) in one workgroup; the total becomes the
+// destination's live count.
+__global__ void __launch_bounds__(1024) k_sort_scan(uint32_t *counts, uint32_t nk, DevCounters *cnt, int to) {
+    __shared__ unsigned long long part[1024];
+    const uint32_t t = threadIdx.x, nt = blockDim.x;
+    const uint32_t chunk = (nk + nt - 1) / nt;
+    const uint32_t lo = t * chunk, hi = lo + chunk < nk ? lo + chunk : nk;
+    unsigned long long sum = 0;
+    for (uint32_t k = lo; k < hi; ++k) sum += counts[k];
+    part[t] = sum;
+    __syncthreads();
+    for (uint32_t off = 1; off < nt; off <<= 1) {
+        const unsigned long long v = t >= off ? part[t - off] : 0ull;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    unsigned long long run = part[t] - sum;   // exclusive prefix of this chunk
+    for (uint32_t k = lo; k < hi; ++k) {
+        const uint32_t c = counts[k];
+        counts[k] = (uint32_t)run;
+        run += c;
+    }
+    if (t == nt - 1) cnt->n_live[to] = part[t];
+}
+
+__global__ void k_sort_scatter(DevState src, DevState dst, const DevCounters *cnt, int from, const uint32_t *keys,
+                               uint32_t *cursor) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt->n_live[from]) return;
+    const uint32_t k = keys[i];
+    if (k == 0xFFFFFFFFu) return;
+    const uint64_t j = atomicAdd(&cursor[k], 1u);
+    dst.x[j] = src.x[i];
+    dst.y[j] = src.y[i];
+    dst.z[j] = src.z[i];
+    dst.mu[j] = src.mu[i];
+    dst.lnp[j] = src.lnp[i];
+    dst.w[j] = src.w[i];
+    dst.pid[j] = src.pid[i];
+    dst.kinj[j] = src.kinj[i];
+    dst.status[j] = FTE_PS_ACTIVE;
+}
+
+__global__ void k_zero_u32(uint32_t *p, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_compact_sorted(const DevGrid &g, DevState src, DevState dst, DevCounters *cnt, int from,
+                                 uint64_t n_upper, uint32_t *keys, uint32_t *counts, uint32_t nk, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(blocks_for(nk, 256)), dim3(256), 0, s, counts, nk);
+    if (n_upper > 0)
+        hipLaunchKernelGGL(k_sort_key, dim3(blocks_for(n_upper, 256)), dim3(256), 0, s, g, src, cnt, from, keys,
+                           counts);
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, counts, nk, cnt, 1 - from);
+    if (n_upper > 0)
+        hipLaunchKernelGGL(k_sort_scatter, dim3(blocks_for(n_upper, 256)), dim3(256), 0, s, src, dst, cnt, from, keys,
+                           counts);
     return hipGetLastError();
 }
 

@@ -105,7 +105,7 @@ def lib():
         L.fte_get_stats.argtypes = [vp, C.POINTER(fte_stats), vp]
         L.fte_read_particles.argtypes = [vp, dp, dp, dp, dp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32),
                                          C.POINTER(C.c_int32), u64, C.POINTER(C.c_uint64), vp]
-        L.fte_set_launch.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+        L.fte_set_launch.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
         L.fte_reset.argtypes = [vp, vp]
         L.fte_set_timing.argtypes = [vp, C.c_int]
         for name in SYMBOLS:
@@ -290,8 +290,8 @@ def fte_read_particles(ctx, cap: int, stream: int) -> dict:
     return dict(x=x[:k], mu=mu[:k], lnp=lnp[:k], w=w[:k], pid=pid[:k], kinj=kinj[:k], status=status[:k])
 
 
-def fte_set_launch(ctx, block: int, steps_per_launch: int, compact_every: int):
-    _check(ctx, lib().fte_set_launch(ctx, int(block), int(steps_per_launch), int(compact_every)))
+def fte_set_launch(ctx, block: int, steps_per_launch: int, compact_every: int, spatial_sort: int = 1):
+    _check(ctx, lib().fte_set_launch(ctx, int(block), int(steps_per_launch), int(compact_every), int(spatial_sort)))
 
 
 def fte_reset(ctx, stream: int):
@@ -352,8 +352,8 @@ class Simulation:
         fte_load_grid(self.ctx, vb.data_ptr(), self.stream)
         del vb
 
-    def set_launch(self, block=256, steps_per_launch=64, compact_every=512):
-        fte_set_launch(self.ctx, block, steps_per_launch, compact_every)
+    def set_launch(self, block=256, steps_per_launch=64, compact_every=512, spatial_sort=1):
+        fte_set_launch(self.ctx, block, steps_per_launch, compact_every, spatial_sort)
 
     def reset(self):
         fte_reset(self.ctx, self.stream)

@@ -208,12 +208,15 @@ def test_launch_shape_invariance(F, torch_cuda):
     raw = W.make_raw(g, cfg["wind"])
     injs = [(dict(cfg["injection"], n_total=3001), 3001, 0)]
     a, sa, _, _ = gpu_run(F, torch_cuda, p, g, raw, injs, 240, launch=(256, 64, 0))
-    b, sb, _, _ = gpu_run(F, torch_cuda, p, g, raw, injs, 240, launch=(64, 1, 7), step_chunks=[13, 100, 127])
-    ma, mb = a["status"] == 0, b["status"] == 0
-    oa, ob = np.argsort(a["pid"][ma]), np.argsort(b["pid"][mb])
-    for k in ("x", "mu", "lnp", "pid"):
-        assert np.array_equal(a[k][ma][oa], b[k][mb][ob])
-    assert np.allclose(sa, sb, rtol=1e-12, atol=0)
+    ma = a["status"] == 0
+    oa = np.argsort(a["pid"][ma])
+    for launch, chunks in (((64, 1, 7, 1), [13, 100, 127]), ((128, 8, 16, 0), [240]), ((192, 5, 15, 1), [1, 239])):
+        b, sb, _, _ = gpu_run(F, torch_cuda, p, g, raw, injs, 240, launch=launch, step_chunks=chunks)
+        mb = b["status"] == 0
+        ob = np.argsort(b["pid"][mb])
+        for k in ("x", "mu", "lnp", "pid"):
+            assert np.array_equal(a[k][ma][oa], b[k][mb][ob]), (launch, k)
+        assert np.allclose(sa, sb, rtol=1e-12, atol=0)
 
 
 def test_edge_cases(F, torch_cuda):
