@@ -262,9 +262,9 @@ fte_status fte_set_timing(fte_ctx *ctx, int enable);
 /* Launch shape: threads per block (64..256, multiple of 64), steps per
  * kernel launch, removal of retired particles every `compact_every` steps (a
  * multiple of steps_per_launch; 0 = never), and whether that removal also
- * regroups the live particles by (leaf, 2x2x2-cell sub-block) so that a
- * wavefront gathers from neighbouring records (1) or keeps their order (0).
- * Defaults 256 / 64 / 512 / 1. */
+ * regroups the live particles by leaf and cube of cells so that a wavefront
+ * gathers from neighbouring records: spatial_sort 0 keeps the storage order,
+ * 1, 2, 3 sort by cubes of 1, 2, 4 cells per edge.  Defaults 256 / 32 / 128 / 2. */
 fte_status fte_set_launch(fte_ctx *ctx, int block, int steps_per_launch, int compact_every, int spatial_sort);
 
 #ifdef __cplusplus

@@ -30,16 +30,16 @@ struct fte_ctx {
     int cur = 0;
     DevCounters *cnt = nullptr;
     double *fin_j = nullptr, *fin_s = nullptr, *cart = nullptr;
-    uint32_t *keys = nullptr, *counts = nullptr;
+    uint32_t *keys = nullptr, *counts = nullptr, *tsum = nullptr;
     uint32_t n_keys = 0;
-    int sort = 1;
+    int sort = 2;
     uint64_t hist_n = 0;
     uint64_t n_upper = 0, injected_since = 0;
     unsigned long long *pinned = nullptr;
     hipEvent_t ev = nullptr;
     bool pending = false;
     uint64_t global_step = 0;
-    int block = 256, spl = 64, compact_every = 512;
+    int block = 256, spl = 32, compact_every = 128;
     uint64_t since_compact = 0;
     bool timing = false;
     std::vector<hipEvent_t> tev;   // pairs: start, stop of each timed launch
@@ -191,7 +191,7 @@ size_t rec_elem(const fte_params *p) { return p->precision == FTE_FP64 ? 8 : 4; 
 struct Layout {
     size_t grid, index, state, hist, work;
     size_t off_child, off_info;
-    size_t off_j, off_s, off_cart, off_keys, off_counts;
+    size_t off_j, off_s, off_cart, off_keys, off_counts, off_tsum;
     uint32_t n_keys;
     int pcells;
 };
@@ -210,9 +210,10 @@ Layout layout(const fte_params *p, const fte_grid_desc *g, uint64_t n_max, size_
     L.off_s = L.off_j + align256(std::max<size_t>(nbins, 1) * 8);
     L.off_cart = L.off_s + align256(std::max<size_t>(nbins, 1) * 8);
     L.off_keys = L.off_cart + align256((size_t)g->n_leaves * L.pcells * 6 * 8);
-    L.n_keys = (uint32_t)((size_t)g->n_leaves * (g->bx[0] / 2) * (g->bx[1] / 2) * (g->bx[2] / 2));
+    L.n_keys = (uint32_t)((size_t)g->n_leaves * g->bx[0] * g->bx[1] * g->bx[2]);   // finest sort key
     L.off_counts = L.off_keys + align256(n_max * 4);
-    L.work = L.off_counts + align256(((size_t)L.n_keys + 1) * 4);
+    L.off_tsum = L.off_counts + align256(((size_t)L.n_keys + 1) * 4);
+    L.work = L.off_tsum + align256(((size_t)L.n_keys / 4096 + 2) * 4);
     return L;
 }
 
@@ -382,6 +383,7 @@ fte_status fte_bind_buffers(fte_ctx *c, const fte_grid_desc *g, uint64_t n_max, 
     c->cart = (double *)(w + L.off_cart);
     c->keys = (uint32_t *)(w + L.off_keys);
     c->counts = (uint32_t *)(w + L.off_counts);
+    c->tsum = (uint32_t *)(w + L.off_tsum);
     c->n_keys = L.n_keys;
     c->hist_n = (uint64_t)c->p.n_obs * c->p.n_e * c->p.n_t * c->p.n_batch;
 
@@ -570,8 +572,8 @@ fte_status fte_step_n(fte_ctx *c, uint32_t n_steps, void *stream) {
         if (c->compact_every > 0 && c->since_compact >= (uint64_t)c->compact_every) {
             const int to = 1 - c->cur;
             if (c->sort) {
-                HIPCHK(c, launch_compact_sorted(c->dg, c->st[c->cur], c->st[to], c->cnt, c->cur, c->n_upper, c->keys,
-                                                c->counts, c->n_keys, s));
+                HIPCHK(c, launch_compact_sorted(c->dg, c->sort, c->st[c->cur], c->st[to], c->cnt, c->cur, c->n_upper,
+                                                c->keys, c->counts, c->tsum, s));
             } else {
                 HIPCHK(c, launch_zero_live(c->cnt, to, s));
                 HIPCHK(c, launch_compact(c->st[c->cur], c->st[to], c->cnt, c->cur, c->n_upper, 256, s));
@@ -718,7 +720,10 @@ fte_status fte_set_launch(fte_ctx *c, int block, int steps_per_launch, int compa
     if (steps_per_launch < 1) return fail(c, FTE_EINVAL, "steps_per_launch must be >= 1");
     if (compact_every < 0 || (compact_every && compact_every % steps_per_launch))
         return fail(c, FTE_EINVAL, "compact_every must be a multiple of steps_per_launch");
-    if (spatial_sort != 0 && spatial_sort != 1) return fail(c, FTE_EINVAL, "spatial_sort must be 0 or 1");
+    if (spatial_sort < 0 || spatial_sort > 3) return fail(c, FTE_EINVAL, "spatial_sort must be 0..3");
+    for (int a = 0; a < 3 && spatial_sort > 1; ++a)
+        if (c->bound && (c->g.bx[a] % (1 << (spatial_sort - 1))))
+            return fail(c, FTE_EINVAL, "sort cube must divide the block");
     c->block = block;
     c->spl = steps_per_launch;
     c->compact_every = compact_every;

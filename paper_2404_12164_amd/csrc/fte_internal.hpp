@@ -90,8 +90,9 @@ hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevCou
 hipError_t launch_compact(DevState src, DevState dst, DevCounters *cnt, int from, uint64_t n_upper, int block,
                           hipStream_t s);
 hipError_t launch_zero_live(DevCounters *cnt, int slot, hipStream_t s);
-hipError_t launch_compact_sorted(const DevGrid &g, DevState src, DevState dst, DevCounters *cnt, int from,
-                                 uint64_t n_upper, uint32_t *keys, uint32_t *counts, uint32_t nk, hipStream_t s);
+uint32_t sort_keys_for(const DevGrid &g, int sort);
+hipError_t launch_compact_sorted(const DevGrid &g, int sort, DevState src, DevState dst, DevCounters *cnt, int from,
+                                 uint64_t n_upper, uint32_t *keys, uint32_t *counts, uint32_t *tsum, hipStream_t s);
 hipError_t launch_finalize(const DevParams &p, const double *hist, const DevCounters *cnt, double *j, double *sig,
                            hipStream_t s);
 hipError_t launch_zero(double *p, uint64_t n, hipStream_t s);

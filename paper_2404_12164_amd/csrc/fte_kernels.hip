@@ -808,31 +808,34 @@ hipError_t launch_compact(DevState src, DevState dst, DevCounters *cnt, int from
 
 // ---------------------------------------------------------------------------
 // compaction with a spatial counting sort: live particles are regrouped by
-// (leaf, 2x2x2-cell sub-block) so that a wavefront gathers from neighbouring
-// records; order inside a key is arbitrary (results depend only on pid).
+// (leaf, cube of 2^(sort-1) cells per edge) so that a wavefront gathers from
+// neighbouring records; order inside a key is arbitrary (results depend only
+// on pid, not on storage order).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t cell_key(const DevGrid &G, double x, double y, double z) {
+__device__ __forceinline__ uint32_t cell_key(const DevGrid &G, int shift, double x, double y, double z) {
     const double r = ::sqrt(x * x + y * y + z * z);
-    double s[3];
-    grid_coords<double>(G, r, ::acos(z / r), ::atan2(y, x) < 0.0 ? ::atan2(y, x) + 2.0 * kPi : ::atan2(y, x), s);
-    fold_s<double>(G, s);
-    double S[3];
+    float ph = ::atan2f((float)y, (float)x);
+    if (ph < 0.f) ph += (float)(2.0 * kPi);
+    float s[3];
+    grid_coords<float>(G, r, ::acosf((float)(z / r)), ph, s);
+    fold_s<float>(G, s);
+    float S[3];
     int B[3];
-    const int leaf = descend<double>(G, s, S, B);
+    const int leaf = descend<float>(G, s, S, B);
     if (leaf < 0) return 0u;
     int sub[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        int l = (int)::floor(S[a]) - B[a] * G.bx[a];
+        int l = (int)::floorf(S[a]) - B[a] * G.bx[a];
         l = l < 0 ? 0 : (l > G.bx[a] - 1 ? G.bx[a] - 1 : l);
-        sub[a] = l >> 1;
+        sub[a] = l >> shift;
     }
-    const int h0 = G.bx[0] >> 1, h1 = G.bx[1] >> 1;
-    const uint32_t nsub = (uint32_t)h0 * h1 * (G.bx[2] >> 1);
+    const int h0 = G.bx[0] >> shift, h1 = G.bx[1] >> shift;
+    const uint32_t nsub = (uint32_t)h0 * h1 * (G.bx[2] >> shift);
     return (uint32_t)leaf * nsub + (uint32_t)(sub[0] + h0 * (sub[1] + h1 * sub[2]));
 }
 
-__global__ void k_sort_key(DevGrid G, DevState src, const DevCounters *cnt, int from, uint32_t *keys,
+__global__ void k_sort_key(DevGrid G, int shift, DevState src, const DevCounters *cnt, int from, uint32_t *keys,
                            uint32_t *counts) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cnt->n_live[from]) return;
@@ -840,35 +843,69 @@ __global__ void k_sort_key(DevGrid G, DevState src, const DevCounters *cnt, int 
         keys[i] = 0xFFFFFFFFu;
         return;
     }
-    const uint32_t k = cell_key(G, src.x[i], src.y[i], src.z[i]);
+    const uint32_t k = cell_key(G, shift, src.x[i], src.y[i], src.z[i]);
     keys[i] = k;
     atomicAdd(&counts[k], 1u);
 }
 
-// Exclusive scan of counts[0..nk) in one workgroup; the total becomes the
+// Exclusive scan of counts[0..nk) in three passes: tiles of 4096 scanned by
+// one workgroup each (tile totals to tsum), the tile totals by one
+// workgroup, then the tile offsets added back.  The total becomes the
 // destination's live count.
-__global__ void __launch_bounds__(1024) k_sort_scan(uint32_t *counts, uint32_t nk, DevCounters *cnt, int to) {
-    __shared__ unsigned long long part[1024];
-    const uint32_t t = threadIdx.x, nt = blockDim.x;
-    const uint32_t chunk = (nk + nt - 1) / nt;
-    const uint32_t lo = t * chunk, hi = lo + chunk < nk ? lo + chunk : nk;
-    unsigned long long sum = 0;
-    for (uint32_t k = lo; k < hi; ++k) sum += counts[k];
-    part[t] = sum;
+constexpr int kScanTile = 4096;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t *total) {
+    const int t = threadIdx.x, nt = blockDim.x;
+    sh[t] = v;
     __syncthreads();
-    for (uint32_t off = 1; off < nt; off <<= 1) {
-        const unsigned long long v = t >= off ? part[t - off] : 0ull;
+    for (int off = 1; off < nt; off <<= 1) {
+        const uint32_t a = t >= off ? sh[t - off] : 0u;
         __syncthreads();
-        part[t] += v;
+        sh[t] += a;
         __syncthreads();
     }
-    unsigned long long run = part[t] - sum;   // exclusive prefix of this chunk
-    for (uint32_t k = lo; k < hi; ++k) {
-        const uint32_t c = counts[k];
-        counts[k] = (uint32_t)run;
-        run += c;
+    const uint32_t incl = sh[t];
+    *total = sh[nt - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_tiles(uint32_t *counts, uint32_t nk, uint32_t *tsum) {
+    __shared__ uint32_t sh[1024];
+    const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * 4;
+    uint32_t c[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        c[q] = base + q < nk ? counts[base + q] : 0u;
+        sum += c[q];
     }
-    if (t == nt - 1) cnt->n_live[to] = part[t];
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(sum, sh, &tot);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (base + q < nk) counts[base + q] = run;
+        run += c[q];
+    }
+    if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_totals(uint32_t *tsum, uint32_t nt, DevCounters *cnt, int to) {
+    __shared__ uint32_t sh[1024];
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < nt; b0 += blockDim.x) {
+        const uint32_t k = b0 + threadIdx.x;
+        const uint32_t v = k < nt ? tsum[k] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan(v, sh, &tot);
+        if (k < nt) tsum[k] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) cnt->n_live[to] = carry;
+}
+
+__global__ void k_scan_add(uint32_t *counts, uint32_t nk, const uint32_t *tsum) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nk) counts[i] += tsum[i / kScanTile];
 }
 
 __global__ void k_sort_scatter(DevState src, DevState dst, const DevCounters *cnt, int from, const uint32_t *keys,
@@ -894,13 +931,22 @@ __global__ void k_zero_u32(uint32_t *p, uint32_t n) {
     if (i < n) p[i] = 0u;
 }
 
-hipError_t launch_compact_sorted(const DevGrid &g, DevState src, DevState dst, DevCounters *cnt, int from,
-                                 uint64_t n_upper, uint32_t *keys, uint32_t *counts, uint32_t nk, hipStream_t s) {
+uint32_t sort_keys_for(const DevGrid &g, int sort) {
+    const int sh = sort - 1;
+    return (uint32_t)g.n_leaves * (uint32_t)((g.bx[0] >> sh) * (g.bx[1] >> sh) * (g.bx[2] >> sh));
+}
+
+hipError_t launch_compact_sorted(const DevGrid &g, int sort, DevState src, DevState dst, DevCounters *cnt, int from,
+                                 uint64_t n_upper, uint32_t *keys, uint32_t *counts, uint32_t *tsum, hipStream_t s) {
+    const uint32_t nk = sort_keys_for(g, sort);
+    const uint32_t ntile = (nk + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_zero_u32, dim3(blocks_for(nk, 256)), dim3(256), 0, s, counts, nk);
     if (n_upper > 0)
-        hipLaunchKernelGGL(k_sort_key, dim3(blocks_for(n_upper, 256)), dim3(256), 0, s, g, src, cnt, from, keys,
-                           counts);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, counts, nk, cnt, 1 - from);
+        hipLaunchKernelGGL(k_sort_key, dim3(blocks_for(n_upper, 256)), dim3(256), 0, s, g, sort - 1, src, cnt, from,
+                           keys, counts);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(ntile), dim3(1024), 0, s, counts, nk, tsum);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, tsum, ntile, cnt, 1 - from);
+    hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(nk, 256)), dim3(256), 0, s, counts, nk, tsum);
     if (n_upper > 0)
         hipLaunchKernelGGL(k_sort_scatter, dim3(blocks_for(n_upper, 256)), dim3(256), 0, s, src, dst, cnt, from, keys,
                            counts);

@@ -290,7 +290,7 @@ def fte_read_particles(ctx, cap: int, stream: int) -> dict:
     return dict(x=x[:k], mu=mu[:k], lnp=lnp[:k], w=w[:k], pid=pid[:k], kinj=kinj[:k], status=status[:k])
 
 
-def fte_set_launch(ctx, block: int, steps_per_launch: int, compact_every: int, spatial_sort: int = 1):
+def fte_set_launch(ctx, block: int, steps_per_launch: int, compact_every: int, spatial_sort: int = 2):
     _check(ctx, lib().fte_set_launch(ctx, int(block), int(steps_per_launch), int(compact_every), int(spatial_sort)))
 
 
@@ -352,7 +352,7 @@ class Simulation:
         fte_load_grid(self.ctx, vb.data_ptr(), self.stream)
         del vb
 
-    def set_launch(self, block=256, steps_per_launch=64, compact_every=512, spatial_sort=1):
+    def set_launch(self, block=256, steps_per_launch=32, compact_every=128, spatial_sort=2):
         fte_set_launch(self.ctx, block, steps_per_launch, compact_every, spatial_sort)
 
     def reset(self):
