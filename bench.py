@@ -186,11 +186,12 @@ def main():
     log(f"wind generated on the GPU in {gen_s:.1f} s ({raw.numel() * 8 / 1e9:.1f} GB)")
 
     if args.calib_copy:
-        a = torch.empty(2 ** 28, dtype=torch.float64, device=dev)
+        # a plain streaming kernel of known traffic (reads 2 GiB, writes 2 GiB)
+        # for scaling the FETCH_SIZE / WRITE_SIZE counters
+        a = torch.ones(2 ** 28, dtype=torch.int64, device=dev)
         b = torch.empty_like(a)
-        a.fill_(1.0)
         torch.cuda.synchronize()
-        b.copy_(a)
+        torch.bitwise_not(a, out=b)
         torch.cuda.synchronize()
         del a, b
 

@@ -194,12 +194,14 @@ struct Layout {
     size_t off_j, off_s, off_cart, off_keys, off_counts, off_tsum;
     uint32_t n_keys;
     int pcells;
+    int rs;
 };
 
 Layout layout(const fte_params *p, const fte_grid_desc *g, uint64_t n_max, size_t n_base, size_t n_child) {
     Layout L{};
     L.pcells = (g->bx[0] + 2) * (g->bx[1] + 2) * (g->bx[2] + 2);
-    L.grid = (size_t)g->n_snap * g->n_leaves * L.pcells * kRS * rec_elem(p);
+    L.rs = (p->kperp_ratio > 0.0 || p->lambda_perp > 0.0) ? kRSKperp : kRSPlain;
+    L.grid = (size_t)g->n_snap * g->n_leaves * L.pcells * L.rs * rec_elem(p);
     L.off_child = align256(n_base * 4);
     L.off_info = L.off_child + align256(std::max<size_t>(n_child, 8) * 4);
     L.index = L.off_info + align256((size_t)g->n_leaves * 16);
@@ -422,6 +424,8 @@ fte_status fte_bind_buffers(fte_ctx *c, const fte_grid_desc *g, uint64_t n_max, 
     d.child = (const int32_t *)(ix + L.off_child);
     d.leaf_info = (const int32_t *)(ix + L.off_info);
     d.rec = b->grid;
+    d.rs = L.rs;
+    d.nf = L.rs == kRSKperp ? kNF : 10;
     c->bound = true;
     c->loaded = false;
     c->global_step = 0;

@@ -20,10 +20,11 @@ struct U4 {
 __device__ __forceinline__ U4 philox10(U4 ctr, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * ctr.a;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, ctr.a);
-        const uint32_t lo1 = 0xCD9E8D57u * ctr.c;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, ctr.c);
+        // one 32x32->64 multiply each (a single v_mad_u64_u32)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * ctr.a;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * ctr.c;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         U4 nx;
         nx.a = hi1 ^ ctr.b ^ k0;
         nx.b = lo1;
@@ -62,6 +63,8 @@ struct M<double> {
     static __device__ __forceinline__ double acos_(double x) { return ::acos(x); }
     static __device__ __forceinline__ double atan2_(double y, double x) { return ::atan2(y, x); }
     static __device__ __forceinline__ double floor_(double x) { return ::floor(x); }
+    // quotients in the double path stay correctly rounded
+    static __device__ __forceinline__ double div_(double a, double b) { return a / b; }
     static __device__ __forceinline__ double u01(uint32_t k) { return ((double)k + 0.5) * (1.0 / 4294967296.0); }
     // (cos, sin)(2 pi u)
     static __device__ __forceinline__ void cs2pi(double u, double *c, double *s) { ::sincospi(2.0 * u, s, c); }
@@ -76,6 +79,8 @@ struct M<float> {
     static __device__ __forceinline__ float acos_(float x) { return ::acosf(x); }
     static __device__ __forceinline__ float atan2_(float y, float x) { return ::atan2f(y, x); }
     static __device__ __forceinline__ float floor_(float x) { return ::floorf(x); }
+    // quotients in the float path: hardware reciprocal (1 ulp) times numerator
+    static __device__ __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
     // top 24 bits: strictly inside (0, 1) in float
     static __device__ __forceinline__ float u01(uint32_t k) { return ((float)(k >> 8) + 0.5f) * (1.0f / 16777216.0f); }
     // the hardware sine/cosine take their argument in revolutions

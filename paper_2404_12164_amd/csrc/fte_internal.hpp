@@ -9,8 +9,9 @@ namespace fte {
 
 constexpr double kC = 299792458.0;
 constexpr double kPi = 3.14159265358979323846;
-constexpr int kRS = FTE_RECORD_STRIDE;
 constexpr int kNF = FTE_RECORD_FIELDS;
+constexpr int kRSPlain = FTE_RECORD_STRIDE;       // fields 0-9
+constexpr int kRSKperp = FTE_RECORD_STRIDE_KPERP; // fields 0-12 + pad
 
 // Device-side copy of the run parameters, pre-digested on the host.
 struct DevParams {
@@ -45,7 +46,8 @@ struct DevGrid {
     const int32_t *base;         // [nb1 product] node codes (>=0 leaf, <0 -(group+1))
     const int32_t *child;        // [n_groups][8] node codes
     const int32_t *leaf_info;    // [n_leaves][4] level, I, J, K
-    const void *rec;             // records [snap][leaf][pcell][kRS]
+    const void *rec;             // records [snap][leaf][pcell][rs]
+    int rs, nf;                  // record stride and stored fields (10/10 or 14/13)
 };
 
 // Particle state (struct of arrays, capacity n_max).

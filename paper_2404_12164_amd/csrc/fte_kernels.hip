@@ -43,12 +43,12 @@ struct RawSrc {
     }
 };
 
-// records: [snap][leaf][pcell][kRS] of R, interior at padded offset +1
+// records: [snap][leaf][pcell][rs] of R, interior at padded offset +1
 template <typename R>
 struct RecSrc {
     const R *p;
     const int32_t *leaf_info;
-    int snap, n_leaves, pcells, px0, px1, bx0, bx1, bx2;
+    int snap, n_leaves, pcells, px0, px1, bx0, bx1, bx2, rs, nf;
     __device__ void mean_cube(int leaf, const int cm[3], int k, double out[kNF]) const {
         const int4 li = reinterpret_cast<const int4 *>(leaf_info)[leaf];
         const int l0 = cm[0] - li.y * bx0, l1 = cm[1] - li.z * bx1, l2 = cm[2] - li.w * bx2;
@@ -61,8 +61,8 @@ struct RecSrc {
             for (int c1 = 0; c1 < k; ++c1)
                 for (int c0 = 0; c0 < k; ++c0) {
                     const size_t pc = (l0 + c0 + 1) + (size_t)px0 * ((l1 + c1 + 1) + (size_t)px1 * (l2 + c2 + 1));
-                    const R *src = p + (((size_t)snap * n_leaves + leaf) * pcells + pc) * kRS;
-                    for (int q = 0; q < kNF; ++q) out[q] += (double)src[q];
+                    const R *src = p + (((size_t)snap * n_leaves + leaf) * pcells + pc) * rs;
+                    for (int q = 0; q < nf; ++q) out[q] += (double)src[q];
                 }
         const double inv = 1.0 / (double)(k * k * k);
         for (int q = 0; q < kNF; ++q) out[q] *= inv;
@@ -245,7 +245,7 @@ __global__ void k_derive(DevGrid G, const double *raw, int snap, const double *c
 
     const double *s = raw + (((size_t)snap * G.n_leaves + leaf) * G.cells + idx) * 6;
     const double Bn = ::sqrt(s[3] * s[3] + s[4] * s[4] + s[5] * s[5]);
-    R *out = rec + (((size_t)snap * G.n_leaves + leaf) * G.pcells + pc) * kRS;
+    R *out = rec + (((size_t)snap * G.n_leaves + leaf) * G.pcells + pc) * G.rs;
     out[0] = (R)s[0];
     out[1] = (R)s[1];
     out[2] = (R)s[2];
@@ -256,8 +256,9 @@ __global__ void k_derive(DevGrid G, const double *raw, int snap, const double *c
     out[7] = (R)bbgV;
     out[8] = (R)divb;
     out[9] = (R)bDV;
-    for (int a = 0; a < 3; ++a) out[10 + a] = (R)(curv[0] * e[a][0] + curv[1] * e[a][1] + curv[2] * e[a][2]);
-    for (int q = kNF; q < kRS; ++q) out[q] = (R)0;
+    if (G.nf > 10)
+        for (int a = 0; a < 3; ++a) out[10 + a] = (R)(curv[0] * e[a][0] + curv[1] * e[a][1] + curv[2] * e[a][2]);
+    for (int q = G.nf; q < G.rs; ++q) out[q] = (R)0;
 }
 
 // Ghost layer of the records by the block-boundary rule.
@@ -271,15 +272,15 @@ __global__ void k_record_ghost(DevGrid G, int snap, R *rec, DevCounters *cnt) {
     const bool interior = loc[0] >= 0 && loc[0] < G.bx[0] && loc[1] >= 0 && loc[1] < G.bx[1] && loc[2] >= 0 &&
                           loc[2] < G.bx[2];
     if (interior) return;
-    RecSrc<R> S{rec, G.leaf_info, snap, G.n_leaves, G.pcells, G.px[0], G.px[1], G.bx[0], G.bx[1], G.bx[2]};
+    RecSrc<R> S{rec, G.leaf_info, snap, G.n_leaves, G.pcells, G.px[0], G.px[1], G.bx[0], G.bx[1], G.bx[2], G.rs, G.nf};
     double v[kNF];
-    R *out = rec + (((size_t)snap * G.n_leaves + leaf) * G.pcells + pc) * kRS;
+    R *out = rec + (((size_t)snap * G.n_leaves + leaf) * G.pcells + pc) * G.rs;
     if (!virtual_value<kNF>(G, S, L, c, v)) {
         atomicOr(&cnt->flags, kFlagAmrDepth);
         for (int q = 0; q < kNF; ++q) v[q] = __builtin_nan("");
     }
-    for (int q = 0; q < kNF; ++q) out[q] = (R)v[q];
-    for (int q = kNF; q < kRS; ++q) out[q] = (R)0;
+    for (int q = 0; q < G.nf; ++q) out[q] = (R)v[q];
+    for (int q = G.nf; q < G.rs; ++q) out[q] = (R)0;
 }
 
 static inline unsigned blocks_for(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
@@ -477,6 +478,7 @@ __device__ __forceinline__ void fold_s(const DevGrid &G, R s[3]) {
 template <typename R, bool KPERP>
 __device__ __forceinline__ bool gather(const DevGrid &G, R s[3], int ks, R alpha, R acc[kNF]) {
     constexpr int NF = KPERP ? 13 : 10;
+    constexpr int RS = KPERP ? kRSKperp : kRSPlain;
     fold_s<R>(G, s);
     int B[3];
     R S[3];
@@ -500,12 +502,12 @@ __device__ __forceinline__ bool gather(const DevGrid &G, R s[3], int ks, R alpha
     const int nsn = G.n_snap >= 2 ? 2 : 1;
     for (int sn = 0; sn < nsn; ++sn) {
         const R ws = (G.n_snap >= 2) ? (sn == 0 ? (R)1 - alpha : alpha) : (R)1;
-        const R *base = rec + (((size_t)(ks + sn) * G.n_leaves + leaf) * G.pcells + pc) * kRS;
+        const R *base = rec + (((size_t)(ks + sn) * G.n_leaves + leaf) * G.pcells + pc) * RS;
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             const int e0 = d & 1, e1 = (d >> 1) & 1, e2 = (d >> 2) & 1;
             const R w = ws * (e0 ? f[0] : (R)1 - f[0]) * (e1 ? f[1] : (R)1 - f[1]) * (e2 ? f[2] : (R)1 - f[2]);
-            const R *p = base + (e0 * sx + e1 * sy + e2 * sz) * kRS;
+            const R *p = base + (e0 * sx + e1 * sy + e2 * sz) * RS;
 #pragma unroll
             for (int q = 0; q < NF; ++q) acc[q] += w * p[q];
         }
@@ -545,6 +547,8 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
         R th = M<R>::acos_((R)(z / r));
         R ph = M<R>::atan2_((R)y, (R)x);
         if (ph < (R)0) ph += (R)(2.0 * kPi);
+        R Pcur = M<R>::exp_(lnp);
+        R vcur = M<R>::div_((R)kC * Pcur, M<R>::sqrt_((R)1 + Pcur * Pcur));
         const uint64_t n_end = n0 + n_steps;
         uint64_t nstart = n0 > kinj ? n0 : kinj;
         for (uint64_t n = nstart; n < n_end; ++n) {
@@ -572,10 +576,10 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
                 const R xf = (R)x, yf = (R)y, zf = (R)z;
                 const R rho = M<R>::sqrt_(xf * xf + yf * yf);
                 const R rr = (R)r;
-                st_ = rho / rr;
-                ct_ = zf / rr;
-                sp_ = yf / rho;
-                cp_ = xf / rho;
+                st_ = M<R>::div_(rho, rr);
+                ct_ = M<R>::div_(zf, rr);
+                sp_ = M<R>::div_(yf, rho);
+                cp_ = M<R>::div_(xf, rho);
             }
             Fields<R> F;
             to_cart<R>(st_, ct_, sp_, cp_, acc + 0, F.V);
@@ -586,9 +590,9 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
                 status = FTE_PS_NUMERIC;
                 break;
             }
-            F.b[0] = bt[0] / bn;
-            F.b[1] = bt[1] / bn;
-            F.b[2] = bt[2] / bn;
+            F.b[0] = M<R>::div_(bt[0], bn);
+            F.b[1] = M<R>::div_(bt[1], bn);
+            F.b[2] = M<R>::div_(bt[2], bn);
             F.divV = acc[6];
             F.bbgV = acc[7];
             F.divb = acc[8];
@@ -598,10 +602,10 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
             } else {
                 F.curv[0] = F.curv[1] = F.curv[2] = (R)0;
             }
-            // ---- coefficients (Eqs. 2-5)
-            const R Pm = M<R>::exp_(lnp);
-            const R gam = M<R>::sqrt_((R)1 + Pm * Pm);
-            const R v = (R)kC * Pm / gam;
+            // ---- coefficients (Eqs. 2-5); P = p/(m c) and the speed are carried
+            // from the previous update (the same values as exp(lnp) recomputed)
+            const R Pm = Pcur;
+            const R v = vcur;
             R lam = (R)P.lambda_ref;
             if (P.alpha != 0.0) lam *= M<R>::pow_(Pm * (R)P.inv_p_ref, (R)P.alpha);
             const R A = (R)P.dmm_scale * v / lam;
@@ -630,8 +634,8 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
             R a_x[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) a_x[a] = F.V[a] + mu * v * F.b[a] - kperp * (F.divb * F.b[a] + F.curv[a]);
-            const R a_mu = (R)0.5 * om * (v * F.divb + mu * F.divV - (R)3 * mu * F.bbgV - ((R)2 / v) * F.bDV) + dD;
-            const R a_lnp = (R)0.5 * ((R)1 - (R)3 * mu * mu) * F.bbgV - (R)0.5 * om * F.divV - (mu / v) * F.bDV;
+            const R a_mu = (R)0.5 * om * (v * F.divb + mu * F.divV - (R)3 * mu * F.bbgV - M<R>::div_((R)2, v) * F.bDV) + dD;
+            const R a_lnp = (R)0.5 * ((R)1 - (R)3 * mu * mu) * F.bbgV - (R)0.5 * om * F.divV - M<R>::div_(mu, v) * F.bDV;
             // ---- Wiener increments: one Philox block, Box-Muller pairs
             const U4 k4 = philox_words(P.seed, P.run_id, n, pid, 0u);
             const R u0 = M<R>::u01(k4.a), u1 = M<R>::u01(k4.b), u2 = M<R>::u01(k4.c), u3 = M<R>::u01(k4.d);
@@ -675,6 +679,9 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
             z = zn;
             mu = mun;
             lnp = lnpn;
+            Pcur = M<R>::exp_(lnp);
+            const R gcur = M<R>::sqrt_((R)1 + Pcur * Pcur);
+            vcur = M<R>::div_((R)kC * Pcur, gcur);
             // ---- boundaries (radius in double on both paths)
             r = ::sqrt(x * x + y * y + z * z);
             if (r < P.r_in) {
@@ -692,28 +699,25 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
                 status = FTE_PS_OUT_OF_DOMAIN;
                 break;
             }
-            // ---- residence-time observer estimator, post-step state
+            // ---- residence-time observer estimator, post-step state: the box
+            // tests come first, the energy bin only for a particle inside one
             if (P.n_obs > 0) {
-                const R Pn = M<R>::exp_(lnp);
-                const R gn = M<R>::sqrt_((R)1 + Pn * Pn);
-                const R vn = (R)kC * Pn / gn;
-                const R lnE = M<R>::log_((R)P.mass_c2 * Pn * Pn / (gn + (R)1));
-                const R ue = (lnE - (R)P.e_min_ln) * (R)P.inv_dlne;
                 const double ut = (t + P.dt - P.t_ref) * P.inv_dT;
-                if (ue >= (R)0 && ue < (R)P.n_e && ut >= 0.0 && ut < (double)P.n_t) {
-                    const int ie = (int)M<R>::floor_(ue);
-                    const int it = (int)::floor(ut);
-                    const int ib = (int)(pid % (uint64_t)P.n_batch);
-                    for (int o = 0; o < P.n_obs; ++o) {
-                        const double *ob = P.obs[o];
-                        R dph = ph - (R)ob[4];
-                        while (dph >= (R)kPi) dph -= (R)(2.0 * kPi);
-                        while (dph < (R)-kPi) dph += (R)(2.0 * kPi);
-                        if (r >= ob[0] && r < ob[1] && th >= (R)ob[2] && th < (R)ob[3] && dph >= (R)-ob[5] &&
-                            dph < (R)ob[5]) {
-                            const size_t hidx = (((size_t)o * P.n_e + ie) * P.n_t + it) * P.n_batch + ib;
-                            atomicAdd(&hist[hidx], w * (double)vn * P.dt);
-                        }
+                for (int o = 0; o < P.n_obs; ++o) {
+                    const double *ob = P.obs[o];
+                    if (!(r >= ob[0] && r < ob[1] && th >= (R)ob[2] && th < (R)ob[3])) continue;
+                    R dph = ph - (R)ob[4];
+                    while (dph >= (R)kPi) dph -= (R)(2.0 * kPi);
+                    while (dph < (R)-kPi) dph += (R)(2.0 * kPi);
+                    if (!(dph >= (R)-ob[5] && dph < (R)ob[5])) continue;
+                    const R lnE = M<R>::log_((R)P.mass_c2 * M<R>::div_(Pcur * Pcur, gcur + (R)1));
+                    const R ue = (lnE - (R)P.e_min_ln) * (R)P.inv_dlne;
+                    if (ue >= (R)0 && ue < (R)P.n_e && ut >= 0.0 && ut < (double)P.n_t) {
+                        const int ie = (int)M<R>::floor_(ue);
+                        const int it = (int)::floor(ut);
+                        const int ib = (int)(pid % (uint64_t)P.n_batch);
+                        const size_t hidx = (((size_t)o * P.n_e + ie) * P.n_t + it) * P.n_batch + ib;
+                        atomicAdd(&hist[hidx], w * (double)vcur * P.dt);
                     }
                 }
             }

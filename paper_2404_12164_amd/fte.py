@@ -15,13 +15,14 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfte.so")
+LIB_PATH = os.environ.get("FTE_LIB_PATH") or os.path.join(_HERE, "libfte.so")
 
 FTE_OK, FTE_EINVAL, FTE_ESTATE, FTE_ENOMEM, FTE_EDEVICE, FTE_ERANGE = 0, -1, -2, -3, -4, -5
 FTE_FP64, FTE_MIXED = 0, 1
 DMM = {"iso": 0, "eq5": 1, "power_q": 2}
 MAX_OBS = 8
-RECORD_STRIDE = 16
+RECORD_STRIDE = 10        # fields 0-9 (no kappa_perp)
+RECORD_STRIDE_KPERP = 14  # fields 0-12 and one pad
 RECORD_FIELDS = 13
 STATUS = {"active": 0, "absorbed_in": 1, "absorbed_out": 2, "out_of_domain": 3, "numeric": 4}
 SYMBOLS = ["fte_create", "fte_destroy", "fte_last_error", "fte_query_sizes", "fte_bind_buffers", "fte_load_grid",
@@ -381,14 +382,15 @@ class Simulation:
         return fte_read_particles(self.ctx, self.n_max, self.stream)
 
     def records(self):
-        """Grid records as a float tensor view [n_snap][n_leaves][pcells][16]."""
+        """Grid records as a tensor view [n_snap][n_leaves][pcells][stride]."""
         t = self.torch
         bx = self.grid["bx"]
         pc = (bx[0] + 2) * (bx[1] + 2) * (bx[2] + 2)
-        dt = t.float64 if make_params(self.params).precision == FTE_FP64 else t.float32
+        pp = make_params(self.params)
+        dt = t.float64 if pp.precision == FTE_FP64 else t.float32
+        rs = RECORD_STRIDE_KPERP if (pp.kperp_ratio > 0 or pp.lambda_perp > 0) else RECORD_STRIDE
         nl = len(self.grid["leaves"])
-        return self.t_grid.view(dt)[: self.grid["n_snap"] * nl * pc * RECORD_STRIDE].view(
-            self.grid["n_snap"], nl, pc, RECORD_STRIDE)
+        return self.t_grid.view(dt)[: self.grid["n_snap"] * nl * pc * rs].view(self.grid["n_snap"], nl, pc, rs)
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -183,7 +183,8 @@ def test_records_match_oracle(F, torch_cuda, orc):
     rng = np.random.default_rng(0)
     bx = g["bx"]
     px = [b + 2 for b in bx]
-    scale = np.abs(rec[..., :13]).reshape(-1, 13).max(axis=0)
+    nf = 13 if rec.shape[-1] == 14 else 10
+    scale = np.abs(rec[..., :nf]).reshape(-1, nf).max(axis=0)
     n = 0
     for leaf in rng.choice(len(g["leaves"]), size=40, replace=False):
         L, I, J, K = g["leaves"][leaf]
@@ -192,8 +193,8 @@ def test_records_match_oracle(F, torch_cuda, orc):
             pc = (loc[0] + 1) + px[0] * ((loc[1] + 1) + px[1] * (loc[2] + 1))
             c = np.array([I * bx[0] + loc[0], J * bx[1] + loc[1], K * bx[2] + loc[2]])
             snap = int(rng.integers(0, g["n_snap"]))
-            want = G.derived_virtual(snap, int(L), c)
-            gotv = rec[snap, leaf, pc, :13]
+            want = G.derived_virtual(snap, int(L), c)[:nf]
+            gotv = rec[snap, leaf, pc, :nf]
             assert np.all(np.abs(gotv - want) <= 1e-11 * scale + 1e-12 * np.abs(want)), (leaf, loc, snap)
             n += 1
     assert n == 1600

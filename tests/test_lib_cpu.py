@@ -44,7 +44,7 @@ def test_query_sizes_valid(F):
     cfg = W.tiny_parker()
     s = F.fte_query_sizes(cfg["params"], cfg["grid"], 2000)
     pc = 18 ** 3
-    assert s.grid_bytes == 1 * 32 * pc * 16 * 8
+    assert s.grid_bytes == 1 * 32 * pc * 10 * 8          # stride 10 without kappa_perp
     mixed = dict(cfg["params"], precision="mixed")
     assert F.fte_query_sizes(mixed, cfg["grid"], 2000).grid_bytes == s.grid_bytes // 2
     assert s.hist_bytes == 1 * 10 * 60 * 32 * 8
@@ -55,7 +55,9 @@ def test_query_sizes_amr_cir(F):
     cfg = W.cir_time_dependent(n_particles=1000, n_snap=3)
     s = F.fte_query_sizes(cfg["params"], cfg["grid"], 1000)
     nl = len(cfg["grid"]["leaves"])
-    assert s.grid_bytes == 3 * nl * 18 * 14 * 18 * 16 * 4
+    assert s.grid_bytes == 3 * nl * 18 * 14 * 18 * 10 * 4
+    kp = dict(cfg["params"], kperp_ratio=0.01)
+    assert F.fte_query_sizes(kp, cfg["grid"], 1000).grid_bytes == 3 * nl * 18 * 14 * 18 * 14 * 4
 
 
 def _tiny_grid(**over):
