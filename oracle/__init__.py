@@ -22,6 +22,7 @@ Parity status of each function (see the tests under ``tests/test_oracle_*.py``):
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 import sys
@@ -59,6 +60,7 @@ class OrParams(C.Structure):
         ("e_min", C.c_double), ("dlne", C.c_double), ("n_e", C.c_int),
         ("t_ref", C.c_double), ("dT", C.c_double), ("n_t", C.c_int), ("n_batch", C.c_int),
         ("bg_kind", C.c_int), ("bg", C.c_double * 16),
+        ("smooth", C.c_int), ("sig_x", C.c_double), ("sig_lne", C.c_double), ("sig_t", C.c_double),
     ]
 
 
@@ -114,7 +116,7 @@ def lib():
         L.or_fields_public.argtypes = [C.POINTER(OrParams), C.c_void_p, dp, C.c_double, dp]
         L.or_fields_public.restype = C.c_int
         L.or_run.argtypes = [C.POINTER(OrParams), C.c_void_p, C.c_long, dp, dp, dp, dp, u64p, u32p,
-                             i32p, C.c_uint64, C.c_uint32, dp, C.c_int]
+                             i32p, C.c_uint64, C.c_uint32, dp, dp, C.c_int]
         L.or_run.restype = C.c_uint64
         L.or_inject.argtypes = [C.POINTER(OrParams), C.POINTER(OrInjection), C.c_long, C.c_uint64,
                                 dp, dp, dp, dp, u64p, u32p, i32p]
@@ -167,6 +169,10 @@ def make_params(p: dict) -> OrParams:
     o.bg_kind = BG[bk] if isinstance(bk, str) else int(bk)
     for i, v in enumerate(p.get("bg", [])):
         o.bg[i] = v
+    sm = p.get("smoothing")
+    if sm:
+        o.smooth = 1
+        o.sig_x, o.sig_lne, o.sig_t = sm["sigma_x"], sm["sigma_lne"], sm["sigma_t"]
     return o
 
 
@@ -347,16 +353,19 @@ def inject(params: dict, inj: dict, n: int, first_pid: int) -> Particles:
     return p
 
 
-def run(params: dict, grid, parts: Particles, n0: int, n_steps: int, hist=None, n_threads: int = 0) -> int:
+def run(params: dict, grid, parts: Particles, n0: int, n_steps: int, hist=None, n_threads: int = 0,
+        smooth=None) -> int:
     """Advance ``parts`` in place through steps n0..n0+n_steps-1; returns
     particle-steps taken.  ``hist`` (float64, ``hist_size(params)`` entries)
-    is accumulated into when given."""
+    is accumulated into when given; ``smooth`` (n_obs*n_e*n_t entries)
+    receives the kernel-smoothed intensity sums when params has "smoothing"."""
     o = make_params(params)
     hp = _ptr(hist, C.c_double) if hist is not None else None
+    sp = _ptr(smooth, C.c_double) if smooth is not None else None
     return lib().or_run(C.byref(o), grid.h if grid is not None else None, len(parts),
                         _ptr(parts.x, C.c_double), _ptr(parts.mu, C.c_double), _ptr(parts.lnp, C.c_double),
                         _ptr(parts.w, C.c_double), _ptr(parts.pid, C.c_uint64), _ptr(parts.kinj, C.c_uint32),
-                        _ptr(parts.status, C.c_int32), n0, n_steps, hp, n_threads)
+                        _ptr(parts.status, C.c_int32), n0, n_steps, hp, sp, n_threads)
 
 
 def finalize(params: dict, hist: np.ndarray, w_inj: float):
@@ -368,6 +377,13 @@ def finalize(params: dict, hist: np.ndarray, w_inj: float):
     lib().or_finalize(C.byref(o), _ptr(h, C.c_double), w_inj, _ptr(j, C.c_double), _ptr(s, C.c_double))
     shp = (len(params["observers"]), int(params["n_e"]), int(params["n_t"]))
     return j.reshape(shp), s.reshape(shp)
+
+
+def finalize_smoothed(params: dict, sm: np.ndarray, w_inj: float) -> np.ndarray:
+    """Smoothed intensities J = sums / (4 pi W_inj), shaped (n_obs, n_e, n_t):
+    the kernels already carry the 1/(dV dE dT) of the histogram estimator."""
+    shp = (len(params["observers"]), int(params["n_e"]), int(params["n_t"]))
+    return np.asarray(sm, dtype=np.float64).reshape(shp) / (4.0 * math.pi * w_inj)
 
 
 if __name__ == "__main__":

@@ -62,6 +62,8 @@ typedef struct {
     int    n_batch;       /* batch = pid mod n_batch                             */
     int    bg_kind;       /* OR_BG_*                                             */
     double bg[16];        /* analytic background parameters                      */
+    int    smooth;        /* accumulate the kernel-smoothed intensity sums       */
+    double sig_x, sig_lne, sig_t;  /* Gaussian widths: space (m), ln E, time (s) */
 } or_params;
 
 typedef struct {
@@ -736,7 +738,39 @@ static double or_ekin(double mass, double P)
     return mass * OR_C * OR_C * P * P / (gam + 1.0);
 }
 
-static void or_step(const or_params *pp, const void *g, or_particle *pt, uint64_t n, double *hist)
+/* Kernel-smoothed intensity sums: every post-step state adds
+ *   w v dt G3(x - x_o) G1(ln E - ln E_e)/E G1(t - t_t)
+ * to observer o, energy-bin centre E_e and time-bin centre t_t, where G3 and G1
+ * are normalised Gaussians of widths sig_x, sig_lne, sig_t cut at 4 widths.
+ * Divided by 4 pi W_inj this is a smooth estimate of j = v n_E / (4 pi)
+ * (section 2.3) that is differentiable along each trajectory. */
+static void or_smooth_add(const or_params *pp, const double x[3], double t1, double w, double P, double *sm)
+{
+    double gam = sqrt(1.0 + P * P), v = OR_C * P / gam;
+    double E = pp->mass * OR_C * OR_C * P * P / (gam + 1.0), lnE = log(E);
+    for (int o = 0; o < pp->n_obs; ++o) {
+        const double *ob = pp->obs[o];
+        double xo[3] = {ob[0] * sin(ob[1]) * cos(ob[2]), ob[0] * sin(ob[1]) * sin(ob[2]), ob[0] * cos(ob[1])};
+        double d2 = 0.0;
+        for (int a = 0; a < 3; ++a) d2 += (x[a] - xo[a]) * (x[a] - xo[a]);
+        if (d2 > 16.0 * pp->sig_x * pp->sig_x) continue;
+        double g3 = exp(-d2 / (2.0 * pp->sig_x * pp->sig_x)) /
+                    (pow(2.0 * OR_PI, 1.5) * pp->sig_x * pp->sig_x * pp->sig_x);
+        for (int e = 0; e < pp->n_e; ++e) {
+            double ue = lnE - (log(pp->e_min) + (e + 0.5) * pp->dlne);
+            if (fabs(ue) > 4.0 * pp->sig_lne) continue;
+            double ke = exp(-ue * ue / (2.0 * pp->sig_lne * pp->sig_lne)) / (sqrt(2.0 * OR_PI) * pp->sig_lne) / E;
+            for (int it = 0; it < pp->n_t; ++it) {
+                double ut = t1 - (pp->t_ref + (it + 0.5) * pp->dT);
+                if (fabs(ut) > 4.0 * pp->sig_t) continue;
+                double kt = exp(-ut * ut / (2.0 * pp->sig_t * pp->sig_t)) / (sqrt(2.0 * OR_PI) * pp->sig_t);
+                sm[((long)o * pp->n_e + e) * pp->n_t + it] += w * v * pp->dt * g3 * ke * kt;
+            }
+        }
+    }
+}
+
+static void or_step(const or_params *pp, const void *g, or_particle *pt, uint64_t n, double *hist, double *sm)
 {
     double t = pp->t0 + (double)n * pp->dt;
     or_fields F;
@@ -790,6 +824,9 @@ static void or_step(const or_params *pp, const void *g, or_particle *pt, uint64_
         }
     }
 
+    if (sm && pp->smooth && pp->n_obs > 0)
+        or_smooth_add(pp, xn, pp->t0 + (double)(n + 1) * pp->dt, pt->w, exp(lnpn), sm);
+
     /* Residence-time estimator of the intensity j = p^2 f = v n_E / (4 pi)
      * (section 2.3): the post-step state adds w v dt to its bin. */
     if (hist && pp->n_obs > 0) {
@@ -825,9 +862,10 @@ static void or_step(const or_params *pp, const void *g, or_particle *pt, uint64_
  * number of particle-steps taken. */
 uint64_t or_run(const or_params *pp, const void *g, long n, double *x, double *mu, double *lnp,
                 double *w, const uint64_t *pid, const uint32_t *kinj, int32_t *status,
-                uint64_t n0, uint32_t n_steps, double *hist, int n_threads)
+                uint64_t n0, uint32_t n_steps, double *hist, double *sm, int n_threads)
 {
     long hsz = hist ? (long)pp->n_obs * pp->n_e * pp->n_t * pp->n_batch : 0;
+    long ssz = sm ? (long)pp->n_obs * pp->n_e * pp->n_t : 0;
     uint64_t total = 0;
 #ifdef _OPENMP
     if (n_threads <= 0) n_threads = omp_get_max_threads();
@@ -835,6 +873,7 @@ uint64_t or_run(const or_params *pp, const void *g, long n, double *x, double *m
     n_threads = 1;
 #endif
     double *priv = hist ? (double *)calloc((size_t)hsz * n_threads, sizeof(double)) : NULL;
+    double *spriv = sm ? (double *)calloc((size_t)ssz * n_threads, sizeof(double)) : NULL;
 #ifdef _OPENMP
 #pragma omp parallel num_threads(n_threads) reduction(+ : total)
 #endif
@@ -844,6 +883,7 @@ uint64_t or_run(const or_params *pp, const void *g, long n, double *x, double *m
         tid = omp_get_thread_num();
 #endif
         double *h = priv ? priv + (long)tid * hsz : NULL;
+        double *sp = spriv ? spriv + (long)tid * ssz : NULL;
 #ifdef _OPENMP
 #pragma omp for schedule(static)
 #endif
@@ -855,7 +895,7 @@ uint64_t or_run(const or_params *pp, const void *g, long n, double *x, double *m
             for (uint64_t s = n0; s < n0 + n_steps; ++s) {
                 if (pt.status != OR_ACTIVE) break;
                 if (s < pt.kinj) continue;
-                or_step(pp, g, &pt, s, h);
+                or_step(pp, g, &pt, s, h, sp);
                 total += 1;
             }
             x[3 * i] = pt.x[0]; x[3 * i + 1] = pt.x[1]; x[3 * i + 2] = pt.x[2];
@@ -866,6 +906,11 @@ uint64_t or_run(const or_params *pp, const void *g, long n, double *x, double *m
         for (int t = 0; t < n_threads; ++t)
             for (long k = 0; k < hsz; ++k) hist[k] += priv[(long)t * hsz + k];
         free(priv);
+    }
+    if (sm) {
+        for (int t = 0; t < n_threads; ++t)
+            for (long k = 0; k < ssz; ++k) sm[k] += spriv[(long)t * ssz + k];
+        free(spriv);
     }
     return total;
 }

@@ -345,3 +345,42 @@ def test_shock_acceleration_index(orc):
     assert 4.35 < q3 < 5.0, q3
     assert 5.6 < q2 < 6.8, q2
     assert 0.9 < q2 - q3 < 2.1, (q2, q3)
+
+
+def test_smoothed_intensity_profile(orc):
+    """Kernel-smoothed estimator on a uniform static population of one energy
+    E0 filling a box much larger than the spatial kernel: its expectation is
+    v n / (4 pi) G1(ln E0 - ln E_e) / E0 in every time bin whose kernel lies
+    inside the run (the smoothed form of j = v n_E / (4 pi), section 2.3).
+    A misplaced observer centre, energy or time centre, or a wrong kernel
+    normalisation moves some bin far outside the tolerance."""
+    N = 200000
+    rng = np.random.default_rng(3)
+    half = 0.1 * AU
+    sx, sl, st = 0.02 * AU, 0.1, 60.0
+    E0 = E100
+    # energy bins of width 0.1 in ln E, centres from ln E0 - 0.25 to ln E0 + 0.15
+    n_e = 5
+    e_min = E0 * math.exp(-0.3)
+    par = iso_uniform(1e30, dt=10.0, observers=[(AU, 90 * W.DEG, 0.0, 0.05 * AU, 10 * W.DEG, 10 * W.DEG),
+                                                 (AU, 60 * W.DEG, 0.0, 0.05 * AU, 10 * W.DEG, 10 * W.DEG)],
+                      e_min=e_min, dlne=0.1, n_e=n_e, t_ref=0.0, dT=600.0, n_t=4, n_batch=1,
+                      smoothing=dict(sigma_x=sx, sigma_lne=sl, sigma_t=st))
+    p = mk(orc, N, mu=0.0)
+    p.x[:, 0] = AU + half * (2 * rng.random(N) - 1)
+    p.x[:, 1] = half * (2 * rng.random(N) - 1)
+    p.x[:, 2] = half * (2 * rng.random(N) - 1)
+    sm = np.zeros(2 * n_e * 4)
+    orc.run(par, None, p, 0, 180, None, smooth=sm)       # t = 10 .. 1800 s
+    J = orc.finalize_smoothed(par, sm, float(N))
+    n = 1.0 / (2 * half) ** 3          # per unit injected weight (W_inj = N)
+    for e in range(n_e):
+        u = math.log(E0) - (math.log(e_min) + (e + 0.5) * 0.1)
+        want = V100 * n / (4 * math.pi) * math.exp(-u * u / (2 * sl * sl)) / (math.sqrt(2 * math.pi) * sl) / E0
+        # time bins centred at 300, 900, 1500 s hold the whole time kernel;
+        # the one at 2100 s holds none of it
+        for it in range(3):
+            assert J[0, e, it] == pytest.approx(want, rel=0.045), (e, it)
+        assert J[0, e, 3] == 0.0
+    # the second observer sits 0.5 au away from the population
+    assert np.all(J[1] == 0.0)
