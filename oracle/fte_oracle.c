@@ -738,10 +738,14 @@ static double or_ekin(double mass, double P)
     return mass * OR_C * OR_C * P * P / (gam + 1.0);
 }
 
+#define OR_KCUT 6.0
+
 /* Kernel-smoothed intensity sums: every post-step state adds
  *   w v dt G3(x - x_o) G1(ln E - ln E_e)/E G1(t - t_t)
  * to observer o, energy-bin centre E_e and time-bin centre t_t, where G3 and G1
- * are normalised Gaussians of widths sig_x, sig_lne, sig_t cut at 4 widths.
+ * are normalised Gaussians of widths sig_x, sig_lne, sig_t cut at OR_KCUT
+ * widths (where they have fallen to 1.5e-8 of the peak, so that the jump at the
+ * cut adds no visible boundary term to derivatives along a trajectory).
  * Divided by 4 pi W_inj this is a smooth estimate of j = v n_E / (4 pi)
  * (section 2.3) that is differentiable along each trajectory. */
 static void or_smooth_add(const or_params *pp, const double x[3], double t1, double w, double P, double *sm)
@@ -753,16 +757,16 @@ static void or_smooth_add(const or_params *pp, const double x[3], double t1, dou
         double xo[3] = {ob[0] * sin(ob[1]) * cos(ob[2]), ob[0] * sin(ob[1]) * sin(ob[2]), ob[0] * cos(ob[1])};
         double d2 = 0.0;
         for (int a = 0; a < 3; ++a) d2 += (x[a] - xo[a]) * (x[a] - xo[a]);
-        if (d2 > 16.0 * pp->sig_x * pp->sig_x) continue;
+        if (d2 > OR_KCUT * OR_KCUT * pp->sig_x * pp->sig_x) continue;
         double g3 = exp(-d2 / (2.0 * pp->sig_x * pp->sig_x)) /
                     (pow(2.0 * OR_PI, 1.5) * pp->sig_x * pp->sig_x * pp->sig_x);
         for (int e = 0; e < pp->n_e; ++e) {
             double ue = lnE - (log(pp->e_min) + (e + 0.5) * pp->dlne);
-            if (fabs(ue) > 4.0 * pp->sig_lne) continue;
+            if (fabs(ue) > OR_KCUT * pp->sig_lne) continue;
             double ke = exp(-ue * ue / (2.0 * pp->sig_lne * pp->sig_lne)) / (sqrt(2.0 * OR_PI) * pp->sig_lne) / E;
             for (int it = 0; it < pp->n_t; ++it) {
                 double ut = t1 - (pp->t_ref + (it + 0.5) * pp->dT);
-                if (fabs(ut) > 4.0 * pp->sig_t) continue;
+                if (fabs(ut) > OR_KCUT * pp->sig_t) continue;
                 double kt = exp(-ut * ut / (2.0 * pp->sig_t * pp->sig_t)) / (sqrt(2.0 * OR_PI) * pp->sig_t);
                 sm[((long)o * pp->n_e + e) * pp->n_t + it] += w * v * pp->dt * g3 * ke * kt;
             }

@@ -378,9 +378,9 @@ def test_smoothed_intensity_profile(orc):
         u = math.log(E0) - (math.log(e_min) + (e + 0.5) * 0.1)
         want = V100 * n / (4 * math.pi) * math.exp(-u * u / (2 * sl * sl)) / (math.sqrt(2 * math.pi) * sl) / E0
         # time bins centred at 300, 900, 1500 s hold the whole time kernel;
-        # the one at 2100 s holds none of it
+        # the one at 2100 s (5 widths after the run's last step) only its tail
         for it in range(3):
             assert J[0, e, it] == pytest.approx(want, rel=0.045), (e, it)
-        assert J[0, e, 3] == 0.0
+        assert J[0, e, 3] < 1e-6 * want
     # the second observer sits 0.5 au away from the population
     assert np.all(J[1] == 0.0)
