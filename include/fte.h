@@ -111,6 +111,22 @@ typedef struct {
     double dT;            /* time-bin width, s                                     */
     int n_t;              /* time bins                                             */
     int n_batch;          /* 1..FTE_MAX_BATCH; batch = pid mod n_batch             */
+    /* Kernel-smoothed intensities (on when sigma_x > 0): every post-step
+     * state adds w v dt G3(x - x_o) G1(ln E - ln E_e) / E G1(t - t_t) to
+     * J[o][e][t], x_o the observer centre, ln E_e = ln e_min + (e + 1/2) dlne
+     * and t_t = t_ref + (t + 1/2) dT the bin centres, G3 / G1 normalised
+     * Gaussians of widths sigma_x, sigma_lne, sigma_t, each dropped beyond 6
+     * widths (1.5e-8 of the peak); J = sums / (4 pi W_inj).  A differentiable estimate of
+     * j = p^2 f = v n_E / (4 pi) (section 2.3). */
+    double sigma_x;       /* m                                                     */
+    double sigma_lne;     /* ln E                                                  */
+    double sigma_t;       /* s                                                     */
+    int grad;             /* 1: also carry, per particle, the pathwise derivatives
+                             of (x, mu, ln p) with respect to lambda_ref and
+                             kperp_ratio (forward tangents driven by the same
+                             noise) and d ln w / d gamma_inj, and accumulate dJ.
+                             Needs sigma_x, sigma_lne, sigma_t > 0 and the
+                             tangent buffers.                                     */
 } fte_params;
 
 /* Block-AMR spherical grid (section 2.4).  Coordinates (xi, theta, phi), with
@@ -160,17 +176,19 @@ typedef struct {
 
 /* Byte sizes of the caller-owned device buffers. */
 typedef struct {
-    uint64_t grid_bytes;   /* derived-field records of every snapshot             */
-    uint64_t index_bytes;  /* block index and leaf table                          */
-    uint64_t state_bytes;  /* one particle state buffer (two are bound)           */
-    uint64_t hist_bytes;   /* observer batch sums                                 */
-    uint64_t work_bytes;   /* counters, load-time workspace, finalize output      */
+    uint64_t grid_bytes;    /* derived-field records of every snapshot             */
+    uint64_t index_bytes;   /* block index and leaf table                          */
+    uint64_t state_bytes;   /* one particle state buffer (two are bound)           */
+    uint64_t hist_bytes;    /* observer batch sums                                 */
+    uint64_t work_bytes;    /* counters, load-time workspace, finalize output,
+                               smoothed-intensity sums                            */
+    uint64_t tangent_bytes; /* one tangent buffer (two; gradient mode only)        */
 } fte_sizes;
 
 /* Device pointers, each at least the matching fte_sizes bytes, 256-byte
- * aligned. */
+ * aligned.  tangent_a / tangent_b may be NULL when fte_params.grad == 0. */
 typedef struct {
-    void *grid, *index, *state_a, *state_b, *hist, *work;
+    void *grid, *index, *state_a, *state_b, *hist, *work, *tangent_a, *tangent_b;
 } fte_buffers;
 
 typedef struct {
@@ -202,7 +220,8 @@ typedef struct {
 
 /* Particle state buffer layout for capacity n_max: arrays of n_max entries
  * in this order: x, y, z, mu, lnp (ln of p / (m c)), w (all double), pid
- * (uint64), kinj (uint32), status (int32). */
+ * (uint64), kinj (uint32), status (int32).  Tangent buffer layout: 11 double
+ * arrays of n_max entries, in the order of fte_read_tangents. */
 
 fte_status fte_create(fte_ctx **out, const fte_params *p);
 void fte_destroy(fte_ctx *ctx);
@@ -253,6 +272,28 @@ fte_status fte_get_stats(fte_ctx *ctx, fte_stats *out, void *stream);
  * order (not pid order).  Synchronises. */
 fte_status fte_read_particles(fte_ctx *ctx, double *x3, double *mu, double *lnp, double *w, uint64_t *pid,
                               uint32_t *kinj, int32_t *status, uint64_t cap, uint64_t *n_out, void *stream);
+
+/* Smoothed intensities J (HOST array of n_obs*n_e*n_t; needs sigma_x > 0)
+ * and, in gradient mode, their derivatives dJ (HOST array
+ * [3][n_obs*n_e*n_t]) with respect to (lambda_ref, kperp_ratio, gamma_inj),
+ * the last including the change of W_inj.  The derivatives are pathwise:
+ * absorption and the 6-width cut of the kernels are treated as fixed events.
+ * The kperp_ratio derivative is 0 unless kperp_ratio > 0.  Either array may
+ * be NULL.  Synchronises. */
+fte_status fte_bin_smoothed(fte_ctx *ctx, double *J, double *dJ, void *stream);
+
+/* Gradient of a loss L(J) with respect to (lambda_ref, kperp_ratio,
+ * gamma_inj): grad[k] = sum over bins of dL_dJ[bin] dJ[k][bin], contracted
+ * on the device (gradient mode).  dL_dJ is a HOST array of n_obs*n_e*n_t;
+ * grad a HOST array of 3.  Synchronises. */
+fte_status fte_grad(fte_ctx *ctx, const double *dL_dJ, double grad[3], void *stream);
+
+/* Tangents of the held particles (gradient mode), storage order as
+ * fte_read_particles: HOST array [n_live][11] = dx, dy, dz, dmu, dlnp with
+ * respect to lambda_ref, the same five with respect to kperp_ratio, and
+ * d ln w / d gamma_inj.  cap is the row capacity of tan (FTE_ENOMEM if
+ * below n_live); *n_out receives n_live.  Synchronises. */
+fte_status fte_read_tangents(fte_ctx *ctx, double *tan, uint64_t cap, uint64_t *n_out, void *stream);
 
 /* Drop all particles, observer sums, counters and timings and rewind the
  * global clock to step 0; the loaded grid stays.  Synchronises. */

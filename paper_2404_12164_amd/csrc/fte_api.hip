@@ -27,9 +27,12 @@ struct fte_ctx {
     uint64_t n_max = 0;
     fte_buffers b{};
     DevState st[2]{};
+    DevTan tn[2]{};
     int cur = 0;
     DevCounters *cnt = nullptr;
     double *fin_j = nullptr, *fin_s = nullptr, *cart = nullptr;
+    double *sm = nullptr, *fin_sm = nullptr, *dl = nullptr, *out4 = nullptr;
+    uint64_t sm_n = 0;
     uint32_t *keys = nullptr, *counts = nullptr, *tsum = nullptr;
     uint32_t n_keys = 0;
     int sort = 2;
@@ -64,6 +67,25 @@ fte_status fail(fte_ctx *c, fte_status s, const std::string &msg) {
 
 bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
 
+// Global steps whose post-step time t0 + (n+1) dt can lie within the time
+// kernel's cut of
+// a time-bin centre (padded by a step on each side; the read-out applies the
+// exact cut).
+void smooth_window(const fte_params *p, long long *lo, long long *n) {
+    const double cut = kKernelCut * p->sigma_t;
+    const double t_lo = p->t_ref + 0.5 * p->dT - cut;
+    const double t_hi = p->t_ref + ((double)p->n_t - 0.5) * p->dT + cut;
+    double a = floor((t_lo - p->t0) / p->dt) - 2.0, b = floor((t_hi - p->t0) / p->dt) + 1.0;
+    if (a < 0.0) a = 0.0;
+    if (!(b >= a) || !isfinite(a) || !isfinite(b) || b - a > 1e12) {
+        *lo = 0;
+        *n = (isfinite(a) && isfinite(b) && b >= a) ? (long long)1e12 : 0;
+        return;
+    }
+    *lo = (long long)a;
+    *n = (long long)(b - a) + 1;
+}
+
 std::string check_params(const fte_params *p) {
     if (!p) return "params is NULL";
     if (!finite_pos(p->mass)) return "mass must be > 0";
@@ -92,6 +114,16 @@ std::string check_params(const fte_params *p) {
                 ob.dr >= 2 * ob.r || !isfinite(ob.theta) || !isfinite(ob.phi) || ob.dphi > 2 * kPi)
                 return "bad observer box";
         }
+    }
+    if (!(p->sigma_x >= 0.0) || !isfinite(p->sigma_x)) return "sigma_x must be >= 0";
+    if (p->grad != 0 && p->grad != 1) return "grad must be 0 or 1";
+    if (p->grad && !(p->sigma_x > 0.0)) return "the gradient needs the smoothed intensities (sigma_x > 0)";
+    if (p->sigma_x > 0.0) {
+        if (p->n_obs < 1) return "smoothed intensities need observers";
+        if (!finite_pos(p->sigma_lne) || !finite_pos(p->sigma_t)) return "sigma_lne and sigma_t must be > 0";
+        long long lo, n;
+        smooth_window(p, &lo, &n);
+        if ((double)n * p->n_obs * p->n_e * (p->grad ? 4 : 1) > 4e9) return "smoothing window too large";
     }
     return "";
 }
@@ -189,9 +221,10 @@ std::string build_index(const fte_grid_desc *g, std::vector<int32_t> &base, std:
 size_t rec_elem(const fte_params *p) { return p->precision == FTE_FP64 ? 8 : 4; }
 
 struct Layout {
-    size_t grid, index, state, hist, work;
+    size_t grid, index, state, hist, work, tangent;
     size_t off_child, off_info;
     size_t off_j, off_s, off_cart, off_keys, off_counts, off_tsum;
+    size_t off_sm, off_fin_sm, off_dl, off_out4, sm_n;
     uint32_t n_keys;
     int pcells;
     int rs;
@@ -215,7 +248,18 @@ Layout layout(const fte_params *p, const fte_grid_desc *g, uint64_t n_max, size_
     L.n_keys = (uint32_t)((size_t)g->n_leaves * g->bx[0] * g->bx[1] * g->bx[2]);   // finest sort key
     L.off_counts = L.off_keys + align256(n_max * 4);
     L.off_tsum = L.off_counts + align256(((size_t)L.n_keys + 1) * 4);
-    L.work = L.off_tsum + align256(((size_t)L.n_keys / 4096 + 2) * 4);
+    L.off_sm = L.off_tsum + align256(((size_t)L.n_keys / 4096 + 2) * 4);
+    L.sm_n = 0;
+    if (p->sigma_x > 0.0) {
+        long long lo, nw;
+        smooth_window(p, &lo, &nw);
+        L.sm_n = (size_t)nw * p->n_obs * p->n_e * (p->grad ? 4 : 1);
+    }
+    L.off_fin_sm = L.off_sm + align256(L.sm_n * 8);
+    L.off_dl = L.off_fin_sm + align256(p->sigma_x > 0.0 ? 4 * nbins * 8 : 0);
+    L.off_out4 = L.off_dl + align256(p->sigma_x > 0.0 ? nbins * 8 : 0);
+    L.work = L.off_out4 + 256;
+    L.tangent = p->grad ? tangent_bytes(n_max) : 0;
     return L;
 }
 
@@ -280,6 +324,31 @@ void make_devparams(const fte_params *p, DevParams *d) {
     d->n_e = p->n_obs > 0 ? p->n_e : 1;
     d->n_t = p->n_obs > 0 ? p->n_t : 1;
     d->n_batch = p->n_batch;
+    // kernel-smoothed intensities
+    if (p->sigma_x > 0.0) {
+        d->smooth = 1;
+        d->grad = p->grad;
+        d->nk = p->grad ? 4 : 1;
+        for (int o = 0; o < p->n_obs; ++o) {
+            const fte_observer &ob = p->obs[o];
+            d->obs_xyz[o][0] = ob.r * sin(ob.theta) * cos(ob.phi);
+            d->obs_xyz[o][1] = ob.r * sin(ob.theta) * sin(ob.phi);
+            d->obs_xyz[o][2] = ob.r * cos(ob.theta);
+        }
+        const double sx = p->sigma_x, sl = p->sigma_lne;
+        d->sx_cut2 = kKernelCut * kKernelCut * sx * sx;
+        d->inv_2sx2 = 1.0 / (2.0 * sx * sx);
+        d->inv_sx2 = 1.0 / (sx * sx);
+        d->norm3 = 1.0 / (pow(2.0 * kPi, 1.5) * sx * sx * sx);
+        d->sl_cut = kKernelCut * sl;
+        d->inv_2sl2 = 1.0 / (2.0 * sl * sl);
+        d->inv_sl2 = 1.0 / (sl * sl);
+        d->norm1 = 1.0 / (sqrt(2.0 * kPi) * sl);
+        d->sig_t = p->sigma_t;
+        d->inv_lambda_ref = 1.0 / p->lambda_ref;
+        d->inv_kperp_ratio = p->kperp_ratio > 0.0 ? 1.0 / p->kperp_ratio : 0.0;
+        smooth_window(p, &d->win_lo, &d->n_win);
+    }
 }
 
 }  // namespace
@@ -288,6 +357,15 @@ namespace fte {
 
 size_t state_bytes(uint64_t n) {
     return 6 * align256(n * 8) + align256(n * 8) + align256(n * 4) + align256(n * 4);
+}
+
+size_t tangent_bytes(uint64_t n) { return 11 * align256(n * 8); }
+
+DevTan tangent_view(void *base, uint64_t n) {
+    DevTan t{};
+    t.base = (double *)base;
+    t.stride = align256(n * 8) / 8;
+    return t;
 }
 
 DevState state_view(void *base, uint64_t n) {
@@ -353,6 +431,7 @@ fte_status fte_query_sizes(const fte_params *p, const fte_grid_desc *g, uint64_t
     out->state_bytes = L.state;
     out->hist_bytes = L.hist;
     out->work_bytes = L.work;
+    out->tangent_bytes = L.tangent;
     return FTE_OK;
 }
 
@@ -366,6 +445,9 @@ fte_status fte_bind_buffers(fte_ctx *c, const fte_grid_desc *g, uint64_t n_max, 
     const void *ptrs[6] = {b->grid, b->index, b->state_a, b->state_b, b->hist, b->work};
     for (int k = 0; k < 6; ++k)
         if (!ptrs[k] || ((uintptr_t)ptrs[k] & 255)) return fail(c, FTE_EINVAL, "buffers must be non-NULL, 256-byte aligned");
+    if (c->p.grad && (!b->tangent_a || !b->tangent_b || ((uintptr_t)b->tangent_a & 255) ||
+                      ((uintptr_t)b->tangent_b & 255)))
+        return fail(c, FTE_EINVAL, "gradient mode needs 256-byte aligned tangent buffers");
     const Layout L = layout(&c->p, g, n_max, base.size(), child.size());
     c->g = *g;
     c->leaves.assign(g->leaves, g->leaves + 4 * (size_t)g->n_leaves);
@@ -377,6 +459,8 @@ fte_status fte_bind_buffers(fte_ctx *c, const fte_grid_desc *g, uint64_t n_max, 
     c->b = *b;
     c->st[0] = state_view(b->state_a, n_max);
     c->st[1] = state_view(b->state_b, n_max);
+    c->tn[0] = c->p.grad ? tangent_view(b->tangent_a, n_max) : DevTan{};
+    c->tn[1] = c->p.grad ? tangent_view(b->tangent_b, n_max) : DevTan{};
     c->cur = 0;
     char *w = (char *)b->work;
     c->cnt = (DevCounters *)w;
@@ -387,6 +471,11 @@ fte_status fte_bind_buffers(fte_ctx *c, const fte_grid_desc *g, uint64_t n_max, 
     c->counts = (uint32_t *)(w + L.off_counts);
     c->tsum = (uint32_t *)(w + L.off_tsum);
     c->n_keys = L.n_keys;
+    c->sm = (double *)(w + L.off_sm);
+    c->sm_n = L.sm_n;
+    c->fin_sm = (double *)(w + L.off_fin_sm);
+    c->dl = (double *)(w + L.off_dl);
+    c->out4 = (double *)(w + L.off_out4);
     c->hist_n = (uint64_t)c->p.n_obs * c->p.n_e * c->p.n_t * c->p.n_batch;
 
     DevGrid &d = c->dg;
@@ -450,6 +539,7 @@ fte_status fte_load_grid(fte_ctx *c, const double *vb, void *stream) {
     HIPCHK(c, hipMemcpyAsync((void *)d.leaf_info, c->info.data(), c->info.size() * 4, hipMemcpyHostToDevice, s));
     HIPCHK(c, launch_zero_counters(c->cnt, s));
     if (c->hist_n) HIPCHK(c, launch_zero((double *)c->b.hist, c->hist_n, s));
+    if (c->sm_n) HIPCHK(c, launch_zero(c->sm, c->sm_n, s));
     HIPCHK(c, launch_check_raw(d, vb, c->cnt, s));
     const int fp32 = c->p.precision == FTE_MIXED;
     for (int k = 0; k < d.n_snap; ++k) {
@@ -529,7 +619,7 @@ fte_status fte_inject(fte_ctx *c, const fte_injection *inj, uint64_t n, uint64_t
         if (r != FTE_OK) return r;
         if (c->n_upper + n > c->n_max) return fail(c, FTE_ENOMEM, "particle capacity exceeded");
     }
-    HIPCHK(c, launch_inject(c->dp, *inj, c->st[c->cur], c->cnt, c->cur, n, first_pid, s));
+    HIPCHK(c, launch_inject(c->dp, *inj, c->st[c->cur], c->tn[c->cur], c->cnt, c->cur, n, first_pid, s));
     HIPCHK(c, launch_add_live(c->cnt, c->cur, n, s));
     c->n_upper += n;
     c->injected_since += n;
@@ -564,8 +654,8 @@ fte_status fte_step_n(fte_ctx *c, uint32_t n_steps, void *stream) {
             }
             HIPCHK(c, hipEventRecord(c->tev[c->tev_used], s));
         }
-        HIPCHK(c, launch_step(c->dp, c->dg, c->st[c->cur], c->cnt, c->cur, (double *)c->b.hist, c->global_step,
-                              chunk, c->n_upper, c->block, c->p.precision == FTE_MIXED, s));
+        HIPCHK(c, launch_step(c->dp, c->dg, c->st[c->cur], c->tn[c->cur], c->cnt, c->cur, (double *)c->b.hist, c->sm,
+                              c->global_step, chunk, c->n_upper, c->block, c->p.precision == FTE_MIXED, s));
         if (c->timing) {
             HIPCHK(c, hipEventRecord(c->tev[c->tev_used + 1], s));
             c->tev_used += 2;
@@ -576,11 +666,12 @@ fte_status fte_step_n(fte_ctx *c, uint32_t n_steps, void *stream) {
         if (c->compact_every > 0 && c->since_compact >= (uint64_t)c->compact_every) {
             const int to = 1 - c->cur;
             if (c->sort) {
-                HIPCHK(c, launch_compact_sorted(c->dg, c->sort, c->st[c->cur], c->st[to], c->cnt, c->cur, c->n_upper,
-                                                c->keys, c->counts, c->tsum, s));
+                HIPCHK(c, launch_compact_sorted(c->dg, c->sort, c->st[c->cur], c->st[to], c->tn[c->cur], c->tn[to],
+                                                c->cnt, c->cur, c->n_upper, c->keys, c->counts, c->tsum, s));
             } else {
                 HIPCHK(c, launch_zero_live(c->cnt, to, s));
-                HIPCHK(c, launch_compact(c->st[c->cur], c->st[to], c->cnt, c->cur, c->n_upper, 256, s));
+                HIPCHK(c, launch_compact(c->st[c->cur], c->st[to], c->tn[c->cur], c->tn[to], c->cnt, c->cur,
+                                         c->n_upper, 256, s));
             }
             c->cur = to;
             c->since_compact = 0;
@@ -661,6 +752,7 @@ fte_status fte_reset(fte_ctx *c, void *stream) {
     HIPCHK(c, hipStreamSynchronize(s));
     HIPCHK(c, launch_zero_counters(c->cnt, s));
     if (c->hist_n) HIPCHK(c, launch_zero((double *)c->b.hist, c->hist_n, s));
+    if (c->sm_n) HIPCHK(c, launch_zero(c->sm, c->sm_n, s));
     HIPCHK(c, hipStreamSynchronize(s));
     c->cur = 0;
     c->n_upper = 0;
@@ -715,6 +807,93 @@ fte_status fte_read_particles(fte_ctx *c, double *x3, double *mu, double *lnp, d
     if (kinj) HIPCHK(c, hipMemcpyAsync(kinj, d.kinj, n * 4, hipMemcpyDeviceToHost, s));
     if (status) HIPCHK(c, hipMemcpyAsync(status, d.status, n * 4, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
+    return FTE_OK;
+}
+
+// Smoothed sums -> fin_sm[k][bins] (k = 0: J numerators, 1-3: derivatives)
+// and the injected weight and its gamma derivative.
+static fte_status smoothed_sums(fte_ctx *c, hipStream_t s, double *W, double *dW) {
+    HIPCHK(c, launch_smooth_finalize(c->dp, c->sm, c->fin_sm, s));
+    double w[FTE_MAX_BATCH], dg = 0.0;
+    HIPCHK(c, hipMemcpyAsync(w, c->cnt->w_inj, sizeof(w), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(&dg, &c->cnt->w_inj_dgamma, sizeof(dg), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    double t = 0.0;
+    for (int b = 0; b < c->p.n_batch; ++b) t += w[b];
+    *W = t;
+    *dW = dg;
+    return FTE_OK;
+}
+
+fte_status fte_bin_smoothed(fte_ctx *c, double *J, double *dJ, void *stream) {
+    if (!c) return FTE_EINVAL;
+    if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
+    if (!(c->p.sigma_x > 0.0)) return fail(c, FTE_ESTATE, "smoothed intensities are off (sigma_x = 0)");
+    if (dJ && !c->p.grad) return fail(c, FTE_ESTATE, "derivatives need gradient mode");
+    hipStream_t s = (hipStream_t)stream;
+    double W = 0.0, dW = 0.0;
+    fte_status r = smoothed_sums(c, s, &W, &dW);
+    if (r != FTE_OK) return r;
+    if (!(W > 0.0)) return fail(c, FTE_ESTATE, "no injected weight");
+    const size_t nb = (size_t)c->p.n_obs * c->p.n_e * c->p.n_t;
+    const int nk = c->p.grad ? 4 : 1;
+    std::vector<double> f(nb * nk);
+    HIPCHK(c, hipMemcpyAsync(f.data(), c->fin_sm, f.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    const double inv = 1.0 / (4.0 * kPi * W);
+    for (size_t b = 0; b < nb; ++b) {
+        const double j = f[b] * inv;
+        if (J) J[b] = j;
+        if (dJ) {
+            dJ[b] = f[nb + b] * inv;
+            dJ[nb + b] = f[2 * nb + b] * inv;
+            dJ[2 * nb + b] = f[3 * nb + b] * inv - j * dW / W;   // W_inj depends on gamma_inj
+        }
+    }
+    return FTE_OK;
+}
+
+fte_status fte_grad(fte_ctx *c, const double *dL_dJ, double grad[3], void *stream) {
+    if (!c) return FTE_EINVAL;
+    if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
+    if (!c->p.grad) return fail(c, FTE_ESTATE, "gradient mode is off");
+    if (!dL_dJ || !grad) return fail(c, FTE_EINVAL, "dL_dJ and grad must be non-NULL");
+    hipStream_t s = (hipStream_t)stream;
+    double W = 0.0, dW = 0.0;
+    fte_status r = smoothed_sums(c, s, &W, &dW);
+    if (r != FTE_OK) return r;
+    if (!(W > 0.0)) return fail(c, FTE_ESTATE, "no injected weight");
+    const size_t nb = (size_t)c->p.n_obs * c->p.n_e * c->p.n_t;
+    HIPCHK(c, hipMemcpyAsync(c->dl, dL_dJ, nb * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(c, launch_grad_contract(c->dp, c->fin_sm, c->dl, c->out4, s));
+    double o4[4];
+    HIPCHK(c, hipMemcpyAsync(o4, c->out4, sizeof(o4), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    const double inv = 1.0 / (4.0 * kPi * W);
+    grad[0] = o4[1] * inv;
+    grad[1] = o4[2] * inv;
+    grad[2] = (o4[3] - o4[0] * dW / W) * inv;
+    return FTE_OK;
+}
+
+fte_status fte_read_tangents(fte_ctx *c, double *tan, uint64_t cap, uint64_t *n_out, void *stream) {
+    if (!c) return FTE_EINVAL;
+    if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
+    if (!c->p.grad) return fail(c, FTE_ESTATE, "gradient mode is off");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long n = 0;
+    HIPCHK(c, hipMemcpyAsync(&n, &c->cnt->n_live[c->cur], sizeof(n), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (n_out) *n_out = n;
+    if (n > cap) return fail(c, FTE_ENOMEM, "host array too small");
+    if (!tan || n == 0) return FTE_OK;
+    const DevTan &t = c->tn[c->cur];
+    std::vector<double> col(n);
+    for (int q = 0; q < 11; ++q) {
+        HIPCHK(c, hipMemcpyAsync(col.data(), t.col(q), n * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        for (size_t i = 0; i < n; ++i) tan[11 * i + q] = col[i];
+    }
     return FTE_OK;
 }
 

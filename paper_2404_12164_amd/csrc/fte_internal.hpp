@@ -12,6 +12,10 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kNF = FTE_RECORD_FIELDS;
 constexpr int kRSPlain = FTE_RECORD_STRIDE;       // fields 0-9
 constexpr int kRSKperp = FTE_RECORD_STRIDE_KPERP; // fields 0-12 + pad
+// Smoothing kernels are dropped beyond this many widths, where a Gaussian has
+// fallen to 1.5e-8 of its peak: the jump at the cut then adds no visible
+// boundary term to the derivatives taken along trajectories.
+constexpr double kKernelCut = 6.0;
 
 // Device-side copy of the run parameters, pre-digested on the host.
 struct DevParams {
@@ -25,6 +29,16 @@ struct DevParams {
     double e_min, dlne, dT;
     double t_ref, inv_dT;
     double obs[FTE_MAX_OBS][6];  // r1, r2, th1, th2, phi centre, half width phi
+    // kernel-smoothed intensities (smooth != 0)
+    double obs_xyz[FTE_MAX_OBS][3];  // observer centres, Cartesian
+    double sx_cut2;          // (kKernelCut sigma_x)^2
+    double inv_2sx2, inv_sx2, norm3;   // 1/(2 sx^2), 1/sx^2, (2 pi)^-3/2 sx^-3
+    double sl_cut, inv_2sl2, inv_sl2, norm1;  // kKernelCut sl, 1/(2 sl^2), 1/sl^2, (2 pi)^-1/2 / sl
+    double sig_t;            // time-kernel width
+    double inv_lambda_ref, inv_kperp_ratio;   // explicit parameter derivatives
+    long long win_lo;        // first global step of the smoothing window
+    long long n_win;         // steps in the window
+    int smooth, grad, nk;    // nk = sums per (step, observer, energy): 4 with grad, else 1
     uint64_t seed;
     int dmm_model;
     int run_id;
@@ -58,6 +72,16 @@ struct DevState {
     int32_t *status;
 };
 
+// Tangent state of the gradient mode (struct of arrays, capacity n_max): 11
+// double arrays of `stride` entries from `base`: d(x, y, z, mu, lnp)/d lambda_ref,
+// the same with respect to kperp_ratio, and d ln w / d gamma_inj.
+struct DevTan {
+    double *base;
+    uint64_t stride;
+    __host__ __device__ double *col(int q) const { return base + (uint64_t)q * stride; }
+};
+enum : int { kTanLnw = 10 };
+
 // Device counters (live in the work buffer).
 struct DevCounters {
     unsigned long long n_live[2];
@@ -68,6 +92,7 @@ struct DevCounters {
     unsigned int flags;
     unsigned int pad;
     double w_inj[FTE_MAX_BATCH];
+    double w_inj_dgamma;     // sum of w d ln w / d gamma_inj
 };
 
 enum : unsigned int { kFlagAmrDepth = 1u, kFlagBadInput = 2u, kFlagNoLeaf = 4u };
@@ -76,6 +101,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 DevState state_view(void *base, uint64_t n_max);
 size_t state_bytes(uint64_t n_max);
+DevTan tangent_view(void *base, uint64_t n_max);
+size_t tangent_bytes(uint64_t n_max);
 
 // Kernel launchers (fte_kernels.hip).
 hipError_t launch_raw_ghost(const DevGrid &g, const double *raw, int snap, double *work_cart, DevCounters *cnt,
@@ -84,19 +111,23 @@ hipError_t launch_derive(const DevGrid &g, const double *raw, int snap, const do
                          int fp32, hipStream_t s);
 hipError_t launch_record_ghost(const DevGrid &g, int snap, void *rec, int fp32, DevCounters *cnt, hipStream_t s);
 hipError_t launch_check_raw(const DevGrid &g, const double *raw, DevCounters *cnt, hipStream_t s);
-hipError_t launch_inject(const DevParams &p, const fte_injection &inj, DevState st, DevCounters *cnt, int slot,
-                         uint64_t n, uint64_t first_pid, hipStream_t s);
+hipError_t launch_inject(const DevParams &p, const fte_injection &inj, DevState st, DevTan tn, DevCounters *cnt,
+                         int slot, uint64_t n, uint64_t first_pid, hipStream_t s);
 hipError_t launch_add_live(DevCounters *cnt, int slot, uint64_t n, hipStream_t s);
-hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevCounters *cnt, int slot, double *hist,
-                       uint64_t n0, uint32_t n_steps, uint64_t n_upper, int block, int fp32, hipStream_t s);
-hipError_t launch_compact(DevState src, DevState dst, DevCounters *cnt, int from, uint64_t n_upper, int block,
-                          hipStream_t s);
+hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
+                       double *hist, double *sm, uint64_t n0, uint32_t n_steps, uint64_t n_upper, int block, int fp32,
+                       hipStream_t s);
+hipError_t launch_compact(DevState src, DevState dst, DevTan tsrc, DevTan tdst, DevCounters *cnt, int from,
+                          uint64_t n_upper, int block, hipStream_t s);
 hipError_t launch_zero_live(DevCounters *cnt, int slot, hipStream_t s);
 uint32_t sort_keys_for(const DevGrid &g, int sort);
-hipError_t launch_compact_sorted(const DevGrid &g, int sort, DevState src, DevState dst, DevCounters *cnt, int from,
-                                 uint64_t n_upper, uint32_t *keys, uint32_t *counts, uint32_t *tsum, hipStream_t s);
+hipError_t launch_compact_sorted(const DevGrid &g, int sort, DevState src, DevState dst, DevTan tsrc, DevTan tdst,
+                                 DevCounters *cnt, int from, uint64_t n_upper, uint32_t *keys, uint32_t *counts,
+                                 uint32_t *tsum, hipStream_t s);
 hipError_t launch_finalize(const DevParams &p, const double *hist, const DevCounters *cnt, double *j, double *sig,
                            hipStream_t s);
+hipError_t launch_smooth_finalize(const DevParams &p, const double *sm, double *out, hipStream_t s);
+hipError_t launch_grad_contract(const DevParams &p, const double *fin, const double *dl, double *out4, hipStream_t s);
 hipError_t launch_zero(double *p, uint64_t n, hipStream_t s);
 hipError_t launch_zero_counters(DevCounters *cnt, hipStream_t s);
 

@@ -325,10 +325,12 @@ hipError_t launch_record_ghost(const DevGrid &g, int snap, void *rec, int fp32, 
 // ===========================================================================
 // injection
 // ===========================================================================
-__global__ void k_inject(DevParams P, fte_injection inj, DevState st, DevCounters *cnt, int slot, uint64_t n,
-                         uint64_t first_pid) {
+__global__ void k_inject(DevParams P, fte_injection inj, DevState st, DevTan tn, DevCounters *cnt, int slot,
+                         uint64_t n, uint64_t first_pid) {
     __shared__ double wsum[FTE_MAX_BATCH];
+    __shared__ double wdg;
     for (int b = threadIdx.x; b < FTE_MAX_BATCH; b += blockDim.x) wsum[b] = 0.0;
+    if (threadIdx.x == 0) wdg = 0.0;
     __syncthreads();
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
@@ -343,10 +345,11 @@ __global__ void k_inject(DevParams P, fte_injection inj, DevState st, DevCounter
         const double ct = c1 + u1 * (c2 - c1);
         const double th = ::acos(ct);
         const double ph = inj.ph_lo + u2 * (inj.ph_hi - inj.ph_lo);
-        double E, wt = inj.w0;
+        double E, wt = inj.w0, dlnw = 0.0;
         if (inj.e_hi > inj.e_lo) {
             E = ::exp(::log(inj.e_lo) + u3 * (::log(inj.e_hi) - ::log(inj.e_lo)));
             wt *= ::pow(E / inj.e_lo, 1.0 - inj.gamma_inj);
+            dlnw = -::log(E / inj.e_lo);     // d ln w / d gamma_inj
         } else {
             E = inj.e_lo;
         }
@@ -369,10 +372,16 @@ __global__ void k_inject(DevParams P, fte_injection inj, DevState st, DevCounter
         st.kinj[j] = k;
         st.status[j] = FTE_PS_ACTIVE;
         atomicAdd(&wsum[pid % (uint64_t)P.n_batch], wt);
+        if (P.grad) {
+            for (int q = 0; q < kTanLnw; ++q) tn.col(q)[j] = 0.0;
+            tn.col(kTanLnw)[j] = dlnw;
+            atomicAdd(&wdg, wt * dlnw);
+        }
     }
     __syncthreads();
     for (int b = threadIdx.x; b < P.n_batch; b += blockDim.x)
         if (wsum[b] != 0.0) atomicAdd(&cnt->w_inj[b], wsum[b]);
+    if (threadIdx.x == 0 && wdg != 0.0) atomicAdd(&cnt->w_inj_dgamma, wdg);
 }
 
 __global__ void k_add_live(DevCounters *cnt, int slot, uint64_t n) {
@@ -382,10 +391,10 @@ __global__ void k_add_live(DevCounters *cnt, int slot, uint64_t n) {
     }
 }
 
-hipError_t launch_inject(const DevParams &p, const fte_injection &inj, DevState st, DevCounters *cnt, int slot,
-                         uint64_t n, uint64_t first_pid, hipStream_t s) {
+hipError_t launch_inject(const DevParams &p, const fte_injection &inj, DevState st, DevTan tn, DevCounters *cnt,
+                         int slot, uint64_t n, uint64_t first_pid, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_inject, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, inj, st, cnt, slot, n, first_pid);
+    hipLaunchKernelGGL(k_inject, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, inj, st, tn, cnt, slot, n, first_pid);
     return hipGetLastError();
 }
 
@@ -423,9 +432,10 @@ __device__ __forceinline__ void grid_coords<float>(const DevGrid &G, double r, f
 
 // Walk the block index from level 1 down to the leaf that holds the folded
 // level-1 coordinates s.  S receives the coordinates in cells of the leaf's
-// level and B the leaf's block index; returns the leaf id or -1.
+// level, B the leaf's block index and *Lout (if given) its level; returns the
+// leaf id or -1.
 template <typename R>
-__device__ __forceinline__ int descend(const DevGrid &G, const R s[3], R S[3], int B[3]) {
+__device__ __forceinline__ int descend(const DevGrid &G, const R s[3], R S[3], int B[3], int *Lout = nullptr) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         int c = (int)M<R>::floor_(s[a]);
@@ -451,6 +461,7 @@ __device__ __forceinline__ int descend(const DevGrid &G, const R s[3], R S[3], i
         }
         node = G.child[grp * 8 + slot];
     }
+    if (Lout) *Lout = L;
     return node;
 }
 
@@ -515,6 +526,72 @@ __device__ __forceinline__ bool gather(const DevGrid &G, R s[3], int ks, R alpha
     return true;
 }
 
+// Directional derivatives of the gathered (spherical-component) fields along
+// ND tangent directions: ds[k] holds the derivative of the level-1
+// coordinates along direction k; axes clamped by the fold contribute none.
+template <typename R, bool KPERP, int ND>
+__device__ __forceinline__ bool gather_d(const DevGrid &G, R s[3], const R ds[ND][3], int ks, R alpha,
+                                         R acc[kNF], R dacc[ND][kNF]) {
+    constexpr int NF = KPERP ? 13 : 10;
+    constexpr int RS = KPERP ? kRSKperp : kRSPlain;
+    const R s_in[3] = {s[0], s[1], s[2]};
+    fold_s<R>(G, s);
+    bool live[3] = {s[0] == s_in[0], s[1] == s_in[1], G.periodic ? true : s[2] == s_in[2]};
+    int B[3], L;
+    R S[3];
+    const int leaf = descend<R>(G, s, S, B, &L);
+    if (leaf < 0) return false;
+    const R scale = (R)(1 << (L - 1));
+    R dS[ND][3];
+#pragma unroll
+    for (int k = 0; k < ND; ++k)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dS[k][a] = live[a] ? ds[k][a] * scale : (R)0;
+    int i[3];
+    R f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const R u = S[a] - (R)(B[a] * G.bx[a]) - (R)0.5;
+        const R fl = M<R>::floor_(u);
+        i[a] = (int)fl;
+        f[a] = u - fl;
+    }
+    const size_t pc = (size_t)(i[0] + 1) + (size_t)G.px[0] * ((i[1] + 1) + (size_t)G.px[1] * (i[2] + 1));
+    const size_t sx = 1, sy = G.px[0], sz = (size_t)G.px[0] * G.px[1];
+    const R *rec = reinterpret_cast<const R *>(G.rec);
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+        acc[q] = (R)0;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) dacc[k][q] = (R)0;
+    }
+    const int nsn = G.n_snap >= 2 ? 2 : 1;
+    for (int sn = 0; sn < nsn; ++sn) {
+        const R ws = (G.n_snap >= 2) ? (sn == 0 ? (R)1 - alpha : alpha) : (R)1;
+        const R *base = rec + (((size_t)(ks + sn) * G.n_leaves + leaf) * G.pcells + pc) * RS;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const int e0 = d & 1, e1 = (d >> 1) & 1, e2 = (d >> 2) & 1;
+            const R w0 = e0 ? f[0] : (R)1 - f[0], w1 = e1 ? f[1] : (R)1 - f[1], w2 = e2 ? f[2] : (R)1 - f[2];
+            const R g0 = e0 ? (R)1 : (R)-1, g1 = e1 ? (R)1 : (R)-1, g2 = e2 ? (R)1 : (R)-1;
+            const R w = ws * w0 * w1 * w2;
+            R dw[ND];
+#pragma unroll
+            for (int k = 0; k < ND; ++k)
+                dw[k] = ws * (g0 * w1 * w2 * dS[k][0] + w0 * g1 * w2 * dS[k][1] + w0 * w1 * g2 * dS[k][2]);
+            const R *p = base + (e0 * sx + e1 * sy + e2 * sz) * RS;
+#pragma unroll
+            for (int q = 0; q < NF; ++q) {
+                const R v = p[q];
+                acc[q] += w * v;
+#pragma unroll
+                for (int k = 0; k < ND; ++k) dacc[k][q] += dw[k] * v;
+            }
+        }
+    }
+    return true;
+}
+
 template <typename R>
 __device__ __forceinline__ R sgn(R x) {
     return (R)((x > (R)0) - (x < (R)0));
@@ -528,9 +605,57 @@ __device__ __forceinline__ void to_cart(R st, R ct, R sp, R cp, const R s[3], R 
     out[2] = s[0] * ct - s[1] * st;
 }
 
-template <typename R, bool KPERP>
-__global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState st, DevCounters *cnt, int slot,
-                                              double *hist, uint64_t n0, uint32_t n_steps) {
+// Derivative of a rotated vector field along a displacement with basis
+// projections (tth, tph) = (e_theta . dx, e_phi . dx) / r: the change of its
+// spherical components plus the turn of the local basis, rotated.
+template <typename R>
+__device__ __forceinline__ void d_to_cart(R st, R ct, R sp, R cp, R cot, R tth, R tph, const R a[3], const R da[3],
+                                          R out[3]) {
+    const R v[3] = {da[0] - a[1] * tth - a[2] * tph, da[1] + a[0] * tth - a[2] * cot * tph,
+                    da[2] + a[0] * tph + a[1] * cot * tph};
+    to_cart<R>(st, ct, sp, cp, v, out);
+}
+
+// Second derivative in mu of g(mu) (D_mumu = A g), the derivative of the drift
+// term dD/dmu as the step evaluates it.
+template <typename R>
+__device__ __forceinline__ R dmm_g2(const DevParams &P, R mu) {
+    const R am = mu < (R)0 ? -mu : mu;
+    if (P.dmm_model == FTE_DMM_ISO) return (R)-2;
+    if (P.dmm_model == FTE_DMM_EQ5) return (R)-2 * ((R)1 + (R)P.eps);
+    const R q = (R)P.q;
+    const R amf = am > (R)P.mu_floor ? am : (R)P.mu_floor;
+    const R om = (R)1 - mu * mu;
+    R g2 = (R)-2 * (q - (R)1) * am * M<R>::pow_(amf, q - (R)2) - (R)2 * q * M<R>::pow_(am, q - (R)1);
+    if (am > (R)P.mu_floor) g2 += (q - (R)1) * (q - (R)2) * M<R>::pow_(amf, q - (R)3) * om;
+    return g2;
+}
+
+// First derivative in mu of g(mu) itself (no floor): the change of D along
+// a pitch-angle perturbation, for the noise amplitude.
+template <typename R>
+__device__ __forceinline__ R dmm_g1(const DevParams &P, R mu) {
+    const R am = mu < (R)0 ? -mu : mu;
+    const R om = (R)1 - mu * mu;
+    if (P.dmm_model == FTE_DMM_ISO) return (R)-2 * mu;
+    if (P.dmm_model == FTE_DMM_EQ5) {
+        const R g = am / ((R)1 + am) + (R)P.eps;
+        return sgn(mu) * om / (((R)1 + am) * ((R)1 + am)) - (R)2 * mu * g;
+    }
+    const R q = (R)P.q;
+    const R amx = am > (R)0 ? am : (R)P.mu_floor;
+    return (q - (R)1) * sgn(mu) * M<R>::pow_(amx, q - (R)2) * om - (R)2 * mu * M<R>::pow_(am, q - (R)1);
+}
+
+// MODE 0: histogram estimator only.  MODE 1: also the kernel-smoothed sums.
+// MODE 2: also the pathwise tangents d(x, mu, ln p)/d(lambda_ref,
+// kperp_ratio), propagated by the derivative of the same Euler-Maruyama map
+// under the same Wiener increments, and the derivative sums of the smoothed
+// estimator.
+template <typename R, bool KPERP, int MODE>
+__global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState st, DevTan tn, DevCounters *cnt,
+                                              int slot, double *hist, double *sm, uint64_t n0, uint32_t n_steps) {
+    constexpr int ND = MODE == 2 ? 2 : 1;
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t n_live = cnt->n_live[slot];
     unsigned long long my_steps = 0;
@@ -542,13 +667,28 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
         const uint32_t kinj = st.kinj[i];
         int status = FTE_PS_ACTIVE;
         const R dt = (R)P.dt;
+        // tangents (MODE 2)
+        R TX[ND][3], TM[ND], TL[ND];
+        R dlnw = (R)0;
+        if constexpr (MODE == 2) {
+#pragma unroll
+            for (int k = 0; k < ND; ++k) {
+                TX[k][0] = (R)tn.col(5 * k + 0)[i];
+                TX[k][1] = (R)tn.col(5 * k + 1)[i];
+                TX[k][2] = (R)tn.col(5 * k + 2)[i];
+                TM[k] = (R)tn.col(5 * k + 3)[i];
+                TL[k] = (R)tn.col(5 * k + 4)[i];
+            }
+            dlnw = (R)tn.col(kTanLnw)[i];
+        }
         // spherical coordinates of the current position
         double r = ::sqrt(x * x + y * y + z * z);
         R th = M<R>::acos_((R)(z / r));
         R ph = M<R>::atan2_((R)y, (R)x);
         if (ph < (R)0) ph += (R)(2.0 * kPi);
         R Pcur = M<R>::exp_(lnp);
-        R vcur = M<R>::div_((R)kC * Pcur, M<R>::sqrt_((R)1 + Pcur * Pcur));
+        R gcur = M<R>::sqrt_((R)1 + Pcur * Pcur);
+        R vcur = M<R>::div_((R)kC * Pcur, gcur);
         const uint64_t n_end = n0 + n_steps;
         uint64_t nstart = n0 > kinj ? n0 : kinj;
         for (uint64_t n = nstart; n < n_end; ++n) {
@@ -563,16 +703,10 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
                 ks = (int)kf;
                 alpha = (R)(tau - kf);
             }
-            // ---- locate + gather + interpolate
-            R s[3];
-            grid_coords<R>(G, r, th, ph, s);
-            R acc[kNF];
-            if (!gather<R, KPERP>(G, s, ks, alpha, acc)) {
-                status = FTE_PS_NUMERIC;
-                break;
-            }
+            // basis at the particle: before the gather only when the tangents
+            // need it there (it would otherwise stay live across the gather)
             R st_, ct_, sp_, cp_;
-            {
+            auto basis_at = [&]() {
                 const R xf = (R)x, yf = (R)y, zf = (R)z;
                 const R rho = M<R>::sqrt_(xf * xf + yf * yf);
                 const R rr = (R)r;
@@ -580,6 +714,37 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
                 ct_ = M<R>::div_(zf, rr);
                 sp_ = M<R>::div_(yf, rho);
                 cp_ = M<R>::div_(xf, rho);
+            };
+            if constexpr (MODE == 2) basis_at();
+            // ---- locate + gather + interpolate
+            R s[3];
+            grid_coords<R>(G, r, th, ph, s);
+            R acc[kNF];
+            R dacc[ND][kNF];
+            R tth[ND], tph[ND], cot = (R)0;
+            if constexpr (MODE == 2) {
+                const R ir = M<R>::div_((R)1, (R)r);
+                cot = M<R>::div_(ct_, st_);
+                R ds[ND][3];
+#pragma unroll
+                for (int k = 0; k < ND; ++k) {
+                    const R ter = TX[k][0] * st_ * cp_ + TX[k][1] * st_ * sp_ + TX[k][2] * ct_;
+                    tth[k] = (TX[k][0] * ct_ * cp_ + TX[k][1] * ct_ * sp_ - TX[k][2] * st_) * ir;
+                    tph[k] = (-TX[k][0] * sp_ + TX[k][1] * cp_) * ir;
+                    ds[k][0] = ter * (R)G.inv_dxi * (G.xi_map ? ir : (R)1);
+                    ds[k][1] = tth[k] * (R)G.inv_dth;
+                    ds[k][2] = M<R>::div_(tph[k], st_) * (R)G.inv_dph;
+                }
+                if (!gather_d<R, KPERP, ND>(G, s, ds, ks, alpha, acc, dacc)) {
+                    status = FTE_PS_NUMERIC;
+                    break;
+                }
+            } else {
+                if (!gather<R, KPERP>(G, s, ks, alpha, acc)) {
+                    status = FTE_PS_NUMERIC;
+                    break;
+                }
+                basis_at();
             }
             Fields<R> F;
             to_cart<R>(st_, ct_, sp_, cp_, acc + 0, F.V);
@@ -601,6 +766,29 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
                 to_cart<R>(st_, ct_, sp_, cp_, acc + 10, F.curv);
             } else {
                 F.curv[0] = F.curv[1] = F.curv[2] = (R)0;
+            }
+            // field derivatives along each tangent
+            Fields<R> dF[ND];
+            if constexpr (MODE == 2) {
+                const R ibn = M<R>::div_((R)1, bn);
+#pragma unroll
+                for (int k = 0; k < ND; ++k) {
+                    d_to_cart<R>(st_, ct_, sp_, cp_, cot, tth[k], tph[k], acc + 0, dacc[k] + 0, dF[k].V);
+                    R dbt[3];
+                    d_to_cart<R>(st_, ct_, sp_, cp_, cot, tth[k], tph[k], acc + 3, dacc[k] + 3, dbt);
+                    const R bd = F.b[0] * dbt[0] + F.b[1] * dbt[1] + F.b[2] * dbt[2];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) dF[k].b[a] = (dbt[a] - F.b[a] * bd) * ibn;
+                    dF[k].divV = dacc[k][6];
+                    dF[k].bbgV = dacc[k][7];
+                    dF[k].divb = dacc[k][8];
+                    dF[k].bDV = dacc[k][9];
+                    if (KPERP) {
+                        d_to_cart<R>(st_, ct_, sp_, cp_, cot, tth[k], tph[k], acc + 10, dacc[k] + 10, dF[k].curv);
+                    } else {
+                        dF[k].curv[0] = dF[k].curv[1] = dF[k].curv[2] = (R)0;
+                    }
+                }
             }
             // ---- coefficients (Eqs. 2-5); P = p/(m c) and the speed are carried
             // from the previous update (the same values as exp(lnp) recomputed)
@@ -634,7 +822,8 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
             R a_x[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) a_x[a] = F.V[a] + mu * v * F.b[a] - kperp * (F.divb * F.b[a] + F.curv[a]);
-            const R a_mu = (R)0.5 * om * (v * F.divb + mu * F.divV - (R)3 * mu * F.bbgV - M<R>::div_((R)2, v) * F.bDV) + dD;
+            const R Qm = v * F.divb + mu * F.divV - (R)3 * mu * F.bbgV - M<R>::div_((R)2, v) * F.bDV;
+            const R a_mu = (R)0.5 * om * Qm + dD;
             const R a_lnp = (R)0.5 * ((R)1 - (R)3 * mu * mu) * F.bbgV - (R)0.5 * om * F.divV - M<R>::div_(mu, v) * F.bDV;
             // ---- Wiener increments: one Philox block, Box-Muller pairs
             const U4 k4 = philox_words(P.seed, P.run_id, n, pid, 0u);
@@ -647,14 +836,15 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
             const R z0 = ra * c1, z1 = ra * s1, z2 = rb * c3, z3 = rb * s3;
             // ---- Euler-Maruyama update
             double xn, yn, zn;
+            R sxn = (R)0, xib = (R)0;
             {
                 R dx[3];
                 if (KPERP) {
-                    const R xib = z1 * F.b[0] + z2 * F.b[1] + z3 * F.b[2];
-                    const R sx = M<R>::sqrt_((R)2 * kperp * dt);
-                    dx[0] = a_x[0] * dt + sx * (z1 - xib * F.b[0]);
-                    dx[1] = a_x[1] * dt + sx * (z2 - xib * F.b[1]);
-                    dx[2] = a_x[2] * dt + sx * (z3 - xib * F.b[2]);
+                    xib = z1 * F.b[0] + z2 * F.b[1] + z3 * F.b[2];
+                    sxn = M<R>::sqrt_((R)2 * kperp * dt);
+                    dx[0] = a_x[0] * dt + sxn * (z1 - xib * F.b[0]);
+                    dx[1] = a_x[1] * dt + sxn * (z2 - xib * F.b[1]);
+                    dx[2] = a_x[2] * dt + sxn * (z3 - xib * F.b[2]);
                 } else {
                     dx[0] = a_x[0] * dt;
                     dx[1] = a_x[1] * dt;
@@ -664,11 +854,71 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
                 yn = y + (double)dx[1];
                 zn = z + (double)dx[2];
             }
-            R mun = mu + a_mu * dt + M<R>::sqrt_((R)2 * D * dt) * z0;
-            if (mun > (R)1) mun = (R)2 - mun;
-            if (mun < (R)-1) mun = (R)-2 - mun;
+            const R nmu = M<R>::sqrt_((R)2 * D * dt) * z0;
+            R mun = mu + a_mu * dt + nmu;
+            R flip = (R)1;
+            if (mun > (R)1) {
+                mun = (R)2 - mun;
+                flip = -flip;
+            }
+            if (mun < (R)-1) {
+                mun = (R)-2 - mun;
+                flip = -flip;
+            }
+            if (mun > (R)1 || mun < (R)-1) flip = (R)0;
             mun = mun > (R)1 ? (R)1 : (mun < (R)-1 ? (R)-1 : mun);
             const R lnpn = lnp + a_lnp * dt;
+            // ---- tangent update: derivative of the same map
+            if constexpr (MODE == 2) {
+                const R G2 = M<R>::div_((R)1, (R)1 + Pm * Pm);     // (d v / d ln p) / v
+                const R g1 = dmm_g1<R>(P, mu), g2 = dmm_g2<R>(P, mu);
+                const R iv = M<R>::div_((R)1, v);
+                const R halfD = D > (R)0 ? M<R>::div_(nmu, (R)2 * D) : (R)0;   // d noise / d D
+#pragma unroll
+                for (int k = 0; k < ND; ++k) {
+                    const R dl = TL[k], dm = TM[k];
+                    const R dv = v * G2 * dl;
+                    R dlnA = (G2 - (R)P.alpha) * dl;
+                    R dlnK = (G2 + (R)P.alpha) * dl;
+                    if (k == 0) {
+                        dlnA -= (R)P.inv_lambda_ref;
+                        dlnK += (R)P.inv_lambda_ref;
+                    } else {
+                        dlnK += (R)P.inv_kperp_ratio;
+                    }
+                    if (!(P.kperp_ratio > 0.0)) dlnK = G2 * dl;    // kappa_perp = v lambda_perp / 3
+                    const R dD_ = D * dlnA + A * g1 * dm;            // change of D
+                    const R ddD = dD * dlnA + A * g2 * dm;           // change of dD/dmu
+                    const Fields<R> &f = dF[k];
+                    R dax[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        dax[a] = f.V[a] + (dm * v + mu * dv) * F.b[a] + mu * v * f.b[a];
+                        if (KPERP)
+                            dax[a] -= kperp * dlnK * (F.divb * F.b[a] + F.curv[a]) +
+                                      kperp * (f.divb * F.b[a] + F.divb * f.b[a] + f.curv[a]);
+                    }
+                    const R dQ = dv * F.divb + v * f.divb + dm * F.divV + mu * f.divV - (R)3 * dm * F.bbgV -
+                                 (R)3 * mu * f.bbgV + (R)2 * iv * iv * dv * F.bDV - (R)2 * iv * f.bDV;
+                    const R damu = -mu * dm * Qm + (R)0.5 * om * dQ + ddD;
+                    const R dalnp = (R)-3 * mu * dm * F.bbgV + (R)0.5 * ((R)1 - (R)3 * mu * mu) * f.bbgV +
+                                    mu * dm * F.divV - (R)0.5 * om * f.divV - dm * iv * F.bDV +
+                                    mu * dv * iv * iv * F.bDV - mu * iv * f.bDV;
+                    R dnx[3] = {(R)0, (R)0, (R)0};
+                    if (KPERP) {
+                        const R xidb = z1 * f.b[0] + z2 * f.b[1] + z3 * f.b[2];
+                        const R hk = (R)0.5 * dlnK;
+                        const R zz[3] = {z1, z2, z3};
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+                            dnx[a] = sxn * (hk * (zz[a] - xib * F.b[a]) - xidb * F.b[a] - xib * f.b[a]);
+                    }
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) TX[k][a] += dax[a] * dt + dnx[a];
+                    TM[k] = flip * (dm + damu * dt + halfD * dD_);
+                    TL[k] = dl + dalnp * dt;
+                }
+            }
             ++my_steps;
             if (!(isfinite(xn) && isfinite(yn) && isfinite(zn) && isfinite(mun) && isfinite(lnpn))) {
                 status = FTE_PS_NUMERIC;
@@ -680,7 +930,7 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
             mu = mun;
             lnp = lnpn;
             Pcur = M<R>::exp_(lnp);
-            const R gcur = M<R>::sqrt_((R)1 + Pcur * Pcur);
+            gcur = M<R>::sqrt_((R)1 + Pcur * Pcur);
             vcur = M<R>::div_((R)kC * Pcur, gcur);
             // ---- boundaries (radius in double on both paths)
             r = ::sqrt(x * x + y * y + z * z);
@@ -698,6 +948,53 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
             if (th < (R)G.th_lo || th > (R)G.th_hi) {
                 status = FTE_PS_OUT_OF_DOMAIN;
                 break;
+            }
+            // ---- kernel-smoothed sums of the post-step state, per global step
+            // (the time kernel is applied when they are read out)
+            if constexpr (MODE >= 1) {
+                const long long m = (long long)n - P.win_lo;
+                if (m >= 0 && m < P.n_win) {
+                    const R lnE = M<R>::log_((R)P.mass_c2 * M<R>::div_(Pcur * Pcur, gcur + (R)1));
+                    const R iE = M<R>::exp_(-lnE);
+                    const R base_w = (R)w * vcur * dt;
+                    const R dlE = M<R>::div_(gcur + (R)1, gcur);        // d ln E / d ln p
+                    const R G2n = M<R>::div_((R)1, gcur * gcur);       // d ln v / d ln p
+                    for (int o = 0; o < P.n_obs; ++o) {
+                        const double ddx[3] = {x - P.obs_xyz[o][0], y - P.obs_xyz[o][1], z - P.obs_xyz[o][2]};
+                        const double d2 = ddx[0] * ddx[0] + ddx[1] * ddx[1] + ddx[2] * ddx[2];
+                        if (d2 > P.sx_cut2) continue;
+                        const R g3 = M<R>::exp_((R)(-d2 * P.inv_2sx2)) * (R)P.norm3;
+                        const R c0 = base_w * g3 * iE * (R)P.norm1;
+                        R gx[ND];
+                        if constexpr (MODE == 2) {
+#pragma unroll
+                            for (int k = 0; k < ND; ++k)
+                                gx[k] = TL[k] * G2n - (R)((double)ddx[0] * (double)TX[k][0] + ddx[1] * (double)TX[k][1] +
+                                                          ddx[2] * (double)TX[k][2]) * (R)P.inv_sx2;
+                        }
+                        // energy-bin centres within the cut: a range from the
+                        // continuous centre index, the exact test per bin
+                        const R uc = (lnE - (R)P.e_min_ln) * (R)P.inv_dlne - (R)0.5;
+                        const R span = (R)P.sl_cut * (R)P.inv_dlne;
+                        int e_a = (int)M<R>::floor_(uc - span) - 1, e_b = (int)M<R>::floor_(uc + span) + 2;
+                        e_a = e_a < 0 ? 0 : e_a;
+                        e_b = e_b > P.n_e - 1 ? P.n_e - 1 : e_b;
+                        double *row = sm + ((size_t)m * P.n_obs + o) * (size_t)P.n_e * P.nk;
+                        for (int e = e_a; e <= e_b; ++e) {
+                            const R ue = lnE - (R)(P.e_min_ln + ((double)e + 0.5) * P.dlne);
+                            if (!(ue <= (R)P.sl_cut && ue >= -(R)P.sl_cut)) continue;
+                            const R c = c0 * M<R>::exp_(-ue * ue * (R)P.inv_2sl2);
+                            double *cell = row + (size_t)e * P.nk;
+                            atomicAdd(cell, (double)c);
+                            if constexpr (MODE == 2) {
+                                const R fe = (-ue * (R)P.inv_sl2 - (R)1) * dlE;
+#pragma unroll
+                                for (int k = 0; k < ND; ++k) atomicAdd(cell + 1 + k, (double)(c * (gx[k] + fe * TL[k])));
+                                atomicAdd(cell + 3, (double)(c * dlnw));
+                            }
+                        }
+                    }
+                }
             }
             // ---- residence-time observer estimator, post-step state: the box
             // tests come first, the energy bin only for a particle inside one
@@ -727,6 +1024,16 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
         st.z[i] = z;
         st.mu[i] = (double)mu;
         st.lnp[i] = (double)lnp;
+        if constexpr (MODE == 2) {
+#pragma unroll
+            for (int k = 0; k < ND; ++k) {
+                tn.col(5 * k + 0)[i] = (double)TX[k][0];
+                tn.col(5 * k + 1)[i] = (double)TX[k][1];
+                tn.col(5 * k + 2)[i] = (double)TX[k][2];
+                tn.col(5 * k + 3)[i] = (double)TM[k];
+                tn.col(5 * k + 4)[i] = (double)TL[k];
+            }
+        }
         if (status != FTE_PS_ACTIVE) {
             st.status[i] = status;
             atomicAdd(&cnt->retired[status], 1ull);
@@ -747,21 +1054,29 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
     }
 }
 
-hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevCounters *cnt, int slot, double *hist,
-                       uint64_t n0, uint32_t n_steps, uint64_t n_upper, int block, int fp32, hipStream_t s) {
+template <typename R, bool KPERP>
+static void launch_step_t(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
+                          double *hist, double *sm, uint64_t n0, uint32_t n_steps, dim3 grid, dim3 blk, hipStream_t s) {
+    if (p.grad)
+        hipLaunchKernelGGL((k_step<R, KPERP, 2>), grid, blk, 0, s, p, g, st, tn, cnt, slot, hist, sm, n0, n_steps);
+    else if (p.smooth)
+        hipLaunchKernelGGL((k_step<R, KPERP, 1>), grid, blk, 0, s, p, g, st, tn, cnt, slot, hist, sm, n0, n_steps);
+    else
+        hipLaunchKernelGGL((k_step<R, KPERP, 0>), grid, blk, 0, s, p, g, st, tn, cnt, slot, hist, sm, n0, n_steps);
+}
+
+hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
+                       double *hist, double *sm, uint64_t n0, uint32_t n_steps, uint64_t n_upper, int block, int fp32,
+                       hipStream_t s) {
     if (n_upper == 0 || n_steps == 0) return hipSuccess;
     const bool kp = p.kperp_ratio > 0.0 || p.lambda_perp > 0.0;
     dim3 grid(blocks_for(n_upper, block)), blk(block);
     if (fp32) {
-        if (kp)
-            hipLaunchKernelGGL((k_step<float, true>), grid, blk, 0, s, p, g, st, cnt, slot, hist, n0, n_steps);
-        else
-            hipLaunchKernelGGL((k_step<float, false>), grid, blk, 0, s, p, g, st, cnt, slot, hist, n0, n_steps);
+        if (kp) launch_step_t<float, true>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, s);
+        else launch_step_t<float, false>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, s);
     } else {
-        if (kp)
-            hipLaunchKernelGGL((k_step<double, true>), grid, blk, 0, s, p, g, st, cnt, slot, hist, n0, n_steps);
-        else
-            hipLaunchKernelGGL((k_step<double, false>), grid, blk, 0, s, p, g, st, cnt, slot, hist, n0, n_steps);
+        if (kp) launch_step_t<double, true>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, s);
+        else launch_step_t<double, false>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, s);
     }
     return hipGetLastError();
 }
@@ -773,7 +1088,13 @@ __global__ void k_zero_live(DevCounters *cnt, int slot) {
     if (threadIdx.x == 0 && blockIdx.x == 0) cnt->n_live[slot] = 0;
 }
 
-__global__ void k_compact(DevState src, DevState dst, DevCounters *cnt, int from) {
+__device__ __forceinline__ void copy_tangent(const DevTan &a, const DevTan &b, uint64_t i, uint64_t j) {
+    if (!a.base) return;
+#pragma unroll
+    for (int q = 0; q <= kTanLnw; ++q) b.col(q)[j] = a.col(q)[i];
+}
+
+__global__ void k_compact(DevState src, DevState dst, DevTan tsrc, DevTan tdst, DevCounters *cnt, int from) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t n_live = cnt->n_live[from];
     const bool alive = i < n_live && src.status[i] == FTE_PS_ACTIVE;
@@ -795,6 +1116,7 @@ __global__ void k_compact(DevState src, DevState dst, DevCounters *cnt, int from
         dst.pid[j] = src.pid[i];
         dst.kinj[j] = src.kinj[i];
         dst.status[j] = FTE_PS_ACTIVE;
+        copy_tangent(tsrc, tdst, i, j);
     }
 }
 
@@ -803,10 +1125,11 @@ hipError_t launch_zero_live(DevCounters *cnt, int slot, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_compact(DevState src, DevState dst, DevCounters *cnt, int from, uint64_t n_upper, int block,
-                          hipStream_t s) {
+hipError_t launch_compact(DevState src, DevState dst, DevTan tsrc, DevTan tdst, DevCounters *cnt, int from,
+                          uint64_t n_upper, int block, hipStream_t s) {
     if (n_upper == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_compact, dim3(blocks_for(n_upper, block)), dim3(block), 0, s, src, dst, cnt, from);
+    hipLaunchKernelGGL(k_compact, dim3(blocks_for(n_upper, block)), dim3(block), 0, s, src, dst, tsrc, tdst, cnt,
+                       from);
     return hipGetLastError();
 }
 
@@ -912,8 +1235,8 @@ __global__ void k_scan_add(uint32_t *counts, uint32_t nk, const uint32_t *tsum) 
     if (i < nk) counts[i] += tsum[i / kScanTile];
 }
 
-__global__ void k_sort_scatter(DevState src, DevState dst, const DevCounters *cnt, int from, const uint32_t *keys,
-                               uint32_t *cursor) {
+__global__ void k_sort_scatter(DevState src, DevState dst, DevTan tsrc, DevTan tdst, const DevCounters *cnt,
+                               int from, const uint32_t *keys, uint32_t *cursor) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cnt->n_live[from]) return;
     const uint32_t k = keys[i];
@@ -928,6 +1251,7 @@ __global__ void k_sort_scatter(DevState src, DevState dst, const DevCounters *cn
     dst.pid[j] = src.pid[i];
     dst.kinj[j] = src.kinj[i];
     dst.status[j] = FTE_PS_ACTIVE;
+    copy_tangent(tsrc, tdst, i, j);
 }
 
 __global__ void k_zero_u32(uint32_t *p, uint32_t n) {
@@ -940,8 +1264,9 @@ uint32_t sort_keys_for(const DevGrid &g, int sort) {
     return (uint32_t)g.n_leaves * (uint32_t)((g.bx[0] >> sh) * (g.bx[1] >> sh) * (g.bx[2] >> sh));
 }
 
-hipError_t launch_compact_sorted(const DevGrid &g, int sort, DevState src, DevState dst, DevCounters *cnt, int from,
-                                 uint64_t n_upper, uint32_t *keys, uint32_t *counts, uint32_t *tsum, hipStream_t s) {
+hipError_t launch_compact_sorted(const DevGrid &g, int sort, DevState src, DevState dst, DevTan tsrc, DevTan tdst,
+                                 DevCounters *cnt, int from, uint64_t n_upper, uint32_t *keys, uint32_t *counts,
+                                 uint32_t *tsum, hipStream_t s) {
     const uint32_t nk = sort_keys_for(g, sort);
     const uint32_t ntile = (nk + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_zero_u32, dim3(blocks_for(nk, 256)), dim3(256), 0, s, counts, nk);
@@ -952,8 +1277,8 @@ hipError_t launch_compact_sorted(const DevGrid &g, int sort, DevState src, DevSt
     hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, tsum, ntile, cnt, 1 - from);
     hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(nk, 256)), dim3(256), 0, s, counts, nk, tsum);
     if (n_upper > 0)
-        hipLaunchKernelGGL(k_sort_scatter, dim3(blocks_for(n_upper, 256)), dim3(256), 0, s, src, dst, cnt, from, keys,
-                           counts);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(blocks_for(n_upper, 256)), dim3(256), 0, s, src, dst, tsrc, tdst, cnt,
+                           from, keys, counts);
     return hipGetLastError();
 }
 
@@ -991,6 +1316,65 @@ hipError_t launch_finalize(const DevParams &p, const double *hist, const DevCoun
     const int n = p.n_obs * p.n_e * p.n_t;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, hist, cnt, j, sig);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// smoothed intensities: time kernel over the per-step sums
+// ===========================================================================
+// out[k][o][e][t] = sum over the window's steps n of
+//   G1(t0 + (n+1) dt - t_t) sums[n][o][e][k], dropping |.| > kKernelCut sigma_t.
+__global__ void k_smooth_finalize(DevParams P, const double *sm, double *out) {
+    const int nb = P.n_obs * P.n_e * P.n_t;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nb * P.nk) return;
+    const int k = idx / nb, b = idx % nb;
+    const int o = b / (P.n_e * P.n_t), e = (b / P.n_t) % P.n_e, it = b % P.n_t;
+    const double tc = P.t_ref + ((double)it + 0.5) * P.dT;
+    const double cut = kKernelCut * P.sig_t;
+    long long na = (long long)::floor((tc - cut - P.t0) / P.dt) - 2;
+    long long nb_ = (long long)::ceil((tc + cut - P.t0) / P.dt) + 1;
+    na = na < P.win_lo ? P.win_lo : na;
+    nb_ = nb_ > P.win_lo + P.n_win - 1 ? P.win_lo + P.n_win - 1 : nb_;
+    const double norm = 1.0 / (::sqrt(2.0 * kPi) * P.sig_t);
+    double s = 0.0;
+    for (long long n = na; n <= nb_; ++n) {
+        const double ut = (P.t0 + (double)(n + 1) * P.dt) - tc;
+        if (::fabs(ut) > cut) continue;
+        const double kt = ::exp(-ut * ut / (2.0 * P.sig_t * P.sig_t)) * norm;
+        s += kt * sm[(((size_t)(n - P.win_lo) * P.n_obs + o) * P.n_e + e) * P.nk + k];
+    }
+    out[idx] = s;
+}
+
+hipError_t launch_smooth_finalize(const DevParams &p, const double *sm, double *out, hipStream_t s) {
+    const int n = p.n_obs * p.n_e * p.n_t * p.nk;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_smooth_finalize, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, sm, out);
+    return hipGetLastError();
+}
+
+// out4[k] = sum over bins of dl[bin] fin[k][bin], k = 0..3 (one workgroup).
+__global__ void __launch_bounds__(256) k_grad_contract(int nb, const double *fin, const double *dl, double *out4) {
+    __shared__ double red[4][256];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const double g = dl[b];
+        for (int k = 0; k < 4; ++k) a[k] += g * fin[(size_t)k * nb + b];
+    }
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = a[k];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out4[threadIdx.x] = red[threadIdx.x][0];
+}
+
+hipError_t launch_grad_contract(const DevParams &p, const double *fin, const double *dl, double *out4, hipStream_t s) {
+    const int nb = p.n_obs * p.n_e * p.n_t;
+    hipLaunchKernelGGL(k_grad_contract, dim3(1), dim3(256), 0, s, nb, fin, dl, out4);
     return hipGetLastError();
 }
 

@@ -27,7 +27,8 @@ RECORD_FIELDS = 13
 STATUS = {"active": 0, "absorbed_in": 1, "absorbed_out": 2, "out_of_domain": 3, "numeric": 4}
 SYMBOLS = ["fte_create", "fte_destroy", "fte_last_error", "fte_query_sizes", "fte_bind_buffers", "fte_load_grid",
            "fte_inject", "fte_step_n", "fte_bin_observers", "fte_read_hist", "fte_get_stats", "fte_read_particles",
-           "fte_set_launch", "fte_reset", "fte_set_timing"]
+           "fte_set_launch", "fte_reset", "fte_set_timing", "fte_bin_smoothed", "fte_grad", "fte_read_tangents"]
+TANGENT_COLS = 11         # d(x, y, z, mu, lnp)/d lambda_ref, the same for kperp_ratio, d ln w / d gamma_inj
 
 
 class fte_observer(C.Structure):
@@ -44,7 +45,8 @@ class fte_params(C.Structure):
                 ("seed", C.c_uint64), ("run_id", C.c_int), ("precision", C.c_int),
                 ("n_obs", C.c_int), ("obs", fte_observer * MAX_OBS),
                 ("e_min", C.c_double), ("dlne", C.c_double), ("n_e", C.c_int),
-                ("t_ref", C.c_double), ("dT", C.c_double), ("n_t", C.c_int), ("n_batch", C.c_int)]
+                ("t_ref", C.c_double), ("dT", C.c_double), ("n_t", C.c_int), ("n_batch", C.c_int),
+                ("sigma_x", C.c_double), ("sigma_lne", C.c_double), ("sigma_t", C.c_double), ("grad", C.c_int)]
 
 
 class fte_grid_desc(C.Structure):
@@ -64,12 +66,12 @@ class fte_injection(C.Structure):
 
 class fte_sizes(C.Structure):
     _fields_ = [("grid_bytes", C.c_uint64), ("index_bytes", C.c_uint64), ("state_bytes", C.c_uint64),
-                ("hist_bytes", C.c_uint64), ("work_bytes", C.c_uint64)]
+                ("hist_bytes", C.c_uint64), ("work_bytes", C.c_uint64), ("tangent_bytes", C.c_uint64)]
 
 
 class fte_buffers(C.Structure):
     _fields_ = [("grid", C.c_void_p), ("index", C.c_void_p), ("state_a", C.c_void_p), ("state_b", C.c_void_p),
-                ("hist", C.c_void_p), ("work", C.c_void_p)]
+                ("hist", C.c_void_p), ("work", C.c_void_p), ("tangent_a", C.c_void_p), ("tangent_b", C.c_void_p)]
 
 
 class fte_stats(C.Structure):
@@ -109,6 +111,9 @@ def lib():
         L.fte_set_launch.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
         L.fte_reset.argtypes = [vp, vp]
         L.fte_set_timing.argtypes = [vp, C.c_int]
+        L.fte_bin_smoothed.argtypes = [vp, dp, dp, vp]
+        L.fte_grad.argtypes = [vp, dp, dp, vp]
+        L.fte_read_tangents.argtypes = [vp, dp, u64, C.POINTER(C.c_uint64), vp]
         for name in SYMBOLS:
             if name not in ("fte_destroy", "fte_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -158,6 +163,10 @@ def make_params(p: dict) -> fte_params:
     o.dT = p.get("dT", 1.0)
     o.n_t = int(p.get("n_t", 1))
     o.n_batch = int(p.get("n_batch", 32))
+    sm = p.get("smoothing")
+    if sm:
+        o.sigma_x, o.sigma_lne, o.sigma_t = sm["sigma_x"], sm["sigma_lne"], sm["sigma_t"]
+    o.grad = int(p.get("grad", 0))
     return o
 
 
@@ -291,6 +300,32 @@ def fte_read_particles(ctx, cap: int, stream: int) -> dict:
     return dict(x=x[:k], mu=mu[:k], lnp=lnp[:k], w=w[:k], pid=pid[:k], kinj=kinj[:k], status=status[:k])
 
 
+def fte_bin_smoothed(ctx, shape, grad: bool, stream: int):
+    n = int(np.prod(shape))
+    J = np.zeros(max(n, 1))
+    dJ = np.zeros((3, max(n, 1))) if grad else None
+    dp = C.POINTER(C.c_double)
+    _check(ctx, lib().fte_bin_smoothed(ctx, J.ctypes.data_as(dp), dJ.ctypes.data_as(dp) if grad else None,
+                                       C.c_void_p(stream)))
+    return J[:n].reshape(shape), (dJ[:, :n].reshape((3,) + tuple(shape)) if grad else None)
+
+
+def fte_grad(ctx, dL_dJ, stream: int):
+    g = np.ascontiguousarray(dL_dJ, dtype=np.float64).ravel()
+    out = np.zeros(3)
+    dp = C.POINTER(C.c_double)
+    _check(ctx, lib().fte_grad(ctx, g.ctypes.data_as(dp), out.ctypes.data_as(dp), C.c_void_p(stream)))
+    return out
+
+
+def fte_read_tangents(ctx, cap: int, stream: int):
+    t = np.zeros((max(cap, 1), TANGENT_COLS))
+    n = C.c_uint64()
+    _check(ctx, lib().fte_read_tangents(ctx, t.ctypes.data_as(C.POINTER(C.c_double)), int(cap), C.byref(n),
+                                        C.c_void_p(stream)))
+    return t[: n.value]
+
+
 def fte_set_launch(ctx, block: int, steps_per_launch: int, compact_every: int, spatial_sort: int = 2):
     _check(ctx, lib().fte_set_launch(ctx, int(block), int(steps_per_launch), int(compact_every), int(spatial_sort)))
 
@@ -328,8 +363,13 @@ class Simulation:
         self.t_state_b = buf(s.state_bytes)
         self.t_hist = buf(s.hist_bytes)
         self.t_work = buf(s.work_bytes)
+        self.grad = bool(int(params.get("grad", 0)))
+        self.t_tan_a = buf(s.tangent_bytes) if self.grad else None
+        self.t_tan_b = buf(s.tangent_bytes) if self.grad else None
         self.bufs = fte_buffers(self.t_grid.data_ptr(), self.t_index.data_ptr(), self.t_state_a.data_ptr(),
-                                self.t_state_b.data_ptr(), self.t_hist.data_ptr(), self.t_work.data_ptr())
+                                self.t_state_b.data_ptr(), self.t_hist.data_ptr(), self.t_work.data_ptr(),
+                                self.t_tan_a.data_ptr() if self.grad else None,
+                                self.t_tan_b.data_ptr() if self.grad else None)
         self.ctx = fte_create(params)
         fte_bind_buffers(self.ctx, grid, n_max, self.bufs)
         self.n_bins = (len(params.get("observers", [])), int(params.get("n_e", 1)), int(params.get("n_t", 1)))
@@ -375,6 +415,17 @@ class Simulation:
         n = int(np.prod(self.n_bins)) * int(self.params.get("n_batch", 32))
         return fte_read_hist(self.ctx, n, self.stream)
 
+    def bin_smoothed(self):
+        """Smoothed intensities J[o][e][t] and (gradient mode) dJ[3][o][e][t]."""
+        return fte_bin_smoothed(self.ctx, self.n_bins, self.grad, self.stream)
+
+    def grad_of(self, dL_dJ):
+        """Gradient of a loss with respect to (lambda_ref, kperp_ratio, gamma_inj)."""
+        return fte_grad(self.ctx, dL_dJ, self.stream)
+
+    def tangents(self):
+        return fte_read_tangents(self.ctx, self.n_max, self.stream)
+
     def stats(self) -> fte_stats:
         return fte_get_stats(self.ctx, self.stream)
 
@@ -402,3 +453,62 @@ class Simulation:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------------------
+# differentiable smoothed intensities (torch.autograd)
+# ----------------------------------------------------------------------------
+def run_gradient(params: dict, grid: dict, vb_sph, injection: dict, n_particles: int, n_steps: int,
+                 first_pid: int = 0, launch=None) -> "Simulation":
+    """A gradient-mode Simulation after injecting ``n_particles`` and taking
+    ``n_steps`` global steps; params must hold "smoothing" and grad=1."""
+    sim = Simulation(dict(params, grad=1), grid, n_particles)
+    sim.load_grid(vb_sph)
+    if launch:
+        sim.set_launch(*launch)
+    sim.inject(injection, n_particles, first_pid)
+    sim.step(n_steps)
+    return sim
+
+
+_Fn = None
+
+
+def _function():
+    global _Fn
+    if _Fn is None:
+        import torch
+
+        class SmoothedIntensity(torch.autograd.Function):
+            """J(theta) for theta = (lambda_ref, kperp_ratio, gamma_inj): the
+            forward pass runs the workload in gradient mode and returns the
+            smoothed intensities; the backward pass contracts the incoming
+            dL/dJ on the device (fte_grad)."""
+
+            @staticmethod
+            def forward(ctx, theta, params, grid, vb_sph, injection, n_particles, n_steps, first_pid, launch):
+                lam, kr, gam = (float(v) for v in theta.detach().cpu().tolist())
+                p = dict(params, lambda_ref=lam, kperp_ratio=kr)
+                inj = dict(injection, gamma_inj=gam)
+                sim = run_gradient(p, grid, vb_sph, inj, n_particles, n_steps, first_pid, launch)
+                J, _ = sim.bin_smoothed()
+                ctx.sim = sim
+                return torch.as_tensor(J, dtype=theta.dtype, device=theta.device)
+
+            @staticmethod
+            def backward(ctx, gJ):
+                sim = ctx.sim
+                g = sim.grad_of(gJ.detach().cpu().numpy())
+                sim.close()
+                ctx.sim = None
+                return (torch.as_tensor(g, dtype=gJ.dtype, device=gJ.device),) + (None,) * 8
+
+        _Fn = SmoothedIntensity
+    return _Fn
+
+
+def smoothed_intensity(theta, params: dict, grid: dict, vb_sph, injection: dict, n_particles: int, n_steps: int,
+                       first_pid: int = 0, launch=None):
+    """Differentiable J[o][e][t] as a function of the tensor theta =
+    (lambda_ref, kperp_ratio, gamma_inj); backward gives dL/dtheta."""
+    return _function().apply(theta, params, grid, vb_sph, injection, n_particles, n_steps, first_pid, launch)
