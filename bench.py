@@ -120,6 +120,80 @@ def timed(run, K, chunk):
     return dict(ms=ms, wall=wall, particle_steps=int(steps), kernel_ms=kms, launches=int(nl), stats=st1)
 
 
+def gradient_leg(F, W, raw, args):
+    """Differentiation workload (10^6 protons, 8,000 steps, smoothed
+    intensities at the three 1-au observers): time of the plain forward pass,
+    of the forward pass with smoothed sums, and of the gradient pass (tangents
+    + derivative sums), each over the whole run; then the gradient of two
+    losses against central differences (h = 1e-3, common random numbers) of
+    the smoothed forward pass on the GPU."""
+    import torch
+    cfg = W.cir_differentiation(precision=args.precision)
+    n_steps = cfg["n_steps"]
+    chunk = n_steps // 10
+    p_grad = cfg["params"]
+    p_smooth = dict(p_grad, grad=0)
+    p_plain = {k: v for k, v in p_grad.items() if k not in ("smoothing", "grad")}
+
+    def run(params, inj=None, timed_run=True):
+        c = dict(cfg, params=params, injection=inj or cfg["injection"])
+        r = Run(F, c, raw, args.precision, args.block, args.spl, args.compact, args.sort)
+        res = timed(r, 10, chunk) if timed_run else None
+        return r, res
+
+    out = {"workload": cfg["name"], "particles": cfg["n_particles"], "global_steps": n_steps}
+    r, res = run(p_plain)
+    r.close()
+    # warm the other two modes once, untimed, then time them
+    for params in (p_smooth, p_grad):
+        r, _ = run(params, timed_run=False)
+        r.chunk(chunk)
+        torch.cuda.synchronize()
+        r.close()
+    r, res = run(p_plain)
+    out["forward_ms"] = round(res["ms"], 2)
+    out["forward_particle_steps"] = res["particle_steps"]
+    r.close()
+    r, res = run(p_smooth)
+    out["forward_smoothed_ms"] = round(res["ms"], 2)
+    r.close()
+    r, res = run(p_grad)
+    out["gradient_ms"] = round(res["ms"], 2)
+    out["gradient_kernel_ms"] = round(res["kernel_ms"], 2)
+    J, dJ = r.sim.bin_smoothed()
+    rng = np.random.default_rng(3)
+    losses = [np.ones(J.shape), rng.random(J.shape)]
+    g_dev = [r.sim.grad_of(w) for w in losses]
+    r.close()
+    out["grad_over_forward"] = round(out["gradient_ms"] / out["forward_ms"], 3)
+    out["grad_over_smoothed_forward"] = round(out["gradient_ms"] / out["forward_smoothed_ms"], 3)
+    # central differences with common random numbers
+    h = 1e-3
+    fd = []
+    for key in ("lambda_ref", "kperp_ratio", "gamma_inj"):
+        Js = []
+        for sgn in (1, -1):
+            if key == "gamma_inj":
+                base = cfg["injection"]["gamma_inj"]
+                rr, _ = run(p_smooth, inj=dict(cfg["injection"], gamma_inj=base * (1 + sgn * h)), timed_run=False)
+            else:
+                base = p_grad[key]
+                rr, _ = run(dict(p_smooth, **{key: base * (1 + sgn * h)}), timed_run=False)
+            for _ in range(10):
+                rr.chunk(chunk)
+            Js.append(rr.sim.bin_smoothed()[0])
+            rr.close()
+        fd.append((Js[0] - Js[1]) / (2 * h * base))
+    rel = []
+    for w, gd in zip(losses, g_dev):
+        gf = np.array([(f * w).sum() for f in fd])
+        rel.append([float(abs(a - b) / abs(b)) if b != 0 else None for a, b in zip(gd, gf)])
+    out["grad_sum_J"] = [float(v) for v in g_dev[0]]
+    out["fd_rel_err"] = rel
+    out["J_nonzero"] = int((J > 0).sum())
+    return out
+
+
 def cpu_baseline(cfg, raw_gpu, n_pids, n_steps, n_threads):
     """The FP64 oracle on the first n_pids particles over the first n_steps
     steps, with the snapshots those steps touch copied to the host."""
@@ -156,6 +230,7 @@ def main():
     ap.add_argument("--sort", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--cpu-pids", type=int, default=4000)
     ap.add_argument("--cpu-steps", type=int, default=2800)
     ap.add_argument("--calib-copy", action="store_true", help="also run a 2 GiB device copy (counter calibration)")
@@ -239,6 +314,10 @@ def main():
         b64 = 8 * T_s * F_fields * 8 + 2 * 64 / args.spl
         extra["fp64_roofline_frac"] = round(b64 * res64["particle_steps"] / (res64["kernel_ms"] / 1e3) / 1e9
                                             / HBM_PEAK_GBS, 4)
+
+    if not args.no_grad:
+        log("differentiation workload: forward, smoothed forward, gradient, central differences")
+        extra["gradient"] = gradient_leg(F, W, raw, args)
 
     cpu = None
     if not args.no_cpu:
