@@ -295,6 +295,21 @@ fte_status fte_grad(fte_ctx *ctx, const double *dL_dJ, double grad[3], void *str
  * below n_live); *n_out receives n_live.  Synchronises. */
 fte_status fte_read_tangents(fte_ctx *ctx, double *tan, uint64_t cap, uint64_t *n_out, void *stream);
 
+/* Checkpoint / resume.  A state blob holds the held particles (and tangents
+ * in gradient mode), the global step, the device counters, the observer sums
+ * and the smoothed sums; not the grid, which the resuming context loads
+ * itself.  fte_state_size gives the blob size for the current state
+ * (synchronises).  fte_save_state writes it to a HOST buffer of `bytes`
+ * (FTE_ENOMEM if too small).  fte_load_state restores it into a context
+ * with the same parameters (checked by a fingerprint of the parameters that
+ * shape the trajectories and sums), the same grid shape and capacity >= the
+ * saved particle count, after fte_load_grid; FTE_EINVAL on a mismatch or a
+ * damaged blob.  Stepping on from a restored state gives the trajectories of
+ * an uninterrupted run (they depend only on pid and step). */
+fte_status fte_state_size(fte_ctx *ctx, uint64_t *bytes, void *stream);
+fte_status fte_save_state(fte_ctx *ctx, void *host_blob, uint64_t bytes, void *stream);
+fte_status fte_load_state(fte_ctx *ctx, const void *host_blob, uint64_t bytes, void *stream);
+
 /* Drop all particles, observer sums, counters and timings and rewind the
  * global clock to step 0; the loaded grid stays.  Synchronises. */
 fte_status fte_reset(fte_ctx *ctx, void *stream);

@@ -897,6 +897,182 @@ fte_status fte_read_tangents(fte_ctx *c, double *tan, uint64_t cap, uint64_t *n_
     return FTE_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// checkpoint / resume
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr uint64_t kStateMagic = 0x3145544154534654ull;   // "FTSTATE1"
+
+struct StateHeader {
+    uint64_t magic;
+    uint64_t fingerprint;     // parameters and grid shape
+    uint64_t n_live;
+    uint64_t global_step;
+    uint64_t hist_n, sm_n;
+    uint32_t grad, pad;
+    uint64_t total_bytes;
+};
+
+uint64_t fnv_mix(uint64_t h, const void *p, size_t n) {
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+template <typename T>
+uint64_t fnv_val(uint64_t h, T v) { return fnv_mix(h, &v, sizeof(v)); }
+
+uint64_t state_fingerprint(const fte_ctx *c) {
+    const fte_params &p = c->p;
+    uint64_t h = 1469598103934665603ull;
+    h = fnv_val(h, p.mass); h = fnv_val(h, p.dmm_model); h = fnv_val(h, p.dmm_norm);
+    h = fnv_val(h, p.lambda_ref); h = fnv_val(h, p.p_ref); h = fnv_val(h, p.alpha); h = fnv_val(h, p.q);
+    h = fnv_val(h, p.eps); h = fnv_val(h, p.mu_floor); h = fnv_val(h, p.kperp_ratio); h = fnv_val(h, p.lambda_perp);
+    h = fnv_val(h, p.dt); h = fnv_val(h, p.t0); h = fnv_val(h, p.r_in); h = fnv_val(h, p.r_out);
+    h = fnv_val(h, p.seed); h = fnv_val(h, p.run_id); h = fnv_val(h, p.precision); h = fnv_val(h, p.n_obs);
+    for (int o = 0; o < p.n_obs; ++o) h = fnv_mix(h, &p.obs[o], sizeof(fte_observer));
+    h = fnv_val(h, p.e_min); h = fnv_val(h, p.dlne); h = fnv_val(h, p.n_e); h = fnv_val(h, p.t_ref);
+    h = fnv_val(h, p.dT); h = fnv_val(h, p.n_t); h = fnv_val(h, p.n_batch);
+    h = fnv_val(h, p.sigma_x); h = fnv_val(h, p.sigma_lne); h = fnv_val(h, p.sigma_t); h = fnv_val(h, p.grad);
+    h = fnv_val(h, c->g.n_leaves); h = fnv_val(h, c->g.n_snap); h = fnv_val(h, c->g.n_levels);
+    for (int a = 0; a < 3; ++a) { h = fnv_val(h, c->g.n1[a]); h = fnv_val(h, c->g.bx[a]); }
+    return h;
+}
+
+// SoA columns of the particle state: (device pointer, element bytes)
+int state_columns(const DevState &d, void *col[9], size_t esz[9]) {
+    void *v[9] = {d.x, d.y, d.z, d.mu, d.lnp, d.w, d.pid, d.kinj, d.status};
+    const size_t e[9] = {8, 8, 8, 8, 8, 8, 8, 4, 4};
+    for (int k = 0; k < 9; ++k) { col[k] = v[k]; esz[k] = e[k]; }
+    return 9;
+}
+
+uint64_t state_blob_bytes(const fte_ctx *c, uint64_t n) {
+    uint64_t b = sizeof(StateHeader) + sizeof(DevCounters) + (c->hist_n + c->sm_n) * 8 + n * (6 * 8 + 8 + 4 + 4);
+    if (c->p.grad) b += n * (kTanLnw + 1) * 8;
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+fte_status fte_state_size(fte_ctx *c, uint64_t *bytes, void *stream) {
+    if (!c || !bytes) return FTE_EINVAL;
+    if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long n = 0;
+    HIPCHK(c, hipMemcpyAsync(&n, &c->cnt->n_live[c->cur], sizeof(n), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    *bytes = state_blob_bytes(c, n);
+    return FTE_OK;
+}
+
+fte_status fte_save_state(fte_ctx *c, void *blob, uint64_t bytes, void *stream) {
+    if (!c || !blob) return FTE_EINVAL;
+    if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
+    hipStream_t s = (hipStream_t)stream;
+    DevCounters h;
+    HIPCHK(c, hipMemcpyAsync(&h, c->cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    const uint64_t n = h.n_live[c->cur];
+    const uint64_t need = state_blob_bytes(c, n);
+    if (bytes < need) return fail(c, FTE_ENOMEM, "state blob too small");
+    char *o = (char *)blob;
+    StateHeader hd{};
+    hd.magic = kStateMagic;
+    hd.fingerprint = state_fingerprint(c);
+    hd.n_live = n;
+    hd.global_step = c->global_step;
+    hd.hist_n = c->hist_n;
+    hd.sm_n = c->sm_n;
+    hd.grad = (uint32_t)c->p.grad;
+    hd.total_bytes = need;
+    // the counters as a compacted state: everything held sits in slot 0
+    h.n_live[0] = n;
+    h.n_live[1] = 0;
+    memcpy(o, &hd, sizeof(hd));
+    o += sizeof(hd);
+    memcpy(o, &h, sizeof(h));
+    o += sizeof(h);
+    if (c->hist_n) HIPCHK(c, hipMemcpyAsync(o, c->b.hist, c->hist_n * 8, hipMemcpyDeviceToHost, s));
+    o += c->hist_n * 8;
+    if (c->sm_n) HIPCHK(c, hipMemcpyAsync(o, c->sm, c->sm_n * 8, hipMemcpyDeviceToHost, s));
+    o += c->sm_n * 8;
+    void *col[9];
+    size_t esz[9];
+    const int nc = state_columns(c->st[c->cur], col, esz);
+    for (int k = 0; k < nc; ++k) {
+        if (n) HIPCHK(c, hipMemcpyAsync(o, col[k], n * esz[k], hipMemcpyDeviceToHost, s));
+        o += n * esz[k];
+    }
+    if (c->p.grad)
+        for (int q = 0; q <= kTanLnw; ++q) {
+            if (n) HIPCHK(c, hipMemcpyAsync(o, c->tn[c->cur].col(q), n * 8, hipMemcpyDeviceToHost, s));
+            o += n * 8;
+        }
+    HIPCHK(c, hipStreamSynchronize(s));
+    return FTE_OK;
+}
+
+fte_status fte_load_state(fte_ctx *c, const void *blob, uint64_t bytes, void *stream) {
+    if (!c || !blob) return FTE_EINVAL;
+    if (!c->loaded) return fail(c, FTE_ESTATE, "load the grid before restoring a state");
+    if (bytes < sizeof(StateHeader)) return fail(c, FTE_EINVAL, "state blob too short");
+    StateHeader hd;
+    memcpy(&hd, blob, sizeof(hd));
+    if (hd.magic != kStateMagic) return fail(c, FTE_EINVAL, "not a state blob");
+    if (hd.fingerprint != state_fingerprint(c)) return fail(c, FTE_EINVAL, "state saved with other parameters or grid");
+    if (hd.hist_n != c->hist_n || hd.sm_n != c->sm_n || hd.grad != (uint32_t)c->p.grad)
+        return fail(c, FTE_EINVAL, "state layout differs from this context");
+    if (hd.n_live > c->n_max) return fail(c, FTE_ENOMEM, "state holds more particles than the capacity");
+    if (hd.total_bytes != state_blob_bytes(c, hd.n_live) || bytes < hd.total_bytes)
+        return fail(c, FTE_EINVAL, "state blob size mismatch");
+    if (hd.global_step >= (1ull << 48)) return fail(c, FTE_EINVAL, "bad global step");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipStreamSynchronize(s));
+    const char *o = (const char *)blob + sizeof(hd);
+    DevCounters h;
+    memcpy(&h, o, sizeof(h));
+    o += sizeof(h);
+    if (h.n_live[0] != hd.n_live) return fail(c, FTE_EINVAL, "damaged state blob");
+    const uint64_t n = hd.n_live;
+    HIPCHK(c, hipMemcpyAsync(c->cnt, &h, sizeof(h), hipMemcpyHostToDevice, s));
+    if (c->hist_n) HIPCHK(c, hipMemcpyAsync(c->b.hist, o, c->hist_n * 8, hipMemcpyHostToDevice, s));
+    o += c->hist_n * 8;
+    if (c->sm_n) HIPCHK(c, hipMemcpyAsync(c->sm, o, c->sm_n * 8, hipMemcpyHostToDevice, s));
+    o += c->sm_n * 8;
+    void *col[9];
+    size_t esz[9];
+    const int nc = state_columns(c->st[0], col, esz);
+    for (int k = 0; k < nc; ++k) {
+        if (n) HIPCHK(c, hipMemcpyAsync(col[k], o, n * esz[k], hipMemcpyHostToDevice, s));
+        o += n * esz[k];
+    }
+    if (c->p.grad)
+        for (int q = 0; q <= kTanLnw; ++q) {
+            if (n) HIPCHK(c, hipMemcpyAsync(c->tn[0].col(q), o, n * 8, hipMemcpyHostToDevice, s));
+            o += n * 8;
+        }
+    HIPCHK(c, hipStreamSynchronize(s));
+    c->cur = 0;
+    c->n_upper = n;
+    c->injected_since = 0;
+    c->pending = false;
+    c->global_step = hd.global_step;
+    c->since_compact = 0;
+    c->tev_used = 0;
+    c->timed_ms = 0.0;
+    c->timed_launches = 0;
+    return FTE_OK;
+}
+
 fte_status fte_set_launch(fte_ctx *c, int block, int steps_per_launch, int compact_every, int spatial_sort) {
     if (!c) return FTE_EINVAL;
     if (block < 64 || block > 256 || (block & 63)) return fail(c, FTE_EINVAL, "block must be 64..256, multiple of 64");

@@ -27,7 +27,8 @@ RECORD_FIELDS = 13
 STATUS = {"active": 0, "absorbed_in": 1, "absorbed_out": 2, "out_of_domain": 3, "numeric": 4}
 SYMBOLS = ["fte_create", "fte_destroy", "fte_last_error", "fte_query_sizes", "fte_bind_buffers", "fte_load_grid",
            "fte_inject", "fte_step_n", "fte_bin_observers", "fte_read_hist", "fte_get_stats", "fte_read_particles",
-           "fte_set_launch", "fte_reset", "fte_set_timing", "fte_bin_smoothed", "fte_grad", "fte_read_tangents"]
+           "fte_set_launch", "fte_reset", "fte_set_timing", "fte_bin_smoothed", "fte_grad", "fte_read_tangents",
+           "fte_state_size", "fte_save_state", "fte_load_state"]
 TANGENT_COLS = 11         # d(x, y, z, mu, lnp)/d lambda_ref, the same for kperp_ratio, d ln w / d gamma_inj
 
 
@@ -114,6 +115,9 @@ def lib():
         L.fte_bin_smoothed.argtypes = [vp, dp, dp, vp]
         L.fte_grad.argtypes = [vp, dp, dp, vp]
         L.fte_read_tangents.argtypes = [vp, dp, u64, C.POINTER(C.c_uint64), vp]
+        L.fte_state_size.argtypes = [vp, C.POINTER(C.c_uint64), vp]
+        L.fte_save_state.argtypes = [vp, vp, u64, vp]
+        L.fte_load_state.argtypes = [vp, vp, u64, vp]
         for name in SYMBOLS:
             if name not in ("fte_destroy", "fte_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -326,6 +330,19 @@ def fte_read_tangents(ctx, cap: int, stream: int):
     return t[: n.value]
 
 
+def fte_save_state(ctx, stream: int) -> bytes:
+    n = C.c_uint64()
+    _check(ctx, lib().fte_state_size(ctx, C.byref(n), C.c_void_p(stream)))
+    buf = C.create_string_buffer(n.value)
+    _check(ctx, lib().fte_save_state(ctx, buf, n.value, C.c_void_p(stream)))
+    return buf.raw
+
+
+def fte_load_state(ctx, blob: bytes, stream: int):
+    buf = C.create_string_buffer(bytes(blob), len(blob))
+    _check(ctx, lib().fte_load_state(ctx, buf, len(blob), C.c_void_p(stream)))
+
+
 def fte_set_launch(ctx, block: int, steps_per_launch: int, compact_every: int, spatial_sort: int = 2):
     _check(ctx, lib().fte_set_launch(ctx, int(block), int(steps_per_launch), int(compact_every), int(spatial_sort)))
 
@@ -425,6 +442,12 @@ class Simulation:
 
     def tangents(self):
         return fte_read_tangents(self.ctx, self.n_max, self.stream)
+
+    def save_state(self) -> bytes:
+        return fte_save_state(self.ctx, self.stream)
+
+    def load_state(self, blob: bytes):
+        fte_load_state(self.ctx, blob, self.stream)
 
     def stats(self) -> fte_stats:
         return fte_get_stats(self.ctx, self.stream)
