@@ -15,26 +15,29 @@ def hipcc():
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source (always; the caller asked for a build)."""
+def build(verbose: bool = False, defines=(), out: str = None) -> str:
+    """Compile every source (always; the caller asked for a build).
+    ``defines`` are extra -D macros (tuning knobs of fte_internal.hpp and the
+    step kernel); ``out`` another path for the library."""
+    lib = out or LIB
     objs = []
     common = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall", "-Wno-unused-result",
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics",
               "-I", os.path.join(HERE, "..", "include")]
     for src in SOURCES:
-        obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = [hipcc()] + common + ["-c", os.path.join(CSRC, src), "-o", obj]
+        obj = lib + "." + src.replace(".hip", ".o")
+        cmd = [hipcc()] + common + [f"-D{d}" for d in defines] + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     for o in objs:
         os.remove(o)
-    return LIB
+    return lib
 
 
 if __name__ == "__main__":

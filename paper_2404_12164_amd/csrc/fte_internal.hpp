@@ -82,6 +82,23 @@ struct DevTan {
 };
 enum : int { kTanLnw = 10 };
 
+// LDS plan of a step launch: observer time bins [it_lo, it_lo + n_tb) are
+// accumulated in LDS (n_tb = 0: straight to the global histogram).  The block
+// index can be staged in LDS too (tables up to FTE_LDS_INDEX_BYTES); on the
+// CIR workload its 10 KB stay resident in L1/L2 and staging cost 0.5%, so it
+// is off unless the limit is raised at build time.
+struct StepLds {
+    int it_lo, n_tb;
+};
+#ifndef FTE_LDS_HIST_BYTES
+#define FTE_LDS_HIST_BYTES 16384
+#endif
+#ifndef FTE_LDS_INDEX_BYTES
+#define FTE_LDS_INDEX_BYTES 0
+#endif
+constexpr size_t kLdsHistBytes = FTE_LDS_HIST_BYTES;
+constexpr size_t kLdsIndexBytes = FTE_LDS_INDEX_BYTES;
+
 // Device counters (live in the work buffer).
 struct DevCounters {
     unsigned long long n_live[2];

@@ -435,7 +435,8 @@ __device__ __forceinline__ void grid_coords<float>(const DevGrid &G, double r, f
 // level, B the leaf's block index and *Lout (if given) its level; returns the
 // leaf id or -1.
 template <typename R>
-__device__ __forceinline__ int descend(const DevGrid &G, const R s[3], R S[3], int B[3], int *Lout = nullptr) {
+__device__ __forceinline__ int descend(const DevGrid &G, const int32_t *base, const int32_t *child, const R s[3],
+                                       R S[3], int B[3], int *Lout = nullptr) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         int c = (int)M<R>::floor_(s[a]);
@@ -443,7 +444,7 @@ __device__ __forceinline__ int descend(const DevGrid &G, const R s[3], R S[3], i
         B[a] = c / G.bx[a];
         S[a] = s[a];
     }
-    int node = G.base[B[0] + G.nb1[0] * (B[1] + G.nb1[1] * B[2])];
+    int node = base[B[0] + G.nb1[0] * (B[1] + G.nb1[1] * B[2])];
     int L = 1;
     while (node < 0) {
         const int grp = -node - 1;
@@ -459,7 +460,7 @@ __device__ __forceinline__ int descend(const DevGrid &G, const R s[3], R S[3], i
             B[a] = c / G.bx[a];
             slot |= (B[a] & 1) << a;
         }
-        node = G.child[grp * 8 + slot];
+        node = child[grp * 8 + slot];
     }
     if (Lout) *Lout = L;
     return node;
@@ -487,13 +488,14 @@ __device__ __forceinline__ void fold_s(const DevGrid &G, R s[3]) {
 // Locate the leaf holding level-1 coordinates s and gather + interpolate the
 // records (trilinear in space, linear in time between snapshots k and k+1).
 template <typename R, bool KPERP>
-__device__ __forceinline__ bool gather(const DevGrid &G, R s[3], int ks, R alpha, R acc[kNF]) {
+__device__ __forceinline__ bool gather(const DevGrid &G, const int32_t *ibase, const int32_t *ichild, R s[3], int ks,
+                                       R alpha, R acc[kNF]) {
     constexpr int NF = KPERP ? 13 : 10;
     constexpr int RS = KPERP ? kRSKperp : kRSPlain;
     fold_s<R>(G, s);
     int B[3];
     R S[3];
-    const int leaf = descend<R>(G, s, S, B);
+    const int leaf = descend<R>(G, ibase, ichild, s, S, B);
     if (leaf < 0) return false;
     // local cell relative to the first centre of the block, padded index
     int i[3];
@@ -530,8 +532,8 @@ __device__ __forceinline__ bool gather(const DevGrid &G, R s[3], int ks, R alpha
 // ND tangent directions: ds[k] holds the derivative of the level-1
 // coordinates along direction k; axes clamped by the fold contribute none.
 template <typename R, bool KPERP, int ND>
-__device__ __forceinline__ bool gather_d(const DevGrid &G, R s[3], const R ds[ND][3], int ks, R alpha,
-                                         R acc[kNF], R dacc[ND][kNF]) {
+__device__ __forceinline__ bool gather_d(const DevGrid &G, const int32_t *ibase, const int32_t *ichild, R s[3],
+                                         const R ds[ND][3], int ks, R alpha, R acc[kNF], R dacc[ND][kNF]) {
     constexpr int NF = KPERP ? 13 : 10;
     constexpr int RS = KPERP ? kRSKperp : kRSPlain;
     const R s_in[3] = {s[0], s[1], s[2]};
@@ -539,7 +541,7 @@ __device__ __forceinline__ bool gather_d(const DevGrid &G, R s[3], const R ds[ND
     bool live[3] = {s[0] == s_in[0], s[1] == s_in[1], G.periodic ? true : s[2] == s_in[2]};
     int B[3], L;
     R S[3];
-    const int leaf = descend<R>(G, s, S, B, &L);
+    const int leaf = descend<R>(G, ibase, ichild, s, S, B, &L);
     if (leaf < 0) return false;
     const R scale = (R)(1 << (L - 1));
     R dS[ND][3];
@@ -652,13 +654,48 @@ __device__ __forceinline__ R dmm_g1(const DevParams &P, R mu) {
 // kperp_ratio), propagated by the derivative of the same Euler-Maruyama map
 // under the same Wiener increments, and the derivative sums of the smoothed
 // estimator.
-template <typename R, bool KPERP, int MODE>
-__global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState st, DevTan tn, DevCounters *cnt,
-                                              int slot, double *hist, double *sm, uint64_t n0, uint32_t n_steps) {
+// Dynamic LDS of the step kernel: the observer histogram of the time bins
+// this launch can touch (doubles, zeroed on entry, flushed with one global
+// atomic per nonzero bin on exit), then the block index (base and child
+// tables) when LIDX.
+extern __shared__ __align__(16) unsigned char k_step_lds[];
+
+// Minimum waves per SIMD the register allocation of the step kernel aims
+// for (1 = no constraint).  Measured on the CIR workload: the double forward
+// kernels gain 18% at 2 (one wave per SIMD otherwise; 3 or 4 spill hundreds
+// of bytes); the float ones lose 5% when squeezed from 3 waves to 4.
+#ifndef FTE_STEP_WPE_F32
+#define FTE_STEP_WPE_F32 1
+#endif
+#ifndef FTE_STEP_WPE_F64
+#define FTE_STEP_WPE_F64 2
+#endif
+template <typename R, int MODE>
+constexpr int step_wpe() {
+    return MODE == 2 ? 1 : (std::is_same<R, float>::value ? FTE_STEP_WPE_F32 : FTE_STEP_WPE_F64);
+}
+
+template <typename R, bool KPERP, int MODE, bool LIDX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R, MODE>()))) void k_step(DevParams P, DevGrid G, DevState st, DevTan tn, DevCounters *cnt,
+                                              int slot, double *hist, double *sm, uint64_t n0, uint32_t n_steps,
+                                              StepLds LD) {
     constexpr int ND = MODE == 2 ? 2 : 1;
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t n_live = cnt->n_live[slot];
     unsigned long long my_steps = 0;
+    double *lh = reinterpret_cast<double *>(k_step_lds);
+    const int n_lh = LD.n_tb > 0 ? P.n_obs * P.n_e * LD.n_tb * P.n_batch : 0;
+    const int32_t *ibase = G.base, *ichild = G.child;
+    if constexpr (LIDX) {
+        int32_t *lb = reinterpret_cast<int32_t *>(k_step_lds + (size_t)n_lh * 8);
+        int32_t *lc = lb + G.n_base;
+        for (int k = threadIdx.x; k < G.n_base; k += blockDim.x) lb[k] = G.base[k];
+        for (int k = threadIdx.x; k < G.n_child; k += blockDim.x) lc[k] = G.child[k];
+        ibase = lb;
+        ichild = lc;
+    }
+    for (int k = threadIdx.x; k < n_lh; k += blockDim.x) lh[k] = 0.0;
+    if (LIDX || n_lh > 0) __syncthreads();
     if (i < n_live && st.status[i] == FTE_PS_ACTIVE) {
         double x = st.x[i], y = st.y[i], z = st.z[i];
         R mu = (R)st.mu[i], lnp = (R)st.lnp[i];
@@ -735,12 +772,12 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
                     ds[k][1] = tth[k] * (R)G.inv_dth;
                     ds[k][2] = M<R>::div_(tph[k], st_) * (R)G.inv_dph;
                 }
-                if (!gather_d<R, KPERP, ND>(G, s, ds, ks, alpha, acc, dacc)) {
+                if (!gather_d<R, KPERP, ND>(G, ibase, ichild, s, ds, ks, alpha, acc, dacc)) {
                     status = FTE_PS_NUMERIC;
                     break;
                 }
             } else {
-                if (!gather<R, KPERP>(G, s, ks, alpha, acc)) {
+                if (!gather<R, KPERP>(G, ibase, ichild, s, ks, alpha, acc)) {
                     status = FTE_PS_NUMERIC;
                     break;
                 }
@@ -1013,8 +1050,14 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
                         const int ie = (int)M<R>::floor_(ue);
                         const int it = (int)::floor(ut);
                         const int ib = (int)(pid % (uint64_t)P.n_batch);
-                        const size_t hidx = (((size_t)o * P.n_e + ie) * P.n_t + it) * P.n_batch + ib;
-                        atomicAdd(&hist[hidx], w * (double)vcur * P.dt);
+                        const double add = w * (double)vcur * P.dt;
+                        const int lt = it - LD.it_lo;
+                        if (lt >= 0 && lt < LD.n_tb) {
+                            atomicAdd(&lh[(((size_t)o * P.n_e + ie) * LD.n_tb + lt) * P.n_batch + ib], add);
+                        } else {
+                            const size_t hidx = (((size_t)o * P.n_e + ie) * P.n_t + it) * P.n_batch + ib;
+                            atomicAdd(&hist[hidx], add);
+                        }
                     }
                 }
             }
@@ -1052,17 +1095,68 @@ __global__ __launch_bounds__(256) void k_step(DevParams P, DevGrid G, DevState s
         for (int k = 0; k < (int)(blockDim.x >> 6); ++k) tot += red[k];
         if (tot) atomicAdd(&cnt->steps, tot);
     }
+    // flush the block's histogram (the barrier above orders it after every
+    // LDS accumulation)
+    for (int k = threadIdx.x; k < n_lh; k += blockDim.x) {
+        const double v = lh[k];
+        if (v != 0.0) {
+            const int ib = k % P.n_batch;
+            const int lt = (k / P.n_batch) % LD.n_tb;
+            const int oe = k / (P.n_batch * LD.n_tb);
+            atomicAdd(&hist[((size_t)oe * P.n_t + LD.it_lo + lt) * P.n_batch + ib], v);
+        }
+    }
+}
+
+template <typename R, bool KPERP, int MODE>
+static void launch_step_m(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
+                          double *hist, double *sm, uint64_t n0, uint32_t n_steps, dim3 grid, dim3 blk, StepLds ld,
+                          size_t shmem, bool lidx, hipStream_t s) {
+    if (lidx)
+        hipLaunchKernelGGL((k_step<R, KPERP, MODE, true>), grid, blk, shmem, s, p, g, st, tn, cnt, slot, hist, sm, n0,
+                           n_steps, ld);
+    else
+        hipLaunchKernelGGL((k_step<R, KPERP, MODE, false>), grid, blk, shmem, s, p, g, st, tn, cnt, slot, hist, sm, n0,
+                           n_steps, ld);
 }
 
 template <typename R, bool KPERP>
 static void launch_step_t(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
-                          double *hist, double *sm, uint64_t n0, uint32_t n_steps, dim3 grid, dim3 blk, hipStream_t s) {
+                          double *hist, double *sm, uint64_t n0, uint32_t n_steps, dim3 grid, dim3 blk, StepLds ld,
+                          size_t shmem, bool lidx, hipStream_t s) {
     if (p.grad)
-        hipLaunchKernelGGL((k_step<R, KPERP, 2>), grid, blk, 0, s, p, g, st, tn, cnt, slot, hist, sm, n0, n_steps);
+        launch_step_m<R, KPERP, 2>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld, shmem, lidx, s);
     else if (p.smooth)
-        hipLaunchKernelGGL((k_step<R, KPERP, 1>), grid, blk, 0, s, p, g, st, tn, cnt, slot, hist, sm, n0, n_steps);
+        launch_step_m<R, KPERP, 1>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld, shmem, lidx, s);
     else
-        hipLaunchKernelGGL((k_step<R, KPERP, 0>), grid, blk, 0, s, p, g, st, tn, cnt, slot, hist, sm, n0, n_steps);
+        launch_step_m<R, KPERP, 0>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld, shmem, lidx, s);
+}
+
+// LDS plan of one launch: the time bins its post-step times fall in (the
+// kernel's own floor of (t + dt - t_ref) / dT at the first and last step),
+// when their histogram fits kLdsHistBytes; the block index when it fits
+// kLdsIndexBytes.
+StepLds plan_step_lds(const DevParams &p, const DevGrid &g, uint64_t n0, uint32_t n_steps, size_t *shmem, bool *lidx) {
+    StepLds ld{0, 0};
+    if (p.n_obs > 0 && n_steps > 0) {
+        const double t_a = p.t0 + (double)n0 * p.dt, t_b = p.t0 + (double)(n0 + n_steps - 1) * p.dt;
+        double fa = ::floor((t_a + p.dt - p.t_ref) * p.inv_dT), fb = ::floor((t_b + p.dt - p.t_ref) * p.inv_dT);
+        fa = fa < 0.0 ? 0.0 : fa;
+        fb = fb > (double)(p.n_t - 1) ? (double)(p.n_t - 1) : fb;
+        if (fb >= fa) {
+            const int ntb = (int)(fb - fa) + 1;
+            const size_t bytes = (size_t)p.n_obs * p.n_e * ntb * p.n_batch * 8;
+            if (bytes <= kLdsHistBytes) {
+                ld.it_lo = (int)fa;
+                ld.n_tb = ntb;
+            }
+        }
+    }
+    const size_t hb = ld.n_tb > 0 ? (size_t)p.n_obs * p.n_e * ld.n_tb * p.n_batch * 8 : 0;
+    const size_t ib = ((size_t)g.n_base + g.n_child) * 4;
+    *lidx = ib <= kLdsIndexBytes;
+    *shmem = hb + (*lidx ? ib : 0);
+    return ld;
 }
 
 hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
@@ -1071,12 +1165,15 @@ hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevTan
     if (n_upper == 0 || n_steps == 0) return hipSuccess;
     const bool kp = p.kperp_ratio > 0.0 || p.lambda_perp > 0.0;
     dim3 grid(blocks_for(n_upper, block)), blk(block);
+    size_t shmem = 0;
+    bool lidx = false;
+    const StepLds ld = plan_step_lds(p, g, n0, n_steps, &shmem, &lidx);
     if (fp32) {
-        if (kp) launch_step_t<float, true>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, s);
-        else launch_step_t<float, false>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, s);
+        if (kp) launch_step_t<float, true>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld, shmem, lidx, s);
+        else launch_step_t<float, false>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld, shmem, lidx, s);
     } else {
-        if (kp) launch_step_t<double, true>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, s);
-        else launch_step_t<double, false>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, s);
+        if (kp) launch_step_t<double, true>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld, shmem, lidx, s);
+        else launch_step_t<double, false>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld, shmem, lidx, s);
     }
     return hipGetLastError();
 }
@@ -1148,7 +1245,7 @@ __device__ __forceinline__ uint32_t cell_key(const DevGrid &G, int shift, double
     fold_s<float>(G, s);
     float S[3];
     int B[3];
-    const int leaf = descend<float>(G, s, S, B);
+    const int leaf = descend<float>(G, G.base, G.child, s, S, B);
     if (leaf < 0) return 0u;
     int sub[3];
 #pragma unroll
