@@ -332,6 +332,40 @@ def cir_differentiation(n_particles=1_000_000, n_steps=8000, precision="mixed", 
     return dict(cfg, name="cir_differentiation", params=params)
 
 
+def cir_ensemble(n_runs=64, precision="mixed", seed=0, n_snap=57, particle_range=(1e4, 1e6),
+                 step_range=(2000, 20000)):
+    """Batched ensemble: n_runs independent runs on the CIR grid and wind (one
+    refinement level), lambda log-uniform in [0.05, 1] au, kappa_perp/kappa_par
+    uniform in [0, 0.05], particle counts log-uniform in particle_range, step
+    counts uniform in step_range; each run injects its particles (5-50 keV,
+    E^-4, r = 0.1 au) continuously over its own steps, pids in disjoint
+    ranges.  57 hourly snapshots cover 20,000 steps of 10 s."""
+    rng = np.random.default_rng(seed)
+    g = cir_grid(n_levels=2, n_snap=n_snap)
+    lam = np.exp(rng.uniform(math.log(0.05), math.log(1.0), n_runs)) * AU
+    kr = rng.uniform(0.0, 0.05, n_runs)
+    npart = np.exp(rng.uniform(math.log(particle_range[0]), math.log(particle_range[1]), n_runs)).astype(np.int64)
+    nstep = rng.integers(step_range[0], step_range[1] + 1, n_runs)
+    runs = [dict(lambda_ref=float(lam[r]), kperp_ratio=float(kr[r]), n_steps=int(nstep[r])) for r in range(n_runs)]
+    r_out = 0.1 * AU * math.exp(g["n1"][0] * g["dxi"])
+    params = dict(mass=M_P, dmm_model="power_q", dmm_norm=0, lambda_ref=0.2 * AU, p_ref=1.0, alpha=0.0,
+                  q=5.0 / 3.0, eps=0.0, mu_floor=1e-4, kperp_ratio=0.0, lambda_perp=0.0, dt=10.0, t0=0.0,
+                  r_in=0.05 * AU, r_out=r_out, check_bounds=1, run_id=0, seed=0,
+                  observers=[(1.0 * AU, 90 * DEG, p * DEG, 0.05 * AU, 10 * DEG, 10 * DEG) for p in (0, 30, 60)],
+                  t_ref=0.0, dT=600.0, n_t=int(math.ceil(step_range[1] * 10.0 / 600.0)), n_batch=8,
+                  precision=precision, runs=runs, **_bins(2.0, 100.0, 10))
+    injections = []
+    pid = 0
+    for r in range(n_runs):
+        n = int(npart[r])
+        injections.append(dict(r=0.1 * AU, th_lo=30 * DEG, th_hi=150 * DEG, ph_lo=0.0, ph_hi=2 * math.pi,
+                               e_lo=5 * KEV, e_hi=50 * KEV, gamma_inj=4.0, w0=1.0, pid0=pid, n_total=n,
+                               k0=0, n_inj_steps=int(nstep[r]), run=r))
+        pid += n
+    return dict(name="cir_ensemble", grid=g, wind=cir_wind, wind_kw={}, params=params, injections=injections,
+                n_particles=int(npart.sum()), n_steps=int(nstep.max()), runs=runs)
+
+
 def particle_spec_like(inj, **over):
     d = dict(inj)
     d.update(over)

@@ -68,18 +68,29 @@ enum {
     FTE_PS_ABSORBED_IN = 1,   /* crossed r < r_in                               */
     FTE_PS_ABSORBED_OUT = 2,  /* crossed r > r_out                              */
     FTE_PS_OUT_OF_DOMAIN = 3, /* colatitude left the grid's range               */
-    FTE_PS_NUMERIC = 4        /* non-finite state or vanishing b                */
+    FTE_PS_NUMERIC = 4,       /* non-finite state or vanishing b                */
+    FTE_PS_DONE = 5           /* its run (ensemble) took all its steps          */
 };
 
 #define FTE_MAX_OBS 8
 #define FTE_MAX_LEVELS 8
 #define FTE_MAX_BATCH 64
+#define FTE_MAX_RUNS 64
 
 /* Spherical-box observer volume: r, theta, phi centre and full widths. */
 typedef struct {
     double r, theta, phi;
     double dr, dtheta, dphi;
 } fte_observer;
+
+/* One run of an ensemble: its own mean free path and cross-field ratio (the
+ * other physics is shared), its own step count and Philox run id
+ * (fte_params.run_id + its index), its own observer sums. */
+typedef struct {
+    double lambda_ref;    /* parallel mean free path at p_ref, m                   */
+    double kperp_ratio;   /* kappa_perp / kappa_par (0: lambda_perp or none)        */
+    uint64_t n_steps;     /* global steps 0 .. n_steps-1; then FTE_PS_DONE          */
+} fte_run;
 
 /* Physics and run parameters (fixed for the life of a context). */
 typedef struct {
@@ -127,6 +138,15 @@ typedef struct {
                              noise) and d ln w / d gamma_inj, and accumulate dJ.
                              Needs sigma_x, sigma_lne, sigma_t > 0 and the
                              tangent buffers.                                     */
+    /* Ensembles: n_runs > 0 runs share the grid, the clock and every other
+     * parameter; each particle belongs to one run (fte_injection.run) and
+     * takes that run's lambda_ref, kperp_ratio, step count and Philox run id
+     * run_id + run; observer sums are kept per run.  A particle of run r
+     * follows exactly the trajectory it has in a single-run context with
+     * run_id + r and that run's lambda_ref and kperp_ratio.  n_runs = 0: a
+     * single run with the fields above.  Not combined with sigma_x > 0.      */
+    int n_runs;           /* 0..FTE_MAX_RUNS                                       */
+    const fte_run *runs;  /* host, n_runs entries; copied by fte_create            */
 } fte_params;
 
 /* Block-AMR spherical grid (section 2.4).  Coordinates (xi, theta, phi), with
@@ -172,6 +192,7 @@ typedef struct {
     uint64_t n_total;     /* particles of the whole injection (>= 1)              */
     uint32_t k0;
     uint32_t n_inj_steps;
+    int run;              /* ensemble run the particles belong to (0 if none)     */
 } fte_injection;
 
 /* Byte sizes of the caller-owned device buffers. */
@@ -195,9 +216,9 @@ typedef struct {
     uint64_t n_live;          /* particles held (active or not yet started)     */
     uint64_t n_injected;
     uint64_t particle_steps;  /* steps taken by active particles                */
-    uint64_t n_retired[5];    /* by FTE_PS_* (index 0 unused)                   */
+    uint64_t n_retired[6];    /* by FTE_PS_* (index 0 unused)                   */
     double w_injected;
-    double w_retired[5];
+    double w_retired[6];
     uint64_t global_step;     /* next global step index                         */
     uint32_t device_flags;    /* nonzero: a kernel met an unsupported case      */
     uint32_t step_launches;   /* step-kernel launches timed since the last reset */
@@ -220,7 +241,8 @@ typedef struct {
 
 /* Particle state buffer layout for capacity n_max: arrays of n_max entries
  * in this order: x, y, z, mu, lnp (ln of p / (m c)), w (all double), pid
- * (uint64), kinj (uint32), status (int32).  Tangent buffer layout: 11 double
+ * (uint64), kinj (uint32), status (int32), run (uint16), each array starting
+ * on a 256-byte boundary.  Tangent buffer layout: 11 double
  * arrays of n_max entries, in the order of fte_read_tangents. */
 
 fte_status fte_create(fte_ctx **out, const fte_params *p);
@@ -258,11 +280,13 @@ fte_status fte_step_n(fte_ctx *ctx, uint32_t n_steps, void *stream);
 
 /* Intensities j[o][e][t] = S / (4 pi dV dT dE W_inj) and their standard errors
  * from the n_batch batch sums, written to HOST arrays of n_obs*n_e*n_t doubles
- * (either may be NULL).  reset != 0 clears the sums afterwards.  Synchronises. */
+ * (either may be NULL); for an ensemble [run][o][e][t] with each run's own
+ * W_inj.  reset != 0 clears the sums afterwards.  Synchronises. */
 fte_status fte_bin_observers(fte_ctx *ctx, double *j, double *sigma, int reset, void *stream);
 
-/* Raw batch sums S[o][e][t][batch] (host array of n_obs*n_e*n_t*n_batch) and
- * the injected weight.  Synchronises. */
+/* Raw batch sums S[o][e][t][batch] (host array of n_obs*n_e*n_t*n_batch;
+ * [run][o][e][t][batch] for an ensemble) and the injected weight (host array
+ * of max(n_runs, 1): per run).  Synchronises. */
 fte_status fte_read_hist(fte_ctx *ctx, double *sums, double *w_injected, void *stream);
 
 fte_status fte_get_stats(fte_ctx *ctx, fte_stats *out, void *stream);
@@ -325,6 +349,15 @@ fte_status fte_set_timing(fte_ctx *ctx, int enable);
  * gathers from neighbouring records: spatial_sort 0 keeps the storage order,
  * 1, 2, 3 sort by cubes of 1, 2, 4 cells per edge.  Defaults 256 / 32 / 128 / 2. */
 fte_status fte_set_launch(fte_ctx *ctx, int block, int steps_per_launch, int compact_every, int spatial_sort);
+
+/* Self-tuning of the launch shape: from the current state, run trial_steps
+ * global steps under each candidate (block size x compaction interval, steps
+ * per launch fixed), timing the step and compaction kernels with HIP events,
+ * restoring the state (held in host memory) after each trial; then keep the
+ * fastest and report it in best[0..2] = block, steps_per_launch,
+ * compact_every (host array).  The run continues from the restored state, so
+ * results do not depend on the tuning.  Synchronises. */
+fte_status fte_autotune(fte_ctx *ctx, uint32_t trial_steps, int best[3], void *stream);
 
 #ifdef __cplusplus
 }

@@ -19,6 +19,7 @@ using namespace fte;
 
 struct fte_ctx {
     fte_params p{};
+    std::vector<fte_run> runs;     // copy of the ensemble table
     DevParams dp{};
     bool bound = false, loaded = false;
     fte_grid_desc g{};
@@ -67,6 +68,16 @@ fte_status fail(fte_ctx *c, fte_status s, const std::string &msg) {
 
 bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
 
+int runs_eff(const fte_params *p) { return p->n_runs > 0 ? p->n_runs : 1; }
+
+// kappa_perp terms (and the 13-field records) are needed when any run has them
+bool needs_kperp(const fte_params *p) {
+    if (p->kperp_ratio > 0.0 || p->lambda_perp > 0.0) return true;
+    for (int r = 0; r < p->n_runs; ++r)
+        if (p->runs[r].kperp_ratio > 0.0) return true;
+    return false;
+}
+
 // Global steps whose post-step time t0 + (n+1) dt can lie within the time
 // kernel's cut of
 // a time-bin centre (padded by a step on each side; the read-out applies the
@@ -113,6 +124,18 @@ std::string check_params(const fte_params *p) {
             if (!finite_pos(ob.r) || !finite_pos(ob.dr) || !finite_pos(ob.dtheta) || !finite_pos(ob.dphi) ||
                 ob.dr >= 2 * ob.r || !isfinite(ob.theta) || !isfinite(ob.phi) || ob.dphi > 2 * kPi)
                 return "bad observer box";
+        }
+    }
+    if (p->n_runs < 0 || p->n_runs > FTE_MAX_RUNS) return "n_runs out of range";
+    if (p->n_runs > 0) {
+        if (!p->runs) return "runs is NULL";
+        if (p->run_id + p->n_runs - 1 > 0xFFFF) return "run ids must fit 16 bits";
+        if (p->sigma_x > 0.0 || p->grad) return "ensembles do not combine with smoothed intensities";
+        for (int r = 0; r < p->n_runs; ++r) {
+            const fte_run &u = p->runs[r];
+            if (!finite_pos(u.lambda_ref)) return "run lambda_ref must be > 0";
+            if (!(u.kperp_ratio >= 0.0) || !isfinite(u.kperp_ratio)) return "run kperp_ratio must be >= 0";
+            if (u.n_steps < 1 || u.n_steps >= (1ull << 48)) return "run n_steps out of range";
         }
     }
     if (!(p->sigma_x >= 0.0) || !isfinite(p->sigma_x)) return "sigma_x must be >= 0";
@@ -224,7 +247,7 @@ struct Layout {
     size_t grid, index, state, hist, work, tangent;
     size_t off_child, off_info;
     size_t off_j, off_s, off_cart, off_keys, off_counts, off_tsum;
-    size_t off_sm, off_fin_sm, off_dl, off_out4, sm_n;
+    size_t off_sm, off_fin_sm, off_dl, off_out4, sm_n, off_runs;
     uint32_t n_keys;
     int pcells;
     int rs;
@@ -233,17 +256,19 @@ struct Layout {
 Layout layout(const fte_params *p, const fte_grid_desc *g, uint64_t n_max, size_t n_base, size_t n_child) {
     Layout L{};
     L.pcells = (g->bx[0] + 2) * (g->bx[1] + 2) * (g->bx[2] + 2);
-    L.rs = (p->kperp_ratio > 0.0 || p->lambda_perp > 0.0) ? kRSKperp : kRSPlain;
+    L.rs = needs_kperp(p) ? kRSKperp : kRSPlain;
     L.grid = (size_t)g->n_snap * g->n_leaves * L.pcells * L.rs * rec_elem(p);
     L.off_child = align256(n_base * 4);
     L.off_info = L.off_child + align256(std::max<size_t>(n_child, 8) * 4);
     L.index = L.off_info + align256((size_t)g->n_leaves * 16);
     L.state = state_bytes(n_max);
     const size_t nbins = (size_t)p->n_obs * p->n_e * p->n_t;
-    L.hist = std::max<size_t>(nbins * p->n_batch * 8, 256);
-    L.off_j = align256(sizeof(DevCounters));
-    L.off_s = L.off_j + align256(std::max<size_t>(nbins, 1) * 8);
-    L.off_cart = L.off_s + align256(std::max<size_t>(nbins, 1) * 8);
+    const size_t nbr = nbins * runs_eff(p);
+    L.hist = std::max<size_t>(nbr * p->n_batch * 8, 256);
+    L.off_runs = align256(sizeof(DevCounters));
+    L.off_j = L.off_runs + align256(FTE_MAX_RUNS * sizeof(DevRun));
+    L.off_s = L.off_j + align256(std::max<size_t>(nbr, 1) * 8);
+    L.off_cart = L.off_s + align256(std::max<size_t>(nbr, 1) * 8);
     L.off_keys = L.off_cart + align256((size_t)g->n_leaves * L.pcells * 6 * 8);
     L.n_keys = (uint32_t)((size_t)g->n_leaves * g->bx[0] * g->bx[1] * g->bx[2]);   // finest sort key
     L.off_counts = L.off_keys + align256(n_max * 4);
@@ -324,6 +349,9 @@ void make_devparams(const fte_params *p, DevParams *d) {
     d->n_e = p->n_obs > 0 ? p->n_e : 1;
     d->n_t = p->n_obs > 0 ? p->n_t : 1;
     d->n_batch = p->n_batch;
+    d->n_runs = p->n_runs;
+    d->n_runs_eff = runs_eff(p);
+    d->kperp_any = needs_kperp(p) ? 1 : 0;
     // kernel-smoothed intensities
     if (p->sigma_x > 0.0) {
         d->smooth = 1;
@@ -356,7 +384,7 @@ void make_devparams(const fte_params *p, DevParams *d) {
 namespace fte {
 
 size_t state_bytes(uint64_t n) {
-    return 6 * align256(n * 8) + align256(n * 8) + align256(n * 4) + align256(n * 4);
+    return 6 * align256(n * 8) + align256(n * 8) + align256(n * 4) + align256(n * 4) + align256(n * 2);
 }
 
 size_t tangent_bytes(uint64_t n) { return 11 * align256(n * 8); }
@@ -381,6 +409,7 @@ DevState state_view(void *base, uint64_t n) {
     s.pid = (uint64_t *)(c + 6 * a8);
     s.kinj = (uint32_t *)(c + 7 * a8);
     s.status = (int32_t *)(c + 7 * a8 + a4);
+    s.run = (uint16_t *)(c + 7 * a8 + 2 * a4);
     return s;
 }
 
@@ -396,7 +425,13 @@ fte_status fte_create(fte_ctx **out, const fte_params *p) {
     fte_ctx *c = new (std::nothrow) fte_ctx();
     if (!c) return FTE_ENOMEM;
     c->p = *p;
-    make_devparams(p, &c->dp);
+    if (p->n_runs > 0) {
+        c->runs.assign(p->runs, p->runs + p->n_runs);
+        c->p.runs = c->runs.data();
+    } else {
+        c->p.runs = nullptr;
+    }
+    make_devparams(&c->p, &c->dp);
     if (hipHostMalloc((void **)&c->pinned, sizeof(unsigned long long)) != hipSuccess) {
         delete c;
         return FTE_EDEVICE;
@@ -476,7 +511,8 @@ fte_status fte_bind_buffers(fte_ctx *c, const fte_grid_desc *g, uint64_t n_max, 
     c->fin_sm = (double *)(w + L.off_fin_sm);
     c->dl = (double *)(w + L.off_dl);
     c->out4 = (double *)(w + L.off_out4);
-    c->hist_n = (uint64_t)c->p.n_obs * c->p.n_e * c->p.n_t * c->p.n_batch;
+    c->hist_n = (uint64_t)c->p.n_obs * c->p.n_e * c->p.n_t * c->p.n_batch * runs_eff(&c->p);
+    c->dp.runs = (const DevRun *)(w + L.off_runs);
 
     DevGrid &d = c->dg;
     memset(&d, 0, sizeof(d));
@@ -540,6 +576,18 @@ fte_status fte_load_grid(fte_ctx *c, const double *vb, void *stream) {
     HIPCHK(c, launch_zero_counters(c->cnt, s));
     if (c->hist_n) HIPCHK(c, launch_zero((double *)c->b.hist, c->hist_n, s));
     if (c->sm_n) HIPCHK(c, launch_zero(c->sm, c->sm_n, s));
+    if (c->p.n_runs > 0) {
+        std::vector<DevRun> dr(c->p.n_runs);
+        for (int r = 0; r < c->p.n_runs; ++r) {
+            dr[r].lambda_ref = c->runs[r].lambda_ref;
+            dr[r].kperp_ratio = c->runs[r].kperp_ratio;
+            dr[r].step_end = c->runs[r].n_steps;
+            dr[r].run_id = c->p.run_id + r;
+            dr[r].pad = 0;
+        }
+        HIPCHK(c, hipMemcpyAsync((void *)c->dp.runs, dr.data(), dr.size() * sizeof(DevRun), hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
     HIPCHK(c, launch_check_raw(d, vb, c->cnt, s));
     const int fp32 = c->p.precision == FTE_MIXED;
     for (int k = 0; k < d.n_snap; ++k) {
@@ -612,6 +660,7 @@ fte_status fte_inject(fte_ctx *c, const fte_injection *inj, uint64_t n, uint64_t
     if (first_pid + n < first_pid || first_pid + n > (1ull << 60)) return fail(c, FTE_EINVAL, "pid out of range");
     if (inj->n_inj_steps > 0 && (first_pid < inj->pid0 || first_pid + n > inj->pid0 + inj->n_total))
         return fail(c, FTE_EINVAL, "pids outside the injection's range");
+    if (inj->run < 0 || inj->run >= runs_eff(&c->p)) return fail(c, FTE_EINVAL, "injection run out of range");
     if (n == 0) return FTE_OK;
     hipStream_t s = (hipStream_t)stream;
     if (c->n_upper + n > c->n_max) {
@@ -689,7 +738,7 @@ fte_status fte_bin_observers(fte_ctx *c, double *j, double *sigma, int reset, vo
     if (!c) return FTE_EINVAL;
     if (!c->loaded) return fail(c, FTE_ESTATE, "nothing to bin before the grid is loaded");
     hipStream_t s = (hipStream_t)stream;
-    const size_t nb = (size_t)c->p.n_obs * c->p.n_e * c->p.n_t;
+    const size_t nb = (size_t)c->p.n_obs * c->p.n_e * c->p.n_t * runs_eff(&c->p);
     if (nb > 0) {
         HIPCHK(c, launch_finalize(c->dp, (const double *)c->b.hist, c->cnt, c->fin_j, c->fin_s, s));
         if (j) HIPCHK(c, hipMemcpyAsync(j, c->fin_j, nb * 8, hipMemcpyDeviceToHost, s));
@@ -705,14 +754,15 @@ fte_status fte_read_hist(fte_ctx *c, double *sums, double *w_injected, void *str
     if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
     hipStream_t s = (hipStream_t)stream;
     if (sums && c->hist_n) HIPCHK(c, hipMemcpyAsync(sums, c->b.hist, c->hist_n * 8, hipMemcpyDeviceToHost, s));
-    double w[FTE_MAX_BATCH];
-    HIPCHK(c, hipMemcpyAsync(w, c->cnt->w_inj, sizeof(w), hipMemcpyDeviceToHost, s));
+    std::vector<double> w(FTE_MAX_RUNS * FTE_MAX_BATCH);
+    HIPCHK(c, hipMemcpyAsync(w.data(), c->cnt->w_inj, w.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
-    if (w_injected) {
-        double t = 0.0;
-        for (int b = 0; b < c->p.n_batch; ++b) t += w[b];
-        *w_injected = t;
-    }
+    if (w_injected)
+        for (int r = 0; r < runs_eff(&c->p); ++r) {
+            double t = 0.0;
+            for (int b = 0; b < c->p.n_batch; ++b) t += w[r * c->p.n_batch + b];
+            w_injected[r] = t;
+        }
     return FTE_OK;
 }
 
@@ -732,9 +782,9 @@ fte_status fte_get_stats(fte_ctx *c, fte_stats *out, void *stream) {
     out->n_injected = h.injected;
     out->particle_steps = h.steps;
     double wi = 0.0;
-    for (int b = 0; b < c->p.n_batch; ++b) wi += h.w_inj[b];
+    for (int b = 0; b < c->p.n_batch * runs_eff(&c->p); ++b) wi += h.w_inj[b];
     out->w_injected = wi;
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < 6; ++k) {
         out->n_retired[k] = h.retired[k];
         out->w_retired[k] = h.w_retired[k];
     }
@@ -940,21 +990,27 @@ uint64_t state_fingerprint(const fte_ctx *c) {
     h = fnv_val(h, p.e_min); h = fnv_val(h, p.dlne); h = fnv_val(h, p.n_e); h = fnv_val(h, p.t_ref);
     h = fnv_val(h, p.dT); h = fnv_val(h, p.n_t); h = fnv_val(h, p.n_batch);
     h = fnv_val(h, p.sigma_x); h = fnv_val(h, p.sigma_lne); h = fnv_val(h, p.sigma_t); h = fnv_val(h, p.grad);
+    h = fnv_val(h, p.n_runs);
+    for (int r = 0; r < p.n_runs; ++r) {
+        h = fnv_val(h, c->runs[r].lambda_ref);
+        h = fnv_val(h, c->runs[r].kperp_ratio);
+        h = fnv_val(h, c->runs[r].n_steps);
+    }
     h = fnv_val(h, c->g.n_leaves); h = fnv_val(h, c->g.n_snap); h = fnv_val(h, c->g.n_levels);
     for (int a = 0; a < 3; ++a) { h = fnv_val(h, c->g.n1[a]); h = fnv_val(h, c->g.bx[a]); }
     return h;
 }
 
 // SoA columns of the particle state: (device pointer, element bytes)
-int state_columns(const DevState &d, void *col[9], size_t esz[9]) {
-    void *v[9] = {d.x, d.y, d.z, d.mu, d.lnp, d.w, d.pid, d.kinj, d.status};
-    const size_t e[9] = {8, 8, 8, 8, 8, 8, 8, 4, 4};
-    for (int k = 0; k < 9; ++k) { col[k] = v[k]; esz[k] = e[k]; }
-    return 9;
+int state_columns(const DevState &d, void *col[10], size_t esz[10]) {
+    void *v[10] = {d.x, d.y, d.z, d.mu, d.lnp, d.w, d.pid, d.kinj, d.status, d.run};
+    const size_t e[10] = {8, 8, 8, 8, 8, 8, 8, 4, 4, 2};
+    for (int k = 0; k < 10; ++k) { col[k] = v[k]; esz[k] = e[k]; }
+    return 10;
 }
 
 uint64_t state_blob_bytes(const fte_ctx *c, uint64_t n) {
-    uint64_t b = sizeof(StateHeader) + sizeof(DevCounters) + (c->hist_n + c->sm_n) * 8 + n * (6 * 8 + 8 + 4 + 4);
+    uint64_t b = sizeof(StateHeader) + sizeof(DevCounters) + (c->hist_n + c->sm_n) * 8 + n * (6 * 8 + 8 + 4 + 4 + 2);
     if (c->p.grad) b += n * (kTanLnw + 1) * 8;
     return b;
 }
@@ -1005,8 +1061,8 @@ fte_status fte_save_state(fte_ctx *c, void *blob, uint64_t bytes, void *stream) 
     o += c->hist_n * 8;
     if (c->sm_n) HIPCHK(c, hipMemcpyAsync(o, c->sm, c->sm_n * 8, hipMemcpyDeviceToHost, s));
     o += c->sm_n * 8;
-    void *col[9];
-    size_t esz[9];
+    void *col[10];
+    size_t esz[10];
     const int nc = state_columns(c->st[c->cur], col, esz);
     for (int k = 0; k < nc; ++k) {
         if (n) HIPCHK(c, hipMemcpyAsync(o, col[k], n * esz[k], hipMemcpyDeviceToHost, s));
@@ -1048,8 +1104,8 @@ fte_status fte_load_state(fte_ctx *c, const void *blob, uint64_t bytes, void *st
     o += c->hist_n * 8;
     if (c->sm_n) HIPCHK(c, hipMemcpyAsync(c->sm, o, c->sm_n * 8, hipMemcpyHostToDevice, s));
     o += c->sm_n * 8;
-    void *col[9];
-    size_t esz[9];
+    void *col[10];
+    size_t esz[10];
     const int nc = state_columns(c->st[0], col, esz);
     for (int k = 0; k < nc; ++k) {
         if (n) HIPCHK(c, hipMemcpyAsync(col[k], o, n * esz[k], hipMemcpyHostToDevice, s));
@@ -1070,6 +1126,70 @@ fte_status fte_load_state(fte_ctx *c, const void *blob, uint64_t bytes, void *st
     c->tev_used = 0;
     c->timed_ms = 0.0;
     c->timed_launches = 0;
+    return FTE_OK;
+}
+
+fte_status fte_autotune(fte_ctx *c, uint32_t trial_steps, int best[3], void *stream) {
+    if (!c || !best) return FTE_EINVAL;
+    if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
+    if (trial_steps < 1) return fail(c, FTE_EINVAL, "trial_steps must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    uint64_t bytes = 0;
+    fte_status r = fte_state_size(c, &bytes, stream);
+    if (r != FTE_OK) return r;
+    std::vector<char> blob;
+    try {
+        blob.resize(bytes);
+    } catch (...) {
+        return fail(c, FTE_ENOMEM, "no host memory for the state copy");
+    }
+    r = fte_save_state(c, blob.data(), bytes, stream);
+    if (r != FTE_OK) return r;
+    const bool timing = c->timing;
+    const int spl = c->spl, keep_block = c->block, keep_compact = c->compact_every;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    float best_ms = -1.f;
+    int bb = keep_block, bc = keep_compact;
+    const int blocks[3] = {64, 128, 256};
+    const int mult[4] = {1, 2, 4, 8};
+    c->timing = false;
+    for (int ib = 0; ib < 3 && r == FTE_OK; ++ib)
+        for (int im = 0; im < 4 && r == FTE_OK; ++im) {
+            r = fte_load_state(c, blob.data(), bytes, stream);
+            if (r != FTE_OK) break;
+            c->block = blocks[ib];
+            c->compact_every = spl * mult[im];
+            if (hipEventRecord(e0, s) != hipSuccess) { r = fail(c, FTE_EDEVICE, "event record"); break; }
+            r = fte_step_n(c, trial_steps, stream);
+            if (r != FTE_OK) break;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                r = fail(c, FTE_EDEVICE, "event wait");
+                break;
+            }
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { r = fail(c, FTE_EDEVICE, "event time"); break; }
+            if (best_ms < 0.f || ms < best_ms) {
+                best_ms = ms;
+                bb = c->block;
+                bc = c->compact_every;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->timing = timing;
+    c->block = keep_block;
+    c->compact_every = keep_compact;
+    // back to the state the caller had, with the winning shape
+    fte_status r2 = fte_load_state(c, blob.data(), bytes, stream);
+    if (r != FTE_OK) return r;
+    if (r2 != FTE_OK) return r2;
+    c->block = bb;
+    c->compact_every = bc;
+    best[0] = bb;
+    best[1] = spl;
+    best[2] = bc;
     return FTE_OK;
 }
 

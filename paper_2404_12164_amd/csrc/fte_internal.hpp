@@ -17,6 +17,14 @@ constexpr int kRSKperp = FTE_RECORD_STRIDE_KPERP; // fields 0-12 + pad
 // boundary term to the derivatives taken along trajectories.
 constexpr double kKernelCut = 6.0;
 
+// One run of an ensemble as the kernels see it.
+struct DevRun {
+    double lambda_ref, kperp_ratio;
+    uint64_t step_end;       // first global step the run does not take
+    int run_id;              // Philox run id
+    int pad;
+};
+
 // Device-side copy of the run parameters, pre-digested on the host.
 struct DevParams {
     double mass_c2;          // m c^2, J
@@ -39,6 +47,10 @@ struct DevParams {
     long long win_lo;        // first global step of the smoothing window
     long long n_win;         // steps in the window
     int smooth, grad, nk;    // nk = sums per (step, observer, energy): 4 with grad, else 1
+    const DevRun *runs;      // ensemble table (device), n_runs entries
+    int n_runs;              // 0: single run
+    int n_runs_eff;          // max(n_runs, 1): leading dimension of the sums
+    int kperp_any;           // some run has kappa_perp: 13-field records, KPERP kernels
     uint64_t seed;
     int dmm_model;
     int run_id;
@@ -70,6 +82,7 @@ struct DevState {
     uint64_t *pid;
     uint32_t *kinj;
     int32_t *status;
+    uint16_t *run;
 };
 
 // Tangent state of the gradient mode (struct of arrays, capacity n_max): 11
@@ -104,11 +117,11 @@ struct DevCounters {
     unsigned long long n_live[2];
     unsigned long long steps;
     unsigned long long injected;
-    unsigned long long retired[5];
-    double w_retired[5];
+    unsigned long long retired[6];
+    double w_retired[6];
     unsigned int flags;
     unsigned int pad;
-    double w_inj[FTE_MAX_BATCH];
+    double w_inj[FTE_MAX_RUNS * FTE_MAX_BATCH];   // [run][batch]
     double w_inj_dgamma;     // sum of w d ln w / d gamma_inj
 };
 

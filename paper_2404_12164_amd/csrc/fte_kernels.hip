@@ -336,8 +336,9 @@ __global__ void k_inject(DevParams P, fte_injection inj, DevState st, DevTan tn,
     if (i < n) {
         const uint64_t base = cnt->n_live[slot];
         const uint64_t pid = first_pid + i;
-        const U4 ka = philox_words(P.seed, P.run_id, 0, pid, 1u);
-        const U4 kb = philox_words(P.seed, P.run_id, 1, pid, 1u);
+        const int rid = P.n_runs > 0 ? P.runs[inj.run].run_id : P.run_id;
+        const U4 ka = philox_words(P.seed, rid, 0, pid, 1u);
+        const U4 kb = philox_words(P.seed, rid, 1, pid, 1u);
         const double u0 = M<double>::u01(ka.a), u1 = M<double>::u01(ka.b);
         const double u2 = M<double>::u01(ka.c), u3 = M<double>::u01(ka.d);
         const double mu = 2.0 * u0 - 1.0;
@@ -371,6 +372,7 @@ __global__ void k_inject(DevParams P, fte_injection inj, DevState st, DevTan tn,
         }
         st.kinj[j] = k;
         st.status[j] = FTE_PS_ACTIVE;
+        st.run[j] = (uint16_t)inj.run;
         atomicAdd(&wsum[pid % (uint64_t)P.n_batch], wt);
         if (P.grad) {
             for (int q = 0; q < kTanLnw; ++q) tn.col(q)[j] = 0.0;
@@ -380,7 +382,7 @@ __global__ void k_inject(DevParams P, fte_injection inj, DevState st, DevTan tn,
     }
     __syncthreads();
     for (int b = threadIdx.x; b < P.n_batch; b += blockDim.x)
-        if (wsum[b] != 0.0) atomicAdd(&cnt->w_inj[b], wsum[b]);
+        if (wsum[b] != 0.0) atomicAdd(&cnt->w_inj[inj.run * P.n_batch + b], wsum[b]);
     if (threadIdx.x == 0 && wdg != 0.0) atomicAdd(&cnt->w_inj_dgamma, wdg);
 }
 
@@ -684,7 +686,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
     const uint64_t n_live = cnt->n_live[slot];
     unsigned long long my_steps = 0;
     double *lh = reinterpret_cast<double *>(k_step_lds);
-    const int n_lh = LD.n_tb > 0 ? P.n_obs * P.n_e * LD.n_tb * P.n_batch : 0;
+    const int n_lh = LD.n_tb > 0 ? P.n_runs_eff * P.n_obs * P.n_e * LD.n_tb * P.n_batch : 0;
     const int32_t *ibase = G.base, *ichild = G.child;
     if constexpr (LIDX) {
         int32_t *lb = reinterpret_cast<int32_t *>(k_step_lds + (size_t)n_lh * 8);
@@ -704,6 +706,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
         const uint32_t kinj = st.kinj[i];
         int status = FTE_PS_ACTIVE;
         const R dt = (R)P.dt;
+        // this particle's run (ensembles): mean free path, cross-field ratio,
+        // last step, Philox run id
+        int run_r = 0, run_id = P.run_id;
+        double lam_ref = P.lambda_ref, kratio = P.kperp_ratio;
+        uint64_t step_end = ~0ull;
+        if (P.n_runs > 0) {
+            run_r = st.run[i];
+            const DevRun rr = P.runs[run_r];
+            lam_ref = rr.lambda_ref;
+            kratio = rr.kperp_ratio;
+            step_end = rr.step_end;
+            run_id = rr.run_id;
+        }
         // tangents (MODE 2)
         R TX[ND][3], TM[ND], TL[ND];
         R dlnw = (R)0;
@@ -726,7 +741,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
         R Pcur = M<R>::exp_(lnp);
         R gcur = M<R>::sqrt_((R)1 + Pcur * Pcur);
         R vcur = M<R>::div_((R)kC * Pcur, gcur);
-        const uint64_t n_end = n0 + n_steps;
+        const uint64_t n_win = n0 + n_steps;
+        const uint64_t n_end = n_win < step_end ? n_win : step_end;
         uint64_t nstart = n0 > kinj ? n0 : kinj;
         for (uint64_t n = nstart; n < n_end; ++n) {
             // ---- clock and snapshot pair (identical for every particle)
@@ -831,7 +847,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
             // from the previous update (the same values as exp(lnp) recomputed)
             const R Pm = Pcur;
             const R v = vcur;
-            R lam = (R)P.lambda_ref;
+            R lam = (R)lam_ref;
             if (P.alpha != 0.0) lam *= M<R>::pow_(Pm * (R)P.inv_p_ref, (R)P.alpha);
             const R A = (R)P.dmm_scale * v / lam;
             const R am = mu < (R)0 ? -mu : mu;
@@ -853,7 +869,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
             }
             R kperp = (R)0;
             if (KPERP) {
-                if (P.kperp_ratio > 0.0) kperp = (R)P.kperp_ratio * v * lam / (R)3;
+                if (kratio > 0.0) kperp = (R)kratio * v * lam / (R)3;
                 else kperp = v * (R)P.lambda_perp / (R)3;
             }
             R a_x[3];
@@ -863,7 +879,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
             const R a_mu = (R)0.5 * om * Qm + dD;
             const R a_lnp = (R)0.5 * ((R)1 - (R)3 * mu * mu) * F.bbgV - (R)0.5 * om * F.divV - M<R>::div_(mu, v) * F.bDV;
             // ---- Wiener increments: one Philox block, Box-Muller pairs
-            const U4 k4 = philox_words(P.seed, P.run_id, n, pid, 0u);
+            const U4 k4 = philox_words(P.seed, run_id, n, pid, 0u);
             const R u0 = M<R>::u01(k4.a), u1 = M<R>::u01(k4.b), u2 = M<R>::u01(k4.c), u3 = M<R>::u01(k4.d);
             const R ra = M<R>::sqrt_((R)-2 * M<R>::log_(u0));
             const R rb = M<R>::sqrt_((R)-2 * M<R>::log_(u2));
@@ -1053,9 +1069,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                         const double add = w * (double)vcur * P.dt;
                         const int lt = it - LD.it_lo;
                         if (lt >= 0 && lt < LD.n_tb) {
-                            atomicAdd(&lh[(((size_t)o * P.n_e + ie) * LD.n_tb + lt) * P.n_batch + ib], add);
+                            atomicAdd(&lh[((((size_t)run_r * P.n_obs + o) * P.n_e + ie) * LD.n_tb + lt) * P.n_batch + ib],
+                                      add);
                         } else {
-                            const size_t hidx = (((size_t)o * P.n_e + ie) * P.n_t + it) * P.n_batch + ib;
+                            const size_t hidx =
+                                ((((size_t)run_r * P.n_obs + o) * P.n_e + ie) * P.n_t + it) * P.n_batch + ib;
                             atomicAdd(&hist[hidx], add);
                         }
                     }
@@ -1077,6 +1095,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                 tn.col(5 * k + 4)[i] = (double)TL[k];
             }
         }
+        if (status == FTE_PS_ACTIVE && n_win >= step_end) status = FTE_PS_DONE;
         if (status != FTE_PS_ACTIVE) {
             st.status[i] = status;
             atomicAdd(&cnt->retired[status], 1ull);
@@ -1145,14 +1164,14 @@ StepLds plan_step_lds(const DevParams &p, const DevGrid &g, uint64_t n0, uint32_
         fb = fb > (double)(p.n_t - 1) ? (double)(p.n_t - 1) : fb;
         if (fb >= fa) {
             const int ntb = (int)(fb - fa) + 1;
-            const size_t bytes = (size_t)p.n_obs * p.n_e * ntb * p.n_batch * 8;
+            const size_t bytes = (size_t)p.n_runs_eff * p.n_obs * p.n_e * ntb * p.n_batch * 8;
             if (bytes <= kLdsHistBytes) {
                 ld.it_lo = (int)fa;
                 ld.n_tb = ntb;
             }
         }
     }
-    const size_t hb = ld.n_tb > 0 ? (size_t)p.n_obs * p.n_e * ld.n_tb * p.n_batch * 8 : 0;
+    const size_t hb = ld.n_tb > 0 ? (size_t)p.n_runs_eff * p.n_obs * p.n_e * ld.n_tb * p.n_batch * 8 : 0;
     const size_t ib = ((size_t)g.n_base + g.n_child) * 4;
     *lidx = ib <= kLdsIndexBytes;
     *shmem = hb + (*lidx ? ib : 0);
@@ -1163,7 +1182,7 @@ hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevTan
                        double *hist, double *sm, uint64_t n0, uint32_t n_steps, uint64_t n_upper, int block, int fp32,
                        hipStream_t s) {
     if (n_upper == 0 || n_steps == 0) return hipSuccess;
-    const bool kp = p.kperp_ratio > 0.0 || p.lambda_perp > 0.0;
+    const bool kp = p.kperp_any != 0;
     dim3 grid(blocks_for(n_upper, block)), blk(block);
     size_t shmem = 0;
     bool lidx = false;
@@ -1213,6 +1232,7 @@ __global__ void k_compact(DevState src, DevState dst, DevTan tsrc, DevTan tdst, 
         dst.pid[j] = src.pid[i];
         dst.kinj[j] = src.kinj[i];
         dst.status[j] = FTE_PS_ACTIVE;
+        dst.run[j] = src.run[i];
         copy_tangent(tsrc, tdst, i, j);
     }
 }
@@ -1348,6 +1368,7 @@ __global__ void k_sort_scatter(DevState src, DevState dst, DevTan tsrc, DevTan t
     dst.pid[j] = src.pid[i];
     dst.kinj[j] = src.kinj[i];
     dst.status[j] = FTE_PS_ACTIVE;
+    dst.run[j] = src.run[i];
     copy_tangent(tsrc, tdst, i, j);
 }
 
@@ -1384,12 +1405,13 @@ hipError_t launch_compact_sorted(const DevGrid &g, int sort, DevState src, DevSt
 // ===========================================================================
 __global__ void k_finalize(DevParams P, const double *hist, const DevCounters *cnt, double *j, double *sig) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int n = P.n_obs * P.n_e * P.n_t;
-    if (idx >= n) return;
-    const int o = idx / (P.n_e * P.n_t);
+    const int nb = P.n_obs * P.n_e * P.n_t;
+    if (idx >= nb * P.n_runs_eff) return;
+    const int run = idx / nb;
+    const int o = (idx % nb) / (P.n_e * P.n_t);
     const int e = (idx / P.n_t) % P.n_e;
     double W = 0.0;
-    for (int b = 0; b < P.n_batch; ++b) W += cnt->w_inj[b];
+    for (int b = 0; b < P.n_batch; ++b) W += cnt->w_inj[run * P.n_batch + b];
     const double *ob = P.obs[o];
     const double dV = (ob[1] * ob[1] * ob[1] - ob[0] * ob[0] * ob[0]) / 3.0 * (::cos(ob[2]) - ::cos(ob[3])) *
                       (2.0 * ob[5]);
@@ -1398,10 +1420,10 @@ __global__ void k_finalize(DevParams P, const double *hist, const DevCounters *c
     const double *h = hist + (size_t)idx * P.n_batch;
     double s = 0.0;
     for (int b = 0; b < P.n_batch; ++b) s += h[b];
-    const double jm = s / norm;
+    const double jm = W > 0.0 ? s / norm : 0.0;
     double var = 0.0;
     for (int b = 0; b < P.n_batch; ++b) {
-        const double jb = P.n_batch * h[b] / norm;
+        const double jb = W > 0.0 ? P.n_batch * h[b] / norm : 0.0;
         var += (jb - jm) * (jb - jm);
     }
     j[idx] = jm;
@@ -1410,7 +1432,7 @@ __global__ void k_finalize(DevParams P, const double *hist, const DevCounters *c
 
 hipError_t launch_finalize(const DevParams &p, const double *hist, const DevCounters *cnt, double *j, double *sig,
                            hipStream_t s) {
-    const int n = p.n_obs * p.n_e * p.n_t;
+    const int n = p.n_obs * p.n_e * p.n_t * p.n_runs_eff;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, hist, cnt, j, sig);
     return hipGetLastError();

@@ -24,17 +24,22 @@ MAX_OBS = 8
 RECORD_STRIDE = 10        # fields 0-9 (no kappa_perp)
 RECORD_STRIDE_KPERP = 14  # fields 0-12 and one pad
 RECORD_FIELDS = 13
-STATUS = {"active": 0, "absorbed_in": 1, "absorbed_out": 2, "out_of_domain": 3, "numeric": 4}
+STATUS = {"active": 0, "absorbed_in": 1, "absorbed_out": 2, "out_of_domain": 3, "numeric": 4, "done": 5}
+MAX_RUNS = 64
 SYMBOLS = ["fte_create", "fte_destroy", "fte_last_error", "fte_query_sizes", "fte_bind_buffers", "fte_load_grid",
            "fte_inject", "fte_step_n", "fte_bin_observers", "fte_read_hist", "fte_get_stats", "fte_read_particles",
            "fte_set_launch", "fte_reset", "fte_set_timing", "fte_bin_smoothed", "fte_grad", "fte_read_tangents",
-           "fte_state_size", "fte_save_state", "fte_load_state"]
+           "fte_state_size", "fte_save_state", "fte_load_state", "fte_autotune"]
 TANGENT_COLS = 11         # d(x, y, z, mu, lnp)/d lambda_ref, the same for kperp_ratio, d ln w / d gamma_inj
 
 
 class fte_observer(C.Structure):
     _fields_ = [("r", C.c_double), ("theta", C.c_double), ("phi", C.c_double),
                 ("dr", C.c_double), ("dtheta", C.c_double), ("dphi", C.c_double)]
+
+
+class fte_run(C.Structure):
+    _fields_ = [("lambda_ref", C.c_double), ("kperp_ratio", C.c_double), ("n_steps", C.c_uint64)]
 
 
 class fte_params(C.Structure):
@@ -47,7 +52,8 @@ class fte_params(C.Structure):
                 ("n_obs", C.c_int), ("obs", fte_observer * MAX_OBS),
                 ("e_min", C.c_double), ("dlne", C.c_double), ("n_e", C.c_int),
                 ("t_ref", C.c_double), ("dT", C.c_double), ("n_t", C.c_int), ("n_batch", C.c_int),
-                ("sigma_x", C.c_double), ("sigma_lne", C.c_double), ("sigma_t", C.c_double), ("grad", C.c_int)]
+                ("sigma_x", C.c_double), ("sigma_lne", C.c_double), ("sigma_t", C.c_double), ("grad", C.c_int),
+                ("n_runs", C.c_int), ("runs", C.POINTER(fte_run))]
 
 
 class fte_grid_desc(C.Structure):
@@ -62,7 +68,7 @@ class fte_injection(C.Structure):
     _fields_ = [("r", C.c_double), ("th_lo", C.c_double), ("th_hi", C.c_double), ("ph_lo", C.c_double),
                 ("ph_hi", C.c_double), ("e_lo", C.c_double), ("e_hi", C.c_double), ("gamma_inj", C.c_double),
                 ("w0", C.c_double), ("r_weight", C.c_int), ("r_ref", C.c_double), ("pid0", C.c_uint64),
-                ("n_total", C.c_uint64), ("k0", C.c_uint32), ("n_inj_steps", C.c_uint32)]
+                ("n_total", C.c_uint64), ("k0", C.c_uint32), ("n_inj_steps", C.c_uint32), ("run", C.c_int)]
 
 
 class fte_sizes(C.Structure):
@@ -77,7 +83,7 @@ class fte_buffers(C.Structure):
 
 class fte_stats(C.Structure):
     _fields_ = [("n_live", C.c_uint64), ("n_injected", C.c_uint64), ("particle_steps", C.c_uint64),
-                ("n_retired", C.c_uint64 * 5), ("w_injected", C.c_double), ("w_retired", C.c_double * 5),
+                ("n_retired", C.c_uint64 * 6), ("w_injected", C.c_double), ("w_retired", C.c_double * 6),
                 ("global_step", C.c_uint64), ("device_flags", C.c_uint32), ("step_launches", C.c_uint32),
                 ("step_kernel_ms", C.c_double)]
 
@@ -118,6 +124,7 @@ def lib():
         L.fte_state_size.argtypes = [vp, C.POINTER(C.c_uint64), vp]
         L.fte_save_state.argtypes = [vp, vp, u64, vp]
         L.fte_load_state.argtypes = [vp, vp, u64, vp]
+        L.fte_autotune.argtypes = [vp, u32, C.POINTER(C.c_int), vp]
         for name in SYMBOLS:
             if name not in ("fte_destroy", "fte_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -171,6 +178,14 @@ def make_params(p: dict) -> fte_params:
     if sm:
         o.sigma_x, o.sigma_lne, o.sigma_t = sm["sigma_x"], sm["sigma_lne"], sm["sigma_t"]
     o.grad = int(p.get("grad", 0))
+    runs = p.get("runs") or []
+    o.n_runs = len(runs)
+    if runs:
+        arr = (fte_run * len(runs))()
+        for i, r in enumerate(runs):
+            arr[i] = fte_run(float(r["lambda_ref"]), float(r.get("kperp_ratio", 0.0)), int(r["n_steps"]))
+        o.runs = C.cast(arr, C.POINTER(fte_run))
+        o._runs_keep = arr          # the C call reads the table; keep it alive with the struct
     return o
 
 
@@ -209,6 +224,7 @@ def make_injection(inj: dict) -> fte_injection:
     o.n_total = int(inj["n_total"])
     o.k0 = int(inj.get("k0", 0))
     o.n_inj_steps = int(inj.get("n_inj_steps", 0))
+    o.run = int(inj.get("run", 0))
     return o
 
 
@@ -272,11 +288,12 @@ def fte_bin_observers(ctx, shape, reset: bool, stream: int):
     return j[:n].reshape(shape), s[:n].reshape(shape)
 
 
-def fte_read_hist(ctx, n: int, stream: int):
+def fte_read_hist(ctx, n: int, stream: int, n_runs: int = 0):
     h = np.zeros(max(n, 1))
-    w = C.c_double()
-    _check(ctx, lib().fte_read_hist(ctx, h.ctypes.data_as(C.POINTER(C.c_double)), C.byref(w), C.c_void_p(stream)))
-    return h[:n], w.value
+    w = np.zeros(max(n_runs, 1))
+    dp = C.POINTER(C.c_double)
+    _check(ctx, lib().fte_read_hist(ctx, h.ctypes.data_as(dp), w.ctypes.data_as(dp), C.c_void_p(stream)))
+    return h[:n], (w if n_runs > 0 else float(w[0]))
 
 
 def fte_get_stats(ctx, stream: int) -> fte_stats:
@@ -343,6 +360,12 @@ def fte_load_state(ctx, blob: bytes, stream: int):
     _check(ctx, lib().fte_load_state(ctx, buf, len(blob), C.c_void_p(stream)))
 
 
+def fte_autotune(ctx, trial_steps: int, stream: int):
+    best = (C.c_int * 3)()
+    _check(ctx, lib().fte_autotune(ctx, int(trial_steps), best, C.c_void_p(stream)))
+    return tuple(best)
+
+
 def fte_set_launch(ctx, block: int, steps_per_launch: int, compact_every: int, spatial_sort: int = 2):
     _check(ctx, lib().fte_set_launch(ctx, int(block), int(steps_per_launch), int(compact_every), int(spatial_sort)))
 
@@ -389,7 +412,10 @@ class Simulation:
                                 self.t_tan_b.data_ptr() if self.grad else None)
         self.ctx = fte_create(params)
         fte_bind_buffers(self.ctx, grid, n_max, self.bufs)
+        self.n_runs = len(params.get("runs") or [])
         self.n_bins = (len(params.get("observers", [])), int(params.get("n_e", 1)), int(params.get("n_t", 1)))
+        if self.n_runs:
+            self.n_bins = (self.n_runs,) + self.n_bins
 
     @property
     def stream(self) -> int:
@@ -430,7 +456,13 @@ class Simulation:
 
     def read_hist(self):
         n = int(np.prod(self.n_bins)) * int(self.params.get("n_batch", 32))
-        return fte_read_hist(self.ctx, n, self.stream)
+        return fte_read_hist(self.ctx, n, self.stream, self.n_runs)
+
+    def autotune(self, trial_steps: int):
+        """Try block sizes x compaction intervals from the current state (which
+        is restored afterwards) and keep the fastest; returns (block,
+        steps_per_launch, compact_every)."""
+        return fte_autotune(self.ctx, trial_steps, self.stream)
 
     def bin_smoothed(self):
         """Smoothed intensities J[o][e][t] and (gradient mode) dJ[3][o][e][t]."""

@@ -37,7 +37,8 @@ def test_struct_sizes_match_header_layout(F):
     assert C.sizeof(F.fte_observer) == 48
     assert C.sizeof(F.fte_sizes) == 48
     assert C.sizeof(F.fte_buffers) == 64
-    assert C.sizeof(F.fte_injection) == 8 * 9 + 8 + 8 + 8 + 8 + 4 + 4
+    assert C.sizeof(F.fte_injection) == 8 * 9 + 8 + 8 + 8 + 8 + 4 + 4 + 8
+    assert C.sizeof(F.fte_run) == 24
 
 
 def test_query_sizes_valid(F):
@@ -123,3 +124,23 @@ def test_rejects_bad_params(F):
                  dict(q=2.5), dict(r_out=0.0), dict(run_id=70000), dict(precision=3)):
         with pytest.raises(F.FteError):
             F.fte_query_sizes(dict(cfg["params"], **over), cfg["grid"], 10)
+
+
+def test_ensemble_sizes_and_rejections(F):
+    cfg = W.tiny_parker()
+    p = cfg["params"]
+    runs = [dict(lambda_ref=0.1 * W.AU, kperp_ratio=0.01, n_steps=100), dict(lambda_ref=0.2 * W.AU, n_steps=50)]
+    one = F.fte_query_sizes(p, cfg["grid"], 100)
+    two = F.fte_query_sizes(dict(p, runs=runs), cfg["grid"], 100)
+    assert two.hist_bytes == 2 * one.hist_bytes              # sums per run
+    assert two.grid_bytes == one.grid_bytes // 10 * 14       # a run with kappa_perp: 13-field records
+    bad = [[dict(lambda_ref=-1.0, n_steps=5)], [dict(lambda_ref=1e10, n_steps=0)],
+           [dict(lambda_ref=1e10, kperp_ratio=-0.1, n_steps=5)], [dict(lambda_ref=1e10, n_steps=5)] * 65]
+    for r in bad:
+        with pytest.raises(F.FteError):
+            F.fte_query_sizes(dict(p, runs=r), cfg["grid"], 100)
+    with pytest.raises(F.FteError):        # ensembles do not combine with smoothing
+        F.fte_query_sizes(dict(p, runs=runs, smoothing=dict(sigma_x=1e9, sigma_lne=0.1, sigma_t=60.0)),
+                          cfg["grid"], 100)
+    with pytest.raises(F.FteError):        # run ids must fit 16 bits
+        F.fte_query_sizes(dict(p, runs=runs, run_id=65535), cfg["grid"], 100)
