@@ -194,6 +194,91 @@ def gradient_leg(F, W, raw, args):
     return out
 
 
+def ensemble_leg(F, W, args):
+    """Batched ensemble: 64 uneven runs (lambda, kappa ratio, particle and
+    step counts drawn per run) as one population, autotuned, against the same
+    runs stepped one context at a time with the default launch shape."""
+    import torch
+    dev = torch.device("cuda:0")
+    cfg = W.cir_ensemble(precision=args.precision)
+    g = cfg["grid"]
+    raw = W.make_raw(g, cfg["wind"], xp=torch, device=dev)
+    torch.cuda.synchronize()
+    p = cfg["params"]
+    N = cfg["n_particles"]
+    out = {"workload": cfg["name"], "runs": len(cfg["runs"]), "particles": N,
+           "max_steps": cfg["n_steps"], "snapshots": g["n_snap"], "leaves": int(len(g["leaves"]))}
+    chunk = 640
+
+    def ensemble(tune):
+        sim = F.Simulation(p, g, N)
+        sim.load_grid(raw)
+        sim.set_launch(args.block, args.spl, args.compact, args.sort)
+        injected = [0] * len(cfg["injections"])
+        best = None
+        torch.cuda.synchronize()
+        t_tune = 0.0
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = 0.0
+        n0 = 0
+        while n0 < cfg["n_steps"]:
+            n1 = min(n0 + chunk, cfg["n_steps"])
+            if tune and best is None and n0 >= 2 * chunk:
+                t = time.time()
+                best = sim.autotune(4 * args.spl)
+                t_tune = time.time() - t
+            e0.record()
+            for r, inj in enumerate(cfg["injections"]):
+                S, Nr = inj["n_inj_steps"], inj["n_total"]
+                j_max = min(Nr, int(math.ceil(n1 * Nr / S)) + 1)
+                if j_max > injected[r]:
+                    sim.inject(inj, j_max - injected[r], inj["pid0"] + injected[r])
+                    injected[r] = j_max
+            sim.step(n1 - n0)
+            e1.record()
+            torch.cuda.synchronize()
+            ms += e0.elapsed_time(e1)
+            n0 = n1
+        st = sim.stats()
+        sim.close()
+        return ms, int(st.particle_steps), best, t_tune
+
+    ms, steps, best, t_tune = ensemble(True)
+    out.update(ensemble_ms=round(ms, 1), particle_steps=steps, value=steps / (ms / 1e3),
+               autotuned=dict(block=best[0], steps_per_launch=best[1], compact_every=best[2]) if best else None,
+               autotune_s=round(t_tune, 2))
+    ms0, steps0, _, _ = ensemble(False)
+    out.update(ensemble_untuned_ms=round(ms0, 1))
+    # the same runs one context at a time (each loads the grid; not timed)
+    seq_ms = 0.0
+    seq_steps = 0
+    for r, run in enumerate(cfg["runs"]):
+        q = {k: v for k, v in p.items() if k != "runs"}
+        q.update(run_id=p["run_id"] + r, lambda_ref=run["lambda_ref"], kperp_ratio=run["kperp_ratio"])
+        inj = dict(cfg["injections"][r], run=0)
+        c1 = dict(cfg, params=q, injection=inj, n_particles=inj["n_total"])
+        rr = Run(F, c1, raw, args.precision, args.block, args.spl, args.compact, args.sort)
+        n_chunks = int(math.ceil(run["n_steps"] / chunk))
+        ch = int(math.ceil(run["n_steps"] / n_chunks))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        left = run["n_steps"]
+        while left > 0:
+            rr.chunk(min(ch, left))
+            left -= min(ch, left)
+        e1.record()
+        torch.cuda.synchronize()
+        seq_ms += e0.elapsed_time(e1)
+        seq_steps += int(rr.sim.stats().particle_steps)
+        rr.close()
+    out.update(sequential_ms=round(seq_ms, 1), sequential_particle_steps=seq_steps,
+               sequential_value=seq_steps / (seq_ms / 1e3), ensemble_speedup=round(seq_ms / ms, 3))
+    del raw
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(cfg, raw_gpu, n_pids, n_steps, n_threads):
     """The FP64 oracle on the first n_pids particles over the first n_steps
     steps, with the snapshots those steps touch copied to the host."""
@@ -231,6 +316,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble workload")
     ap.add_argument("--cpu-pids", type=int, default=4000)
     ap.add_argument("--cpu-steps", type=int, default=2800)
     ap.add_argument("--calib-copy", action="store_true", help="also run a 2 GiB device copy (counter calibration)")
@@ -318,6 +404,10 @@ def main():
     if not args.no_grad:
         log("differentiation workload: forward, smoothed forward, gradient, central differences")
         extra["gradient"] = gradient_leg(F, W, raw, args)
+
+    if not args.no_ensemble:
+        log("batched ensemble: 64 runs as one population vs one context at a time")
+        extra["ensemble"] = ensemble_leg(F, W, args)
 
     cpu = None
     if not args.no_cpu:
