@@ -56,7 +56,7 @@ class OrParams(C.Structure):
         ("kperp_ratio", C.c_double), ("lambda_perp", C.c_double),
         ("dt", C.c_double), ("t0", C.c_double), ("r_in", C.c_double), ("r_out", C.c_double),
         ("check_bounds", C.c_int), ("run_id", C.c_int), ("seed", C.c_uint64),
-        ("n_obs", C.c_int), ("obs", (C.c_double * 6) * 8),
+        ("n_obs", C.c_int), ("obs", (C.c_double * 6) * 8), ("obs_nphi", C.c_int * 8), ("obs_omega", C.c_double * 8),
         ("e_min", C.c_double), ("dlne", C.c_double), ("n_e", C.c_int),
         ("t_ref", C.c_double), ("dT", C.c_double), ("n_t", C.c_int), ("n_batch", C.c_int),
         ("bg_kind", C.c_int), ("bg", C.c_double * 16),
@@ -81,6 +81,7 @@ class OrInjection(C.Structure):
         ("ph_lo", C.c_double), ("ph_hi", C.c_double), ("e_lo", C.c_double), ("e_hi", C.c_double),
         ("gamma_inj", C.c_double), ("w0", C.c_double), ("r_weight", C.c_int), ("r_ref", C.c_double),
         ("pid0", C.c_uint64), ("n_total", C.c_uint64), ("k0", C.c_uint32), ("n_inj_steps", C.c_uint32),
+        ("region", C.c_int), ("r_hi", C.c_double), ("divv_max", C.c_double), ("max_tries", C.c_uint32),
     ]
 
 
@@ -118,9 +119,12 @@ def lib():
         L.or_run.argtypes = [C.POINTER(OrParams), C.c_void_p, C.c_long, dp, dp, dp, dp, u64p, u32p,
                              i32p, C.c_uint64, C.c_uint32, dp, dp, C.c_int]
         L.or_run.restype = C.c_uint64
-        L.or_inject.argtypes = [C.POINTER(OrParams), C.POINTER(OrInjection), C.c_long, C.c_uint64,
+        L.or_inject.argtypes = [C.POINTER(OrParams), C.c_void_p, C.POINTER(OrInjection), C.c_long, C.c_uint64,
                                 dp, dp, dp, dp, u64p, u32p, i32p]
         L.or_finalize.argtypes = [C.POINTER(OrParams), dp, C.c_double, dp, dp]
+        L.or_finalize_steady.argtypes = [C.POINTER(OrParams), dp, C.c_double, dp, dp]
+        L.or_obs_bins.argtypes = [C.POINTER(OrParams)]
+        L.or_obs_bins.restype = C.c_int
         _lib = L
     return _lib
 
@@ -158,6 +162,8 @@ def make_params(p: dict) -> OrParams:
     for i, ob in enumerate(obs):
         for k in range(6):
             o.obs[i][k] = ob[k]
+        o.obs_nphi[i] = int(ob[6]) if len(ob) > 6 else 1
+        o.obs_omega[i] = float(ob[7]) if len(ob) > 7 else 0.0
     o.e_min = p.get("e_min", 1.0)
     o.dlne = p.get("dlne", 1.0)
     o.n_e = int(p.get("n_e", 1))
@@ -176,8 +182,14 @@ def make_params(p: dict) -> OrParams:
     return o
 
 
+def obs_bins(p: dict) -> int:
+    """Observer bins: each observer (r, theta, phi, dr, dtheta, dphi[, n_phi[,
+    omega]]) covers n_phi longitude bins."""
+    return sum(int(ob[6]) if len(ob) > 6 and int(ob[6]) > 1 else 1 for ob in p.get("observers", []))
+
+
 def hist_size(p: dict) -> int:
-    return len(p.get("observers", [])) * int(p.get("n_e", 1)) * int(p.get("n_t", 1)) * int(p.get("n_batch", 32))
+    return obs_bins(p) * int(p.get("n_e", 1)) * int(p.get("n_t", 1)) * int(p.get("n_batch", 32))
 
 
 class Grid:
@@ -315,6 +327,10 @@ def make_injection(inj: dict) -> OrInjection:
     o.n_total = int(inj["n_total"])
     o.k0 = int(inj.get("k0", 0))
     o.n_inj_steps = int(inj.get("n_inj_steps", 0))
+    o.region = int(inj.get("region", 0))
+    o.r_hi = inj.get("r_hi", inj["r"])
+    o.divv_max = inj.get("divv_max", 0.0)
+    o.max_tries = int(inj.get("max_tries", 4096))
     return o
 
 
@@ -343,11 +359,16 @@ class Particles:
         return self.subset(np.arange(len(self)))
 
 
-def inject(params: dict, inj: dict, n: int, first_pid: int) -> Particles:
+def inject(params: dict, inj: dict, n: int, first_pid: int, grid=None) -> Particles:
+    """Particles of an injection; the region law (inj["region"] = 1) needs the
+    grid it tests div V on."""
     o = make_params(params)
     io = make_injection(inj)
+    if io.region and grid is None:
+        raise ValueError("region injection needs the grid")
     p = Particles(n)
-    lib().or_inject(C.byref(o), C.byref(io), n, first_pid, _ptr(p.x, C.c_double), _ptr(p.mu, C.c_double),
+    lib().or_inject(C.byref(o), grid.h if grid is not None else None, C.byref(io), n, first_pid,
+                    _ptr(p.x, C.c_double), _ptr(p.mu, C.c_double),
                     _ptr(p.lnp, C.c_double), _ptr(p.w, C.c_double), _ptr(p.pid, C.c_uint64),
                     _ptr(p.kinj, C.c_uint32), _ptr(p.status, C.c_int32))
     return p
@@ -370,13 +391,27 @@ def run(params: dict, grid, parts: Particles, n0: int, n_steps: int, hist=None, 
 
 def finalize(params: dict, hist: np.ndarray, w_inj: float):
     o = make_params(params)
-    n = len(params.get("observers", [])) * int(params["n_e"]) * int(params["n_t"])
+    nob = obs_bins(params)
+    n = nob * int(params["n_e"]) * int(params["n_t"])
     j = np.zeros(n)
     s = np.zeros(n)
     h = np.ascontiguousarray(hist, dtype=np.float64)
     lib().or_finalize(C.byref(o), _ptr(h, C.c_double), w_inj, _ptr(j, C.c_double), _ptr(s, C.c_double))
-    shp = (len(params["observers"]), int(params["n_e"]), int(params["n_t"]))
+    shp = (nob, int(params["n_e"]), int(params["n_t"]))
     return j.reshape(shp), s.reshape(shp)
+
+
+def finalize_steady(params: dict, hist: np.ndarray, w_inj: float):
+    """Time-integrated intensities [observer bin][E] of a Green's-function
+    run: the steady state for a unit injection rate (section 2.3)."""
+    o = make_params(params)
+    nob = obs_bins(params)
+    n = nob * int(params["n_e"])
+    j = np.zeros(n)
+    s = np.zeros(n)
+    h = np.ascontiguousarray(hist, dtype=np.float64)
+    lib().or_finalize_steady(C.byref(o), _ptr(h, C.c_double), w_inj, _ptr(j, C.c_double), _ptr(s, C.c_double))
+    return j.reshape(nob, int(params["n_e"])), s.reshape(nob, int(params["n_e"]))
 
 
 def finalize_smoothed(params: dict, sm: np.ndarray, w_inj: float) -> np.ndarray:

@@ -29,6 +29,7 @@
 #define OR_PI  3.14159265358979323846
 
 enum { OR_ACTIVE = 0, OR_ABS_IN = 1, OR_ABS_OUT = 2, OR_OUT_DOMAIN = 3, OR_NUMERIC = 4 };
+
 enum { OR_DMM_ISO = 0, OR_DMM_EQ5 = 1, OR_DMM_POWER_Q = 2 };
 enum { OR_BG_GRID = 0, OR_BG_UNIFORM = 1, OR_BG_PAR_FLOW = 2, OR_BG_PERP_FLOW = 3, OR_BG_RADIAL = 4 };
 
@@ -54,6 +55,8 @@ typedef struct {
     uint64_t seed;
     int    n_obs;
     double obs[8][6];     /* r, theta, phi centre; dr, dtheta, dphi full widths  */
+    int    obs_nphi[8];   /* longitude bins of width dphi (ring observer), >= 1  */
+    double obs_omega[8];  /* rotation of the observer pattern, rad/s             */
     double e_min;         /* lower edge of energy bin 0, J                       */
     double dlne;          /* width of a bin in ln E                              */
     int    n_e;
@@ -65,6 +68,16 @@ typedef struct {
     int    smooth;        /* accumulate the kernel-smoothed intensity sums       */
     double sig_x, sig_lne, sig_t;  /* Gaussian widths: space (m), ln E, time (s) */
 } or_params;
+
+/* Observer bins: observer o covers obs_nphi[o] consecutive longitude bins. */
+static int or_nphi(const or_params *pp, int o) { return pp->obs_nphi[o] > 1 ? pp->obs_nphi[o] : 1; }
+
+int or_obs_bins(const or_params *pp)
+{
+    int n = 0;
+    for (int o = 0; o < pp->n_obs; ++o) n += or_nphi(pp, o);
+    return n;
+}
 
 typedef struct {
     int    xi_map;        /* 0: xi = r - r_lo, 1: xi = ln(r / r_lo)             */
@@ -832,7 +845,10 @@ static void or_step(const or_params *pp, const void *g, or_particle *pt, uint64_
         or_smooth_add(pp, xn, pp->t0 + (double)(n + 1) * pp->dt, pt->w, exp(lnpn), sm);
 
     /* Residence-time estimator of the intensity j = p^2 f = v n_E / (4 pi)
-     * (section 2.3): the post-step state adds w v dt to its bin. */
+     * (section 2.3): the post-step state adds w v dt to its bin.  Observer o
+     * is the radial x colatitude box around (r, theta) and obs_nphi[o]
+     * longitude bins of width dphi, the first centred at phi + omega t (t the
+     * post-step time): a box, a ring of bins, or one that corotates. */
     if (hist && pp->n_obs > 0) {
         double th = acos(xn[2] / r);
         double ph = atan2(xn[1], xn[0]);
@@ -840,21 +856,26 @@ static void or_step(const or_params *pp, const void *g, or_particle *pt, uint64_
         double Pn = exp(lnpn), vn = or_speed(Pn);
         double E = or_ekin(pp->mass, Pn);
         double ue = log(E / pp->e_min) / pp->dlne;
-        double ut = (pp->t0 + (double)(n + 1) * pp->dt - pp->t_ref) / pp->dT;
+        double t1 = pp->t0 + (double)(n + 1) * pp->dt;
+        double ut = (t1 - pp->t_ref) / pp->dT;
         if (ue >= 0.0 && ue < pp->n_e && ut >= 0.0 && ut < pp->n_t) {
             long ie = (long)floor(ue), it = (long)floor(ut);
             long ib = (long)(pt->pid % (uint64_t)pp->n_batch);
+            int off = 0;
             for (int o = 0; o < pp->n_obs; ++o) {
                 const double *ob = pp->obs[o];
-                double dph = ph - ob[2];
-                while (dph >= OR_PI) dph -= 2.0 * OR_PI;
-                while (dph < -OR_PI) dph += 2.0 * OR_PI;
+                int np = or_nphi(pp, o);
                 if (r >= ob[0] - 0.5 * ob[3] && r < ob[0] + 0.5 * ob[3] &&
-                    th >= ob[1] - 0.5 * ob[4] && th < ob[1] + 0.5 * ob[4] &&
-                    dph >= -0.5 * ob[5] && dph < 0.5 * ob[5]) {
-                    long idx = ((o * (long)pp->n_e + ie) * pp->n_t + it) * pp->n_batch + ib;
-                    hist[idx] += pt->w * vn * pp->dt;
+                    th >= ob[1] - 0.5 * ob[4] && th < ob[1] + 0.5 * ob[4]) {
+                    double u = fmod(ph - (ob[2] + pp->obs_omega[o] * t1 - 0.5 * ob[5]), 2.0 * OR_PI);
+                    if (u < 0.0) u += 2.0 * OR_PI;
+                    long k = (long)floor(u / ob[5]);
+                    if (k < np) {
+                        long idx = (((off + k) * (long)pp->n_e + ie) * pp->n_t + it) * pp->n_batch + ib;
+                        hist[idx] += pt->w * vn * pp->dt;
+                    }
                 }
+                off += np;
             }
         }
     }
@@ -868,7 +889,7 @@ uint64_t or_run(const or_params *pp, const void *g, long n, double *x, double *m
                 double *w, const uint64_t *pid, const uint32_t *kinj, int32_t *status,
                 uint64_t n0, uint32_t n_steps, double *hist, double *sm, int n_threads)
 {
-    long hsz = hist ? (long)pp->n_obs * pp->n_e * pp->n_t * pp->n_batch : 0;
+    long hsz = hist ? (long)or_obs_bins(pp) * pp->n_e * pp->n_t * pp->n_batch : 0;
     long ssz = sm ? (long)pp->n_obs * pp->n_e * pp->n_t : 0;
     uint64_t total = 0;
 #ifdef _OPENMP
@@ -954,12 +975,33 @@ typedef struct {
     uint64_t n_total;         /* particles in this injection                    */
     uint32_t k0;              /* first injection step                           */
     uint32_t n_inj_steps;     /* 0: all at k0; else stratified over this many   */
+    int    region;            /* 1: uniform in volume where div V < divv_max    */
+    double r_hi;              /* region: radii r .. r_hi                        */
+    double divv_max;          /* region: threshold on the cell's div V, 1/s     */
+    uint32_t max_tries;       /* region: attempts before giving up              */
 } or_injection;
 
-void or_inject(const or_params *pp, const or_injection *inj, long n, uint64_t first_pid,
+/* Region test of the paper's injection law: the leaf cell holding x has a
+ * converging wind, div V < divv_max, at snapshot k (the cell's own derived
+ * value, section 2.3: the region that traces the CIR shocks). */
+static int or_in_region(const or_grid *g, const double x[3], int k, double divv_max)
+{
+    double r, th, ph, s[3];
+    or_grid_coords(g, x, &r, &th, &ph, s);
+    int L;
+    long cm[3];
+    int leaf = or_find_leaf(g, s, &L, cm);
+    if (leaf < 0) return 0;
+    double d[13];
+    or_derived_leafcell(g, k, leaf, L, cm, d);
+    return d[6] < divv_max;
+}
+
+void or_inject(const or_params *pp, const void *gp, const or_injection *inj, long n, uint64_t first_pid,
                double *x, double *mu, double *lnp, double *w, uint64_t *pid, uint32_t *kinj,
                int32_t *status)
 {
+    const or_grid *g = (const or_grid *)gp;
     double mc2 = pp->mass * OR_C * OR_C;
     for (long i = 0; i < n; ++i) {
         uint64_t p = first_pid + (uint64_t)i;
@@ -967,16 +1009,52 @@ void or_inject(const or_params *pp, const or_injection *inj, long n, uint64_t fi
         or_philox_words(pp->seed, pp->run_id, 0, p, 1, ka);
         or_philox_words(pp->seed, pp->run_id, 1, p, 1, kb);
         double u0 = or_u01(ka[0]), u1 = or_u01(ka[1]), u2 = or_u01(ka[2]), u3 = or_u01(ka[3]);
+        /* first step: all at k0 or stratified over the injection window */
+        if (inj->n_inj_steps > 0) {
+            double j = (double)(p - inj->pid0);
+            kinj[i] = inj->k0 + (uint32_t)floor((j + or_u01(kb[0])) * (double)inj->n_inj_steps / (double)inj->n_total);
+        } else {
+            kinj[i] = inj->k0;
+        }
+        status[i] = OR_ACTIVE;
         /* isotropic pitch-angle cosine */
         mu[i] = 2.0 * u0 - 1.0;
-        /* uniform in solid angle over the patch */
         double c1 = cos(inj->th_lo), c2 = cos(inj->th_hi);
-        double ct = c1 + u1 * (c2 - c1);
-        double th = acos(ct);
-        double ph = inj->ph_lo + u2 * (inj->ph_hi - inj->ph_lo);
-        x[3 * i + 0] = inj->r * sin(th) * cos(ph);
-        x[3 * i + 1] = inj->r * sin(th) * sin(ph);
-        x[3 * i + 2] = inj->r * ct;
+        double rr = inj->r;
+        if (!inj->region) {
+            /* uniform in solid angle over the patch at radius r */
+            double ct = c1 + u1 * (c2 - c1);
+            double th = acos(ct);
+            double ph = inj->ph_lo + u2 * (inj->ph_hi - inj->ph_lo);
+            x[3 * i + 0] = rr * sin(th) * cos(ph);
+            x[3 * i + 1] = rr * sin(th) * sin(ph);
+            x[3 * i + 2] = rr * ct;
+        } else {
+            /* uniform in volume over the shell sector, kept where the wind
+             * converges (rejection: attempt a uses counter step 2 + a) */
+            int snap = 0;
+            if (g->d.n_snap_total >= 2) {
+                double t = pp->t0 + (double)kinj[i] * pp->dt;
+                snap = (int)floor((t - g->d.t_s0) / g->d.dt_s + 0.5);
+                if (snap < 0) snap = 0;
+                if (snap > g->d.n_snap_total - 1) snap = g->d.n_snap_total - 1;
+            }
+            double r3a = inj->r * inj->r * inj->r, r3b = inj->r_hi * inj->r_hi * inj->r_hi;
+            int ok = 0;
+            for (uint32_t a = 0; a < inj->max_tries && !ok; ++a) {
+                uint32_t kc[4];
+                or_philox_words(pp->seed, pp->run_id, 2 + (uint64_t)a, p, 1, kc);
+                rr = cbrt(r3a + or_u01(kc[0]) * (r3b - r3a));
+                double ct = c1 + or_u01(kc[1]) * (c2 - c1);
+                double st = sqrt(1.0 - ct * ct);
+                double ph = inj->ph_lo + or_u01(kc[2]) * (inj->ph_hi - inj->ph_lo);
+                x[3 * i + 0] = rr * st * cos(ph);
+                x[3 * i + 1] = rr * st * sin(ph);
+                x[3 * i + 2] = rr * ct;
+                ok = or_in_region(g, x + 3 * i, snap, inj->divv_max);
+            }
+            if (!ok) status[i] = OR_NUMERIC;
+        }
         /* energy: monoenergetic or log-uniform with a power-law weight */
         double E, wt = inj->w0;
         if (inj->e_hi > inj->e_lo) {
@@ -985,18 +1063,12 @@ void or_inject(const or_params *pp, const or_injection *inj, long n, uint64_t fi
         } else {
             E = inj->e_lo;
         }
-        if (inj->r_weight) wt *= (inj->r_ref / inj->r) * (inj->r_ref / inj->r);
+        /* the r^-2 weight of Eq. 6 */
+        if (inj->r_weight) wt *= (inj->r_ref / rr) * (inj->r_ref / rr);
         double eps = E / mc2;
         lnp[i] = log(sqrt(eps * (eps + 2.0)));
         w[i] = wt;
         pid[i] = p;
-        if (inj->n_inj_steps > 0) {
-            double j = (double)(p - inj->pid0);
-            kinj[i] = inj->k0 + (uint32_t)floor((j + or_u01(kb[0])) * (double)inj->n_inj_steps / (double)inj->n_total);
-        } else {
-            kinj[i] = inj->k0;
-        }
-        status[i] = OR_ACTIVE;
     }
 }
 
@@ -1005,30 +1077,75 @@ void or_inject(const or_params *pp, const or_injection *inj, long n, uint64_t fi
 void or_finalize(const or_params *pp, const double *hist, double w_inj, double *j, double *sigma)
 {
     int nb = pp->n_batch;
+    long ob_i = 0;
     for (int o = 0; o < pp->n_obs; ++o) {
         const double *ob = pp->obs[o];
         double r1 = ob[0] - 0.5 * ob[3], r2 = ob[0] + 0.5 * ob[3];
         double t1 = ob[1] - 0.5 * ob[4], t2 = ob[1] + 0.5 * ob[4];
         double dV = (r2 * r2 * r2 - r1 * r1 * r1) / 3.0 * (cos(t1) - cos(t2)) * ob[5];
-        for (int e = 0; e < pp->n_e; ++e) {
-            double dE = pp->e_min * (exp((e + 1) * pp->dlne) - exp(e * pp->dlne));
-            double norm = 4.0 * OR_PI * dV * pp->dT * dE * w_inj;
-            for (int t = 0; t < pp->n_t; ++t) {
-                const double *h = hist + ((o * (long)pp->n_e + e) * pp->n_t + t) * nb;
+        for (int k = 0; k < or_nphi(pp, o); ++k, ++ob_i) {
+            for (int e = 0; e < pp->n_e; ++e) {
+                double dE = pp->e_min * (exp((e + 1) * pp->dlne) - exp(e * pp->dlne));
+                double norm = 4.0 * OR_PI * dV * pp->dT * dE * w_inj;
+                for (int t = 0; t < pp->n_t; ++t) {
+                    const double *h = hist + ((ob_i * pp->n_e + e) * pp->n_t + t) * nb;
+                    double s = 0.0;
+                    for (int b = 0; b < nb; ++b) s += h[b];
+                    double jm = s / norm;
+                    double var = 0.0;
+                    for (int b = 0; b < nb; ++b) {
+                        double jb = nb * h[b] / norm;
+                        var += (jb - jm) * (jb - jm);
+                    }
+                    long idx = (ob_i * pp->n_e + e) * pp->n_t + t;
+                    j[idx] = jm;
+                    sigma[idx] = nb > 1 ? sqrt(var / ((double)nb * (nb - 1))) : 0.0;
+                }
+            }
+        }
+    }
+}
+
+/* Steady state for a constant injection rate from a Green's-function run
+ * (all particles injected at one time; section 2.3): the time integral of
+ * the intensity, i.e. the sum over time bins of j dT,
+ *   J[o][e] = sum_t S[o][e][t] / (4 pi dV dE W_inj),
+ * per unit injected weight per unit time; sigma from the batch estimates of
+ * the time-summed sums. */
+void or_finalize_steady(const or_params *pp, const double *hist, double w_inj, double *j, double *sigma)
+{
+    int nb = pp->n_batch;
+    long ob_i = 0;
+    double *sb = (double *)calloc((size_t)nb, sizeof(double));
+    for (int o = 0; o < pp->n_obs; ++o) {
+        const double *ob = pp->obs[o];
+        double r1 = ob[0] - 0.5 * ob[3], r2 = ob[0] + 0.5 * ob[3];
+        double t1 = ob[1] - 0.5 * ob[4], t2 = ob[1] + 0.5 * ob[4];
+        double dV = (r2 * r2 * r2 - r1 * r1 * r1) / 3.0 * (cos(t1) - cos(t2)) * ob[5];
+        for (int k = 0; k < or_nphi(pp, o); ++k, ++ob_i) {
+            for (int e = 0; e < pp->n_e; ++e) {
+                double dE = pp->e_min * (exp((e + 1) * pp->dlne) - exp(e * pp->dlne));
+                double norm = 4.0 * OR_PI * dV * dE * w_inj;
+                for (int b = 0; b < nb; ++b) sb[b] = 0.0;
+                for (int t = 0; t < pp->n_t; ++t) {
+                    const double *h = hist + ((ob_i * pp->n_e + e) * pp->n_t + t) * nb;
+                    for (int b = 0; b < nb; ++b) sb[b] += h[b];
+                }
                 double s = 0.0;
-                for (int b = 0; b < nb; ++b) s += h[b];
+                for (int b = 0; b < nb; ++b) s += sb[b];
                 double jm = s / norm;
                 double var = 0.0;
                 for (int b = 0; b < nb; ++b) {
-                    double jb = nb * h[b] / norm;
+                    double jb = nb * sb[b] / norm;
                     var += (jb - jm) * (jb - jm);
                 }
-                long idx = (o * (long)pp->n_e + e) * pp->n_t + t;
+                long idx = ob_i * pp->n_e + e;
                 j[idx] = jm;
                 sigma[idx] = nb > 1 ? sqrt(var / ((double)nb * (nb - 1))) : 0.0;
             }
         }
     }
+    free(sb);
 }
 
 int or_abi_version(void) { return 1; }
