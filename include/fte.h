@@ -77,10 +77,17 @@ enum {
 #define FTE_MAX_BATCH 64
 #define FTE_MAX_RUNS 64
 
-/* Spherical-box observer volume: r, theta, phi centre and full widths. */
+/* Observer: the radial x colatitude box of full widths dr, dtheta around
+ * (r, theta), and n_phi (>= 1; 0 counts as 1) consecutive longitude bins of
+ * width dphi, the first centred at phi + omega t (t the post-step time): a
+ * spherical box (n_phi = 1, omega = 0), a ring of bins for longitudinal
+ * profiles, or a corotating pattern (omega = the structure's rotation rate).
+ * Each longitude bin is one observer bin of the sums. */
 typedef struct {
     double r, theta, phi;
     double dr, dtheta, dphi;
+    int n_phi;
+    double omega;         /* rad/s                                                 */
 } fte_observer;
 
 /* One run of an ensemble: its own mean free path and cross-field ratio (the
@@ -193,6 +200,18 @@ typedef struct {
     uint32_t k0;
     uint32_t n_inj_steps;
     int run;              /* ensemble run the particles belong to (0 if none)     */
+    /* The paper's law (section 2.3, Eq. 6) when region = 1: positions uniform
+     * in volume over the shell sector r .. r_hi x [th_lo, th_hi] x
+     * [ph_lo, ph_hi], kept where the leaf cell holding the point has
+     * div V < divv_max at the snapshot nearest the particle's first step
+     * (rejection sampling on the injection stream, counter steps 2, 3, ...; a
+     * particle that finds no such point in max_tries attempts is retired with
+     * FTE_PS_NUMERIC); with r_weight the weight is (r_ref / r)^2 at the drawn
+     * radius. */
+    int region;
+    double r_hi;
+    double divv_max;      /* 1/s                                                   */
+    uint32_t max_tries;
 } fte_injection;
 
 /* Byte sizes of the caller-owned device buffers. */
@@ -279,10 +298,19 @@ fte_status fte_inject(fte_ctx *ctx, const fte_injection *inj, uint64_t n, uint64
 fte_status fte_step_n(fte_ctx *ctx, uint32_t n_steps, void *stream);
 
 /* Intensities j[o][e][t] = S / (4 pi dV dT dE W_inj) and their standard errors
- * from the n_batch batch sums, written to HOST arrays of n_obs*n_e*n_t doubles
+ * from the n_batch batch sums, o running over the observer bins (n_obs_bins =
+ * the sum of the observers' n_phi), written to HOST arrays of n_obs_bins*n_e*n_t doubles
  * (either may be NULL); for an ensemble [run][o][e][t] with each run's own
  * W_inj.  reset != 0 clears the sums afterwards.  Synchronises. */
 fte_status fte_bin_observers(fte_ctx *ctx, double *j, double *sigma, int reset, void *stream);
+
+/* Steady state of a Green's-function run (all particles started at one
+ * time; section 2.3): the time integral of the intensity, J[o][e] =
+ * sum_t S[o][e][t] / (4 pi dV dE W_inj), i.e. the intensity for a constant
+ * injection of unit weight per unit time, and its standard error from the
+ * batch sums; HOST arrays of n_obs_bins*n_e ([run][o][e] for an ensemble),
+ * either may be NULL.  Synchronises. */
+fte_status fte_bin_steady(fte_ctx *ctx, double *J, double *sigma, void *stream);
 
 /* Raw batch sums S[o][e][t][batch] (host array of n_obs*n_e*n_t*n_batch;
  * [run][o][e][t][batch] for an ensemble) and the injected weight (host array

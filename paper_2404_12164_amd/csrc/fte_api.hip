@@ -70,6 +70,14 @@ bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
 
 int runs_eff(const fte_params *p) { return p->n_runs > 0 ? p->n_runs : 1; }
 
+int obs_nphi(const fte_observer &o) { return o.n_phi > 1 ? o.n_phi : 1; }
+
+int obs_bins(const fte_params *p) {
+    int n = 0;
+    for (int o = 0; o < p->n_obs; ++o) n += obs_nphi(p->obs[o]);
+    return n;
+}
+
 // kappa_perp terms (and the 13-field records) are needed when any run has them
 bool needs_kperp(const fte_params *p) {
     if (p->kperp_ratio > 0.0 || p->lambda_perp > 0.0) return true;
@@ -118,13 +126,16 @@ std::string check_params(const fte_params *p) {
     if (p->n_obs > 0) {
         if (!finite_pos(p->e_min) || !finite_pos(p->dlne) || p->n_e < 1) return "bad energy bins";
         if (!finite_pos(p->dT) || p->n_t < 1 || !isfinite(p->t_ref)) return "bad time bins";
-        if ((double)p->n_obs * p->n_e * p->n_t * p->n_batch > 2e9) return "too many observer bins";
         for (int o = 0; o < p->n_obs; ++o) {
             const fte_observer &ob = p->obs[o];
             if (!finite_pos(ob.r) || !finite_pos(ob.dr) || !finite_pos(ob.dtheta) || !finite_pos(ob.dphi) ||
                 ob.dr >= 2 * ob.r || !isfinite(ob.theta) || !isfinite(ob.phi) || ob.dphi > 2 * kPi)
                 return "bad observer box";
+            if (ob.n_phi < 0 || ob.n_phi > 100000 || !isfinite(ob.omega)) return "bad observer ring";
+            if ((ob.n_phi > 1 || ob.omega != 0.0) && p->sigma_x > 0.0)
+                return "smoothed intensities need box observers (n_phi <= 1, omega = 0)";
         }
+        if ((double)obs_bins(p) * p->n_e * p->n_t * p->n_batch * runs_eff(p) > 2e9) return "too many observer bins";
     }
     if (p->n_runs < 0 || p->n_runs > FTE_MAX_RUNS) return "n_runs out of range";
     if (p->n_runs > 0) {
@@ -262,8 +273,8 @@ Layout layout(const fte_params *p, const fte_grid_desc *g, uint64_t n_max, size_
     L.off_info = L.off_child + align256(std::max<size_t>(n_child, 8) * 4);
     L.index = L.off_info + align256((size_t)g->n_leaves * 16);
     L.state = state_bytes(n_max);
-    const size_t nbins = (size_t)p->n_obs * p->n_e * p->n_t;
-    const size_t nbr = nbins * runs_eff(p);
+    const size_t nbins = (size_t)p->n_obs * p->n_e * p->n_t;          // smoothed (box observers)
+    const size_t nbr = (size_t)obs_bins(p) * p->n_e * p->n_t * runs_eff(p);
     L.hist = std::max<size_t>(nbr * p->n_batch * 8, 256);
     L.off_runs = align256(sizeof(DevCounters));
     L.off_j = L.off_runs + align256(FTE_MAX_RUNS * sizeof(DevRun));
@@ -340,7 +351,11 @@ void make_devparams(const fte_params *p, DevParams *d) {
         d->obs[o][2] = ob.theta - 0.5 * ob.dtheta;
         d->obs[o][3] = ob.theta + 0.5 * ob.dtheta;
         d->obs[o][4] = ob.phi;
-        d->obs[o][5] = 0.5 * ob.dphi;
+        d->obs[o][5] = ob.dphi;
+        d->obs_nphi[o] = obs_nphi(ob);
+        d->obs_omega[o] = ob.omega;
+        d->obs_off[o] = d->n_obs_bins;
+        d->n_obs_bins += d->obs_nphi[o];
     }
     d->seed = p->seed;
     d->dmm_model = p->dmm_model;
@@ -511,7 +526,7 @@ fte_status fte_bind_buffers(fte_ctx *c, const fte_grid_desc *g, uint64_t n_max, 
     c->fin_sm = (double *)(w + L.off_fin_sm);
     c->dl = (double *)(w + L.off_dl);
     c->out4 = (double *)(w + L.off_out4);
-    c->hist_n = (uint64_t)c->p.n_obs * c->p.n_e * c->p.n_t * c->p.n_batch * runs_eff(&c->p);
+    c->hist_n = (uint64_t)obs_bins(&c->p) * c->p.n_e * c->p.n_t * c->p.n_batch * runs_eff(&c->p);
     c->dp.runs = (const DevRun *)(w + L.off_runs);
 
     DevGrid &d = c->dg;
@@ -661,6 +676,10 @@ fte_status fte_inject(fte_ctx *c, const fte_injection *inj, uint64_t n, uint64_t
     if (inj->n_inj_steps > 0 && (first_pid < inj->pid0 || first_pid + n > inj->pid0 + inj->n_total))
         return fail(c, FTE_EINVAL, "pids outside the injection's range");
     if (inj->run < 0 || inj->run >= runs_eff(&c->p)) return fail(c, FTE_EINVAL, "injection run out of range");
+    if (inj->region != 0 && inj->region != 1) return fail(c, FTE_EINVAL, "region must be 0 or 1");
+    if (inj->region && (!(inj->r_hi >= inj->r) || !isfinite(inj->r_hi) || !isfinite(inj->divv_max) ||
+                        inj->max_tries < 1 || !(inj->ph_hi >= inj->ph_lo) || !(inj->th_hi >= inj->th_lo)))
+        return fail(c, FTE_EINVAL, "bad injection region");
     if (n == 0) return FTE_OK;
     hipStream_t s = (hipStream_t)stream;
     if (c->n_upper + n > c->n_max) {
@@ -668,7 +687,8 @@ fte_status fte_inject(fte_ctx *c, const fte_injection *inj, uint64_t n, uint64_t
         if (r != FTE_OK) return r;
         if (c->n_upper + n > c->n_max) return fail(c, FTE_ENOMEM, "particle capacity exceeded");
     }
-    HIPCHK(c, launch_inject(c->dp, *inj, c->st[c->cur], c->tn[c->cur], c->cnt, c->cur, n, first_pid, s));
+    HIPCHK(c, launch_inject(c->dp, c->dg, c->p.precision == FTE_MIXED, *inj, c->st[c->cur], c->tn[c->cur], c->cnt,
+                            c->cur, n, first_pid, s));
     HIPCHK(c, launch_add_live(c->cnt, c->cur, n, s));
     c->n_upper += n;
     c->injected_since += n;
@@ -738,12 +758,26 @@ fte_status fte_bin_observers(fte_ctx *c, double *j, double *sigma, int reset, vo
     if (!c) return FTE_EINVAL;
     if (!c->loaded) return fail(c, FTE_ESTATE, "nothing to bin before the grid is loaded");
     hipStream_t s = (hipStream_t)stream;
-    const size_t nb = (size_t)c->p.n_obs * c->p.n_e * c->p.n_t * runs_eff(&c->p);
+    const size_t nb = (size_t)obs_bins(&c->p) * c->p.n_e * c->p.n_t * runs_eff(&c->p);
     if (nb > 0) {
         HIPCHK(c, launch_finalize(c->dp, (const double *)c->b.hist, c->cnt, c->fin_j, c->fin_s, s));
         if (j) HIPCHK(c, hipMemcpyAsync(j, c->fin_j, nb * 8, hipMemcpyDeviceToHost, s));
         if (sigma) HIPCHK(c, hipMemcpyAsync(sigma, c->fin_s, nb * 8, hipMemcpyDeviceToHost, s));
         if (reset) HIPCHK(c, launch_zero((double *)c->b.hist, c->hist_n, s));
+    }
+    HIPCHK(c, hipStreamSynchronize(s));
+    return FTE_OK;
+}
+
+fte_status fte_bin_steady(fte_ctx *c, double *J, double *sigma, void *stream) {
+    if (!c) return FTE_EINVAL;
+    if (!c->loaded) return fail(c, FTE_ESTATE, "nothing to bin before the grid is loaded");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = (size_t)obs_bins(&c->p) * c->p.n_e * runs_eff(&c->p);
+    if (nb > 0) {
+        HIPCHK(c, launch_finalize_steady(c->dp, (const double *)c->b.hist, c->cnt, c->fin_j, c->fin_s, s));
+        if (J) HIPCHK(c, hipMemcpyAsync(J, c->fin_j, nb * 8, hipMemcpyDeviceToHost, s));
+        if (sigma) HIPCHK(c, hipMemcpyAsync(sigma, c->fin_s, nb * 8, hipMemcpyDeviceToHost, s));
     }
     HIPCHK(c, hipStreamSynchronize(s));
     return FTE_OK;

@@ -63,6 +63,7 @@ struct M<double> {
     static __device__ __forceinline__ double acos_(double x) { return ::acos(x); }
     static __device__ __forceinline__ double atan2_(double y, double x) { return ::atan2(y, x); }
     static __device__ __forceinline__ double floor_(double x) { return ::floor(x); }
+    static __device__ __forceinline__ double fmod_(double x, double y) { return ::fmod(x, y); }
     // quotients in the double path stay correctly rounded
     static __device__ __forceinline__ double div_(double a, double b) { return a / b; }
     static __device__ __forceinline__ double u01(uint32_t k) { return ((double)k + 0.5) * (1.0 / 4294967296.0); }
@@ -79,6 +80,7 @@ struct M<float> {
     static __device__ __forceinline__ float acos_(float x) { return ::acosf(x); }
     static __device__ __forceinline__ float atan2_(float y, float x) { return ::atan2f(y, x); }
     static __device__ __forceinline__ float floor_(float x) { return ::floorf(x); }
+    static __device__ __forceinline__ float fmod_(float x, float y) { return ::fmodf(x, y); }
     // quotients in the float path: hardware reciprocal (1 ulp) times numerator
     static __device__ __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
     // top 24 bits: strictly inside (0, 1) in float

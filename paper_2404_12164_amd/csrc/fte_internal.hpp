@@ -36,7 +36,11 @@ struct DevParams {
     double e_min_ln, inv_dlne;   // ln(e_min), 1 / dlne
     double e_min, dlne, dT;
     double t_ref, inv_dT;
-    double obs[FTE_MAX_OBS][6];  // r1, r2, th1, th2, phi centre, half width phi
+    double obs[FTE_MAX_OBS][6];  // r1, r2, th1, th2, phi centre of bin 0, bin width phi
+    double obs_omega[FTE_MAX_OBS];   // rotation of each observer's pattern
+    int obs_nphi[FTE_MAX_OBS];       // longitude bins per observer
+    int obs_off[FTE_MAX_OBS];        // its first observer bin
+    int n_obs_bins;
     // kernel-smoothed intensities (smooth != 0)
     double obs_xyz[FTE_MAX_OBS][3];  // observer centres, Cartesian
     double sx_cut2;          // (kKernelCut sigma_x)^2
@@ -141,8 +145,8 @@ hipError_t launch_derive(const DevGrid &g, const double *raw, int snap, const do
                          int fp32, hipStream_t s);
 hipError_t launch_record_ghost(const DevGrid &g, int snap, void *rec, int fp32, DevCounters *cnt, hipStream_t s);
 hipError_t launch_check_raw(const DevGrid &g, const double *raw, DevCounters *cnt, hipStream_t s);
-hipError_t launch_inject(const DevParams &p, const fte_injection &inj, DevState st, DevTan tn, DevCounters *cnt,
-                         int slot, uint64_t n, uint64_t first_pid, hipStream_t s);
+hipError_t launch_inject(const DevParams &p, const DevGrid &g, int rec_fp32, const fte_injection &inj, DevState st,
+                         DevTan tn, DevCounters *cnt, int slot, uint64_t n, uint64_t first_pid, hipStream_t s);
 hipError_t launch_add_live(DevCounters *cnt, int slot, uint64_t n, hipStream_t s);
 hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
                        double *hist, double *sm, uint64_t n0, uint32_t n_steps, uint64_t n_upper, int block, int fp32,
@@ -156,6 +160,8 @@ hipError_t launch_compact_sorted(const DevGrid &g, int sort, DevState src, DevSt
                                  uint32_t *tsum, hipStream_t s);
 hipError_t launch_finalize(const DevParams &p, const double *hist, const DevCounters *cnt, double *j, double *sig,
                            hipStream_t s);
+hipError_t launch_finalize_steady(const DevParams &p, const double *hist, const DevCounters *cnt, double *j,
+                                  double *sig, hipStream_t s);
 hipError_t launch_smooth_finalize(const DevParams &p, const double *sm, double *out, hipStream_t s);
 hipError_t launch_grad_contract(const DevParams &p, const double *fin, const double *dl, double *out4, hipStream_t s);
 hipError_t launch_zero(double *p, uint64_t n, hipStream_t s);

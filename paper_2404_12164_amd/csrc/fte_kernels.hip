@@ -323,89 +323,6 @@ hipError_t launch_record_ghost(const DevGrid &g, int snap, void *rec, int fp32, 
 }
 
 // ===========================================================================
-// injection
-// ===========================================================================
-__global__ void k_inject(DevParams P, fte_injection inj, DevState st, DevTan tn, DevCounters *cnt, int slot,
-                         uint64_t n, uint64_t first_pid) {
-    __shared__ double wsum[FTE_MAX_BATCH];
-    __shared__ double wdg;
-    for (int b = threadIdx.x; b < FTE_MAX_BATCH; b += blockDim.x) wsum[b] = 0.0;
-    if (threadIdx.x == 0) wdg = 0.0;
-    __syncthreads();
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        const uint64_t base = cnt->n_live[slot];
-        const uint64_t pid = first_pid + i;
-        const int rid = P.n_runs > 0 ? P.runs[inj.run].run_id : P.run_id;
-        const U4 ka = philox_words(P.seed, rid, 0, pid, 1u);
-        const U4 kb = philox_words(P.seed, rid, 1, pid, 1u);
-        const double u0 = M<double>::u01(ka.a), u1 = M<double>::u01(ka.b);
-        const double u2 = M<double>::u01(ka.c), u3 = M<double>::u01(ka.d);
-        const double mu = 2.0 * u0 - 1.0;
-        const double c1 = ::cos(inj.th_lo), c2 = ::cos(inj.th_hi);
-        const double ct = c1 + u1 * (c2 - c1);
-        const double th = ::acos(ct);
-        const double ph = inj.ph_lo + u2 * (inj.ph_hi - inj.ph_lo);
-        double E, wt = inj.w0, dlnw = 0.0;
-        if (inj.e_hi > inj.e_lo) {
-            E = ::exp(::log(inj.e_lo) + u3 * (::log(inj.e_hi) - ::log(inj.e_lo)));
-            wt *= ::pow(E / inj.e_lo, 1.0 - inj.gamma_inj);
-            dlnw = -::log(E / inj.e_lo);     // d ln w / d gamma_inj
-        } else {
-            E = inj.e_lo;
-        }
-        if (inj.r_weight) wt *= (inj.r_ref / inj.r) * (inj.r_ref / inj.r);
-        const double eps = E / P.mass_c2;
-        const uint64_t j = base + i;
-        st.x[j] = inj.r * ::sin(th) * ::cos(ph);
-        st.y[j] = inj.r * ::sin(th) * ::sin(ph);
-        st.z[j] = inj.r * ct;
-        st.mu[j] = mu;
-        st.lnp[j] = ::log(::sqrt(eps * (eps + 2.0)));
-        st.w[j] = wt;
-        st.pid[j] = pid;
-        uint32_t k = inj.k0;
-        if (inj.n_inj_steps > 0) {
-            const double jj = (double)(pid - inj.pid0);
-            k = inj.k0 + (uint32_t)::floor((jj + M<double>::u01(kb.a)) * (double)inj.n_inj_steps /
-                                           (double)inj.n_total);
-        }
-        st.kinj[j] = k;
-        st.status[j] = FTE_PS_ACTIVE;
-        st.run[j] = (uint16_t)inj.run;
-        atomicAdd(&wsum[pid % (uint64_t)P.n_batch], wt);
-        if (P.grad) {
-            for (int q = 0; q < kTanLnw; ++q) tn.col(q)[j] = 0.0;
-            tn.col(kTanLnw)[j] = dlnw;
-            atomicAdd(&wdg, wt * dlnw);
-        }
-    }
-    __syncthreads();
-    for (int b = threadIdx.x; b < P.n_batch; b += blockDim.x)
-        if (wsum[b] != 0.0) atomicAdd(&cnt->w_inj[inj.run * P.n_batch + b], wsum[b]);
-    if (threadIdx.x == 0 && wdg != 0.0) atomicAdd(&cnt->w_inj_dgamma, wdg);
-}
-
-__global__ void k_add_live(DevCounters *cnt, int slot, uint64_t n) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        cnt->n_live[slot] += n;
-        cnt->injected += n;
-    }
-}
-
-hipError_t launch_inject(const DevParams &p, const fte_injection &inj, DevState st, DevTan tn, DevCounters *cnt,
-                         int slot, uint64_t n, uint64_t first_pid, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_inject, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, inj, st, tn, cnt, slot, n, first_pid);
-    return hipGetLastError();
-}
-
-hipError_t launch_add_live(DevCounters *cnt, int slot, uint64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_add_live, dim3(1), dim3(64), 0, s, cnt, slot, n);
-    return hipGetLastError();
-}
-
-// ===========================================================================
 // the step kernel
 // ===========================================================================
 template <typename R>
@@ -485,6 +402,156 @@ __device__ __forceinline__ void fold_s(const DevGrid &G, R s[3]) {
     } else {
         s[2] = (s[2] >= (R)0) ? (s[2] > n ? n : s[2]) : (R)0;
     }
+}
+
+// ===========================================================================
+// injection
+// ===========================================================================
+// Region test of the paper's injection law (section 2.3): the leaf cell
+// holding x has div V < divv_max at snapshot k (its own record value).
+__device__ bool in_region(const DevGrid &G, int rec_fp32, double x, double y, double z, int k, double divv_max) {
+    const double r = ::sqrt(x * x + y * y + z * z);
+    const double th = ::acos(z / r);
+    double ph = ::atan2(y, x);
+    if (ph < 0.0) ph += 2.0 * kPi;
+    double s[3];
+    grid_coords<double>(G, r, th, ph, s);
+    fold_s<double>(G, s);
+    int B[3], L;
+    double S[3];
+    const int leaf = descend<double>(G, G.base, G.child, s, S, B, &L);
+    if (leaf < 0) return false;
+    int loc[3];
+    for (int a = 0; a < 3; ++a) {
+        const int n = G.n1[a] << (L - 1);
+        int c = (int)::floor(S[a]);
+        c = c > n - 1 ? n - 1 : c;
+        loc[a] = c - B[a] * G.bx[a];
+    }
+    const size_t pc = (size_t)(loc[0] + 1) + (size_t)G.px[0] * ((loc[1] + 1) + (size_t)G.px[1] * (loc[2] + 1));
+    const size_t at = (((size_t)k * G.n_leaves + leaf) * G.pcells + pc) * G.rs + 6;
+    const double dv = rec_fp32 ? (double)reinterpret_cast<const float *>(G.rec)[at]
+                               : reinterpret_cast<const double *>(G.rec)[at];
+    return dv < divv_max;
+}
+
+__global__ void k_inject(DevParams P, DevGrid G, int rec_fp32, fte_injection inj, DevState st, DevTan tn,
+                         DevCounters *cnt, int slot, uint64_t n, uint64_t first_pid) {
+    __shared__ double wsum[FTE_MAX_BATCH];
+    __shared__ double wdg;
+    for (int b = threadIdx.x; b < FTE_MAX_BATCH; b += blockDim.x) wsum[b] = 0.0;
+    if (threadIdx.x == 0) wdg = 0.0;
+    __syncthreads();
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const uint64_t base = cnt->n_live[slot];
+        const uint64_t pid = first_pid + i;
+        const int rid = P.n_runs > 0 ? P.runs[inj.run].run_id : P.run_id;
+        const U4 ka = philox_words(P.seed, rid, 0, pid, 1u);
+        const U4 kb = philox_words(P.seed, rid, 1, pid, 1u);
+        const double u0 = M<double>::u01(ka.a), u1 = M<double>::u01(ka.b);
+        const double u2 = M<double>::u01(ka.c), u3 = M<double>::u01(ka.d);
+        // first step: all at k0 or stratified over the injection window
+        uint32_t k = inj.k0;
+        if (inj.n_inj_steps > 0) {
+            const double jj = (double)(pid - inj.pid0);
+            k = inj.k0 + (uint32_t)::floor((jj + M<double>::u01(kb.a)) * (double)inj.n_inj_steps /
+                                           (double)inj.n_total);
+        }
+        const double mu = 2.0 * u0 - 1.0;
+        const double c1 = ::cos(inj.th_lo), c2 = ::cos(inj.th_hi);
+        double rr = inj.r, px, py, pz;
+        int status = FTE_PS_ACTIVE;
+        if (!inj.region) {
+            // uniform in solid angle over the patch at radius r
+            const double ct = c1 + u1 * (c2 - c1);
+            const double th = ::acos(ct);
+            const double ph = inj.ph_lo + u2 * (inj.ph_hi - inj.ph_lo);
+            px = rr * ::sin(th) * ::cos(ph);
+            py = rr * ::sin(th) * ::sin(ph);
+            pz = rr * ct;
+        } else {
+            // uniform in volume over the shell sector, kept where the wind
+            // converges; attempt a draws from counter step 2 + a
+            int snap = 0;
+            if (G.n_snap >= 2) {
+                const double t = P.t0 + (double)k * P.dt;
+                double f = ::floor((t - G.t_s0) / G.dt_s + 0.5);
+                f = f < 0.0 ? 0.0 : (f > (double)(G.n_snap - 1) ? (double)(G.n_snap - 1) : f);
+                snap = (int)f;
+            }
+            const double r3a = inj.r * inj.r * inj.r, r3b = inj.r_hi * inj.r_hi * inj.r_hi;
+            bool ok = false;
+            px = py = pz = 0.0;
+            for (uint32_t a = 0; a < inj.max_tries && !ok; ++a) {
+                const U4 kc = philox_words(P.seed, rid, 2 + (uint64_t)a, pid, 1u);
+                rr = ::cbrt(r3a + M<double>::u01(kc.a) * (r3b - r3a));
+                const double ct = c1 + M<double>::u01(kc.b) * (c2 - c1);
+                const double stt = ::sqrt(1.0 - ct * ct);
+                const double ph = inj.ph_lo + M<double>::u01(kc.c) * (inj.ph_hi - inj.ph_lo);
+                px = rr * stt * ::cos(ph);
+                py = rr * stt * ::sin(ph);
+                pz = rr * ct;
+                ok = in_region(G, rec_fp32, px, py, pz, snap, inj.divv_max);
+            }
+            if (!ok) status = FTE_PS_NUMERIC;
+        }
+        double E, wt = inj.w0, dlnw = 0.0;
+        if (inj.e_hi > inj.e_lo) {
+            E = ::exp(::log(inj.e_lo) + u3 * (::log(inj.e_hi) - ::log(inj.e_lo)));
+            wt *= ::pow(E / inj.e_lo, 1.0 - inj.gamma_inj);
+            dlnw = -::log(E / inj.e_lo);     // d ln w / d gamma_inj
+        } else {
+            E = inj.e_lo;
+        }
+        if (inj.r_weight) wt *= (inj.r_ref / rr) * (inj.r_ref / rr);
+        const double eps = E / P.mass_c2;
+        const uint64_t j = base + i;
+        st.x[j] = px;
+        st.y[j] = py;
+        st.z[j] = pz;
+        st.mu[j] = mu;
+        st.lnp[j] = ::log(::sqrt(eps * (eps + 2.0)));
+        st.w[j] = wt;
+        st.pid[j] = pid;
+        st.kinj[j] = k;
+        st.status[j] = status;
+        st.run[j] = (uint16_t)inj.run;
+        if (status != FTE_PS_ACTIVE) {
+            atomicAdd(&cnt->retired[status], 1ull);
+            atomicAdd(&cnt->w_retired[status], wt);
+        }
+        atomicAdd(&wsum[pid % (uint64_t)P.n_batch], wt);
+        if (P.grad) {
+            for (int q = 0; q < kTanLnw; ++q) tn.col(q)[j] = 0.0;
+            tn.col(kTanLnw)[j] = dlnw;
+            atomicAdd(&wdg, wt * dlnw);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < P.n_batch; b += blockDim.x)
+        if (wsum[b] != 0.0) atomicAdd(&cnt->w_inj[inj.run * P.n_batch + b], wsum[b]);
+    if (threadIdx.x == 0 && wdg != 0.0) atomicAdd(&cnt->w_inj_dgamma, wdg);
+}
+
+__global__ void k_add_live(DevCounters *cnt, int slot, uint64_t n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        cnt->n_live[slot] += n;
+        cnt->injected += n;
+    }
+}
+
+hipError_t launch_inject(const DevParams &p, const DevGrid &g, int rec_fp32, const fte_injection &inj, DevState st,
+                         DevTan tn, DevCounters *cnt, int slot, uint64_t n, uint64_t first_pid, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_inject, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, g, rec_fp32, inj, st, tn, cnt, slot, n,
+                       first_pid);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_live(DevCounters *cnt, int slot, uint64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_add_live, dim3(1), dim3(64), 0, s, cnt, slot, n);
+    return hipGetLastError();
 }
 
 // Locate the leaf holding level-1 coordinates s and gather + interpolate the
@@ -686,7 +753,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
     const uint64_t n_live = cnt->n_live[slot];
     unsigned long long my_steps = 0;
     double *lh = reinterpret_cast<double *>(k_step_lds);
-    const int n_lh = LD.n_tb > 0 ? P.n_runs_eff * P.n_obs * P.n_e * LD.n_tb * P.n_batch : 0;
+    const int n_lh = LD.n_tb > 0 ? P.n_runs_eff * P.n_obs_bins * P.n_e * LD.n_tb * P.n_batch : 0;
     const int32_t *ibase = G.base, *ichild = G.child;
     if constexpr (LIDX) {
         int32_t *lb = reinterpret_cast<int32_t *>(k_step_lds + (size_t)n_lh * 8);
@@ -1049,17 +1116,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                     }
                 }
             }
-            // ---- residence-time observer estimator, post-step state: the box
-            // tests come first, the energy bin only for a particle inside one
+            // ---- residence-time observer estimator, post-step state: the
+            // radial and colatitude tests come first, then the longitude bin
+            // of each observer (rotating with it), the energy bin only for a
+            // particle inside one
             if (P.n_obs > 0) {
                 const double ut = (t + P.dt - P.t_ref) * P.inv_dT;
+                const double t1 = P.t0 + (double)(n + 1) * P.dt;
                 for (int o = 0; o < P.n_obs; ++o) {
                     const double *ob = P.obs[o];
                     if (!(r >= ob[0] && r < ob[1] && th >= (R)ob[2] && th < (R)ob[3])) continue;
-                    R dph = ph - (R)ob[4];
-                    while (dph >= (R)kPi) dph -= (R)(2.0 * kPi);
-                    while (dph < (R)-kPi) dph += (R)(2.0 * kPi);
-                    if (!(dph >= (R)-ob[5] && dph < (R)ob[5])) continue;
+                    R u = M<R>::fmod_(ph - (R)(ob[4] + P.obs_omega[o] * t1 - 0.5 * ob[5]), (R)(2.0 * kPi));
+                    if (u < (R)0) u += (R)(2.0 * kPi);
+                    const int kb = (int)M<R>::floor_(M<R>::div_(u, (R)ob[5]));
+                    if (!(kb >= 0 && kb < P.obs_nphi[o])) continue;
+                    const int obin = P.obs_off[o] + kb;
                     const R lnE = M<R>::log_((R)P.mass_c2 * M<R>::div_(Pcur * Pcur, gcur + (R)1));
                     const R ue = (lnE - (R)P.e_min_ln) * (R)P.inv_dlne;
                     if (ue >= (R)0 && ue < (R)P.n_e && ut >= 0.0 && ut < (double)P.n_t) {
@@ -1068,13 +1139,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                         const int ib = (int)(pid % (uint64_t)P.n_batch);
                         const double add = w * (double)vcur * P.dt;
                         const int lt = it - LD.it_lo;
+                        const size_t rob = (size_t)run_r * P.n_obs_bins + obin;
                         if (lt >= 0 && lt < LD.n_tb) {
-                            atomicAdd(&lh[((((size_t)run_r * P.n_obs + o) * P.n_e + ie) * LD.n_tb + lt) * P.n_batch + ib],
-                                      add);
+                            atomicAdd(&lh[((rob * P.n_e + ie) * LD.n_tb + lt) * P.n_batch + ib], add);
                         } else {
-                            const size_t hidx =
-                                ((((size_t)run_r * P.n_obs + o) * P.n_e + ie) * P.n_t + it) * P.n_batch + ib;
-                            atomicAdd(&hist[hidx], add);
+                            atomicAdd(&hist[((rob * P.n_e + ie) * P.n_t + it) * P.n_batch + ib], add);
                         }
                     }
                 }
@@ -1164,14 +1233,14 @@ StepLds plan_step_lds(const DevParams &p, const DevGrid &g, uint64_t n0, uint32_
         fb = fb > (double)(p.n_t - 1) ? (double)(p.n_t - 1) : fb;
         if (fb >= fa) {
             const int ntb = (int)(fb - fa) + 1;
-            const size_t bytes = (size_t)p.n_runs_eff * p.n_obs * p.n_e * ntb * p.n_batch * 8;
+            const size_t bytes = (size_t)p.n_runs_eff * p.n_obs_bins * p.n_e * ntb * p.n_batch * 8;
             if (bytes <= kLdsHistBytes) {
                 ld.it_lo = (int)fa;
                 ld.n_tb = ntb;
             }
         }
     }
-    const size_t hb = ld.n_tb > 0 ? (size_t)p.n_runs_eff * p.n_obs * p.n_e * ld.n_tb * p.n_batch * 8 : 0;
+    const size_t hb = ld.n_tb > 0 ? (size_t)p.n_runs_eff * p.n_obs_bins * p.n_e * ld.n_tb * p.n_batch * 8 : 0;
     const size_t ib = ((size_t)g.n_base + g.n_child) * 4;
     *lidx = ib <= kLdsIndexBytes;
     *shmem = hb + (*lidx ? ib : 0);
@@ -1403,18 +1472,28 @@ hipError_t launch_compact_sorted(const DevGrid &g, int sort, DevState src, DevSt
 // ===========================================================================
 // finalisation: j = S / (4 pi dV dT dE W_inj), standard error from batches
 // ===========================================================================
+// observer owning observer bin ob
+__device__ __forceinline__ int obs_of_bin(const DevParams &P, int ob) {
+    int o = 0;
+    while (o + 1 < P.n_obs && ob >= P.obs_off[o + 1]) ++o;
+    return o;
+}
+
+__device__ __forceinline__ double obs_volume(const DevParams &P, int o) {
+    const double *ob = P.obs[o];
+    return (ob[1] * ob[1] * ob[1] - ob[0] * ob[0] * ob[0]) / 3.0 * (::cos(ob[2]) - ::cos(ob[3])) * ob[5];
+}
+
 __global__ void k_finalize(DevParams P, const double *hist, const DevCounters *cnt, double *j, double *sig) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nb = P.n_obs * P.n_e * P.n_t;
+    const int nb = P.n_obs_bins * P.n_e * P.n_t;
     if (idx >= nb * P.n_runs_eff) return;
     const int run = idx / nb;
-    const int o = (idx % nb) / (P.n_e * P.n_t);
+    const int obin = (idx % nb) / (P.n_e * P.n_t);
     const int e = (idx / P.n_t) % P.n_e;
     double W = 0.0;
     for (int b = 0; b < P.n_batch; ++b) W += cnt->w_inj[run * P.n_batch + b];
-    const double *ob = P.obs[o];
-    const double dV = (ob[1] * ob[1] * ob[1] - ob[0] * ob[0] * ob[0]) / 3.0 * (::cos(ob[2]) - ::cos(ob[3])) *
-                      (2.0 * ob[5]);
+    const double dV = obs_volume(P, obs_of_bin(P, obin));
     const double dE = P.e_min * (::exp((e + 1) * P.dlne) - ::exp(e * P.dlne));
     const double norm = 4.0 * kPi * dV * P.dT * dE * W;
     const double *h = hist + (size_t)idx * P.n_batch;
@@ -1430,9 +1509,48 @@ __global__ void k_finalize(DevParams P, const double *hist, const DevCounters *c
     sig[idx] = P.n_batch > 1 ? ::sqrt(var / ((double)P.n_batch * (P.n_batch - 1))) : 0.0;
 }
 
+// Steady state of a Green's-function run: time-summed sums per batch, then
+// J = S / (4 pi dV dE W_inj) and the batch standard error.
+__global__ void k_finalize_steady(DevParams P, const double *hist, const DevCounters *cnt, double *j, double *sig) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nb = P.n_obs_bins * P.n_e;
+    if (idx >= nb * P.n_runs_eff) return;
+    const int run = idx / nb;
+    const int obin = (idx % nb) / P.n_e;
+    const int e = idx % P.n_e;
+    double W = 0.0;
+    for (int b = 0; b < P.n_batch; ++b) W += cnt->w_inj[run * P.n_batch + b];
+    const double dV = obs_volume(P, obs_of_bin(P, obin));
+    const double dE = P.e_min * (::exp((e + 1) * P.dlne) - ::exp(e * P.dlne));
+    const double norm = 4.0 * kPi * dV * dE * W;
+    const double *h = hist + (size_t)idx * P.n_t * P.n_batch;
+    double sb[FTE_MAX_BATCH];
+    for (int b = 0; b < P.n_batch; ++b) sb[b] = 0.0;
+    for (int t = 0; t < P.n_t; ++t)
+        for (int b = 0; b < P.n_batch; ++b) sb[b] += h[(size_t)t * P.n_batch + b];
+    double s = 0.0;
+    for (int b = 0; b < P.n_batch; ++b) s += sb[b];
+    const double jm = W > 0.0 ? s / norm : 0.0;
+    double var = 0.0;
+    for (int b = 0; b < P.n_batch; ++b) {
+        const double jb = W > 0.0 ? P.n_batch * sb[b] / norm : 0.0;
+        var += (jb - jm) * (jb - jm);
+    }
+    j[idx] = jm;
+    sig[idx] = P.n_batch > 1 ? ::sqrt(var / ((double)P.n_batch * (P.n_batch - 1))) : 0.0;
+}
+
+hipError_t launch_finalize_steady(const DevParams &p, const double *hist, const DevCounters *cnt, double *j,
+                                  double *sig, hipStream_t s) {
+    const int n = p.n_obs_bins * p.n_e * p.n_runs_eff;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize_steady, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, hist, cnt, j, sig);
+    return hipGetLastError();
+}
+
 hipError_t launch_finalize(const DevParams &p, const double *hist, const DevCounters *cnt, double *j, double *sig,
                            hipStream_t s) {
-    const int n = p.n_obs * p.n_e * p.n_t * p.n_runs_eff;
+    const int n = p.n_obs_bins * p.n_e * p.n_t * p.n_runs_eff;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, hist, cnt, j, sig);
     return hipGetLastError();

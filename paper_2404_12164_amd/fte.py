@@ -29,13 +29,14 @@ MAX_RUNS = 64
 SYMBOLS = ["fte_create", "fte_destroy", "fte_last_error", "fte_query_sizes", "fte_bind_buffers", "fte_load_grid",
            "fte_inject", "fte_step_n", "fte_bin_observers", "fte_read_hist", "fte_get_stats", "fte_read_particles",
            "fte_set_launch", "fte_reset", "fte_set_timing", "fte_bin_smoothed", "fte_grad", "fte_read_tangents",
-           "fte_state_size", "fte_save_state", "fte_load_state", "fte_autotune"]
+           "fte_state_size", "fte_save_state", "fte_load_state", "fte_autotune", "fte_bin_steady"]
 TANGENT_COLS = 11         # d(x, y, z, mu, lnp)/d lambda_ref, the same for kperp_ratio, d ln w / d gamma_inj
 
 
 class fte_observer(C.Structure):
     _fields_ = [("r", C.c_double), ("theta", C.c_double), ("phi", C.c_double),
-                ("dr", C.c_double), ("dtheta", C.c_double), ("dphi", C.c_double)]
+                ("dr", C.c_double), ("dtheta", C.c_double), ("dphi", C.c_double),
+                ("n_phi", C.c_int), ("omega", C.c_double)]
 
 
 class fte_run(C.Structure):
@@ -68,7 +69,8 @@ class fte_injection(C.Structure):
     _fields_ = [("r", C.c_double), ("th_lo", C.c_double), ("th_hi", C.c_double), ("ph_lo", C.c_double),
                 ("ph_hi", C.c_double), ("e_lo", C.c_double), ("e_hi", C.c_double), ("gamma_inj", C.c_double),
                 ("w0", C.c_double), ("r_weight", C.c_int), ("r_ref", C.c_double), ("pid0", C.c_uint64),
-                ("n_total", C.c_uint64), ("k0", C.c_uint32), ("n_inj_steps", C.c_uint32), ("run", C.c_int)]
+                ("n_total", C.c_uint64), ("k0", C.c_uint32), ("n_inj_steps", C.c_uint32), ("run", C.c_int),
+                ("region", C.c_int), ("r_hi", C.c_double), ("divv_max", C.c_double), ("max_tries", C.c_uint32)]
 
 
 class fte_sizes(C.Structure):
@@ -125,6 +127,7 @@ def lib():
         L.fte_save_state.argtypes = [vp, vp, u64, vp]
         L.fte_load_state.argtypes = [vp, vp, u64, vp]
         L.fte_autotune.argtypes = [vp, u32, C.POINTER(C.c_int), vp]
+        L.fte_bin_steady.argtypes = [vp, dp, dp, vp]
         for name in SYMBOLS:
             if name not in ("fte_destroy", "fte_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -166,7 +169,8 @@ def make_params(p: dict) -> fte_params:
     obs = p.get("observers", [])
     o.n_obs = len(obs)
     for i, ob in enumerate(obs):
-        o.obs[i] = fte_observer(*[float(v) for v in ob])
+        o.obs[i] = fte_observer(*[float(v) for v in ob[:6]], int(ob[6]) if len(ob) > 6 else 1,
+                                float(ob[7]) if len(ob) > 7 else 0.0)
     o.e_min = p.get("e_min", 1.0)
     o.dlne = p.get("dlne", 1.0)
     o.n_e = int(p.get("n_e", 1))
@@ -225,6 +229,10 @@ def make_injection(inj: dict) -> fte_injection:
     o.k0 = int(inj.get("k0", 0))
     o.n_inj_steps = int(inj.get("n_inj_steps", 0))
     o.run = int(inj.get("run", 0))
+    o.region = int(inj.get("region", 0))
+    o.r_hi = inj.get("r_hi", inj["r"])
+    o.divv_max = inj.get("divv_max", 0.0)
+    o.max_tries = int(inj.get("max_tries", 4096))
     return o
 
 
@@ -286,6 +294,21 @@ def fte_bin_observers(ctx, shape, reset: bool, stream: int):
     _check(ctx, lib().fte_bin_observers(ctx, j.ctypes.data_as(dp), s.ctypes.data_as(dp), int(bool(reset)),
                                         C.c_void_p(stream)))
     return j[:n].reshape(shape), s[:n].reshape(shape)
+
+
+def fte_bin_steady(ctx, shape, stream: int):
+    n = int(np.prod(shape))
+    j = np.zeros(max(n, 1))
+    s = np.zeros(max(n, 1))
+    dp = C.POINTER(C.c_double)
+    _check(ctx, lib().fte_bin_steady(ctx, j.ctypes.data_as(dp), s.ctypes.data_as(dp), C.c_void_p(stream)))
+    return j[:n].reshape(shape), s[:n].reshape(shape)
+
+
+def obs_bins(params: dict) -> int:
+    """Observer bins: each observer (r, theta, phi, dr, dtheta, dphi[, n_phi[,
+    omega]]) covers n_phi longitude bins."""
+    return sum(int(ob[6]) if len(ob) > 6 and int(ob[6]) > 1 else 1 for ob in params.get("observers", []))
 
 
 def fte_read_hist(ctx, n: int, stream: int, n_runs: int = 0):
@@ -413,7 +436,7 @@ class Simulation:
         self.ctx = fte_create(params)
         fte_bind_buffers(self.ctx, grid, n_max, self.bufs)
         self.n_runs = len(params.get("runs") or [])
-        self.n_bins = (len(params.get("observers", [])), int(params.get("n_e", 1)), int(params.get("n_t", 1)))
+        self.n_bins = (obs_bins(params), int(params.get("n_e", 1)), int(params.get("n_t", 1)))
         if self.n_runs:
             self.n_bins = (self.n_runs,) + self.n_bins
 
@@ -453,6 +476,12 @@ class Simulation:
 
     def bin_observers(self, reset=False):
         return fte_bin_observers(self.ctx, self.n_bins, reset, self.stream)
+
+    def bin_steady(self):
+        """Time-integrated intensities [observer bin][E] (per run for an
+        ensemble): the steady state of a Green's-function run."""
+        shp = self.n_bins[:-1]
+        return fte_bin_steady(self.ctx, shp, self.stream)
 
     def read_hist(self):
         n = int(np.prod(self.n_bins)) * int(self.params.get("n_batch", 32))

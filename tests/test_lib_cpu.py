@@ -34,10 +34,10 @@ def test_exports_every_declared_symbol(F):
 def test_struct_sizes_match_header_layout(F):
     import ctypes as C
     # the binding's structures are laid out like the C ones (natural alignment)
-    assert C.sizeof(F.fte_observer) == 48
+    assert C.sizeof(F.fte_observer) == 64
     assert C.sizeof(F.fte_sizes) == 48
     assert C.sizeof(F.fte_buffers) == 64
-    assert C.sizeof(F.fte_injection) == 8 * 9 + 8 + 8 + 8 + 8 + 4 + 4 + 8
+    assert C.sizeof(F.fte_injection) == 8 * 9 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 8
     assert C.sizeof(F.fte_run) == 24
 
 
