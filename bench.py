@@ -279,6 +279,55 @@ def ensemble_leg(F, W, args):
     return out
 
 
+def paper_leg(F, W, args, levels=(1, 2, 3)):
+    """The paper's own experiment (section 2.3) on the synthetic CIR in its
+    corotating frame: a Green's-function run of 10^6 protons of 1 MeV injected
+    where div V < 0, weight r^-2, for 36,000 steps of 10 s, at 1, 2 and 3 AMR
+    levels; steady-state longitude profiles at 1.8 au, their peak per energy
+    channel (the intensity-energy curves of the paper's AMR comparison) and the
+    step throughput."""
+    import torch
+    dev = torch.device("cuda:0")
+    out = {"workload": "paper_cir", "levels": {}}
+    for nl in levels:
+        c = W.paper_cir(n_levels=nl, precision=args.precision)
+        g = c["grid"]
+        raw = W.make_raw(g, c["wind"], xp=torch, device=dev)
+        sim = F.Simulation(c["params"], g, c["n_particles"])
+        sim.load_grid(raw)
+        del raw
+        sim.set_launch(args.block, args.spl, args.compact, args.sort)
+        sim.inject(c["injection"], c["n_particles"], 0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        left = c["n_steps"]
+        while left > 0:
+            k = min(3600, left)
+            sim.step(k)
+            left -= k
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        st = sim.stats()
+        J, sig = sim.bin_steady()
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        J = J.reshape(len(c["ring_radii_au"]), -1, c["params"]["n_e"])
+        e_lo = c["params"]["e_min"] * np.exp(np.arange(c["params"]["n_e"]) * c["params"]["dlne"]) / (1e3 * W.KEV)
+        out["levels"][nl] = dict(leaves=int(len(g["leaves"])), particle_steps=int(st.particle_steps),
+                                 value=st.particle_steps / (ms / 1e3), ms=round(ms, 1),
+                                 peak_1p8au=[float("%.4g" % v) for v in J[-1].max(axis=0)])
+    out["channel_lower_edges_MeV"] = [float("%.4g" % v) for v in e_lo]
+    hi = [k for k in range(len(e_lo)) if e_lo[k] >= 1.99][:3]     # the channels from 2 MeV up
+    base = out["levels"][levels[0]]["peak_1p8au"]
+    out["gain_channels_MeV"] = [float("%.4g" % e_lo[k]) for k in hi]
+    out["high_channel_gain_vs_level1"] = {nl: [round(out["levels"][nl]["peak_1p8au"][k] / base[k], 2) if base[k] else None
+                                                for k in hi] for nl in levels}
+    return out
+
+
 def cpu_baseline(cfg, raw_gpu, n_pids, n_steps, n_threads):
     """The FP64 oracle on the first n_pids particles over the first n_steps
     steps, with the snapshots those steps touch copied to the host."""
@@ -317,6 +366,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble workload")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper's CIR experiment at 1-3 AMR levels")
     ap.add_argument("--cpu-pids", type=int, default=4000)
     ap.add_argument("--cpu-steps", type=int, default=2800)
     ap.add_argument("--calib-copy", action="store_true", help="also run a 2 GiB device copy (counter calibration)")
@@ -408,6 +458,10 @@ def main():
     if not args.no_ensemble:
         log("batched ensemble: 64 runs as one population vs one context at a time")
         extra["ensemble"] = ensemble_leg(F, W, args)
+
+    if not args.no_paper:
+        log("the paper's CIR experiment: region injection, Green's function, 1-3 AMR levels")
+        extra["paper"] = paper_leg(F, W, args)
 
     cpu = None
     if not args.no_cpu:

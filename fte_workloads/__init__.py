@@ -209,6 +209,17 @@ def cir_wind(r, th, ph, t, Vs=330e3, Vf=650e3, omega=OMEGA_CIR, U=500e3, r_B=0.1
     return xp.stack([V, z, z, Br, z, Bph], -1)
 
 
+def cir_wind_corotating(r, th, ph, t, omega=OMEGA_CIR, **kw):
+    """The CIR pattern of cir_wind frozen at t = 0 and seen in the frame
+    corotating with it: the same radial speed and field, plus the frame's
+    flow V_phi = -omega r sin(theta), which makes V parallel to B (no
+    electric field in this frame), so the background is steady there."""
+    xp = _xp(r)
+    f = cir_wind(r, th, ph, 0.0 * t, omega=omega, **kw)
+    vph = -omega * r * xp.sin(th)
+    return xp.stack([f[..., 0], f[..., 1], vph, f[..., 3], f[..., 4], f[..., 5]], -1)
+
+
 def affine_fields(r_or_xi, th, ph, t, coef):
     """A field affine in (xi, theta, phi, t) for each of the six components;
     coef is [6][5] = constant, d/dxi, d/dtheta, d/dphi, d/dt."""
@@ -364,6 +375,34 @@ def cir_ensemble(n_runs=64, precision="mixed", seed=0, n_snap=57, particle_range
         pid += n
     return dict(name="cir_ensemble", grid=g, wind=cir_wind, wind_kw={}, params=params, injections=injections,
                 n_particles=int(npart.sum()), n_steps=int(nstep.max()), runs=runs)
+
+
+def paper_cir(n_levels=2, n_particles=1_000_000, n_steps=36000, precision="mixed"):
+    """The paper's own experiment (section 2.3) on the synthetic CIR: the
+    pattern in its corotating frame (one steady snapshot) on a stretched grid
+    r_i = 0.1 * 1.01^i au to 2.06 au with n_levels AMR levels on the band the
+    region criterion (Eq. 7) selects; 1 MeV protons injected at t = 0
+    (a Green's-function run) uniformly where div V < 0 within 0.12-2 au and
+    colatitude 90 +- 2 deg, weight r^-2 (Eq. 6); Eq. 5 scattering
+    (eps = 0.048) with lambda = 0.3 au at 1 MeV scaling as p^(1/3),
+    lambda_perp = 3e-4 au; absorbing at 0.1 and 2 au; longitude rings of 2
+    deg bins at 0.5, 1.0, 1.5 and 1.8 au in the equator, 12 log energy bins
+    0.25-16 MeV; the steady state is the time integral (fte_bin_steady)."""
+    g = cir_grid(n_levels=n_levels, n_snap=1, n_r=304)
+    E1 = 1e3 * KEV
+    eps1 = E1 / (M_P * C_LIGHT ** 2)
+    p1 = math.sqrt(eps1 * (eps1 + 2.0))
+    rings = [(rr * AU, 90 * DEG, 1 * DEG, 0.05 * AU, 4 * DEG, 2 * DEG, 180, 0.0) for rr in (0.5, 1.0, 1.5, 1.8)]
+    params = dict(mass=M_P, dmm_model="eq5", dmm_norm=0, lambda_ref=0.3 * AU, p_ref=p1, alpha=1.0 / 3.0,
+                  q=5.0 / 3.0, eps=0.048, mu_floor=1e-4, kperp_ratio=0.0, lambda_perp=3e-4 * AU, dt=10.0,
+                  t0=0.0, r_in=0.1 * AU, r_out=2.0 * AU, check_bounds=1, run_id=0, seed=0, observers=rings,
+                  t_ref=0.0, dT=n_steps * 10.0 + 10.0, n_t=1, n_batch=16, precision=precision,
+                  **_bins(250.0, 16000.0, 12))
+    inj = dict(r=0.12 * AU, r_hi=2.0 * AU, th_lo=88 * DEG, th_hi=92 * DEG, ph_lo=0.0, ph_hi=2 * math.pi,
+               e_lo=E1, e_hi=E1, gamma_inj=1.0, w0=1.0, r_weight=1, r_ref=AU, pid0=0, n_total=n_particles,
+               k0=0, n_inj_steps=0, region=1, divv_max=0.0, max_tries=65536)
+    return dict(name="paper_cir", grid=g, wind=cir_wind_corotating, wind_kw={}, params=params, injection=inj,
+                n_particles=n_particles, n_steps=n_steps, ring_radii_au=[0.5, 1.0, 1.5, 1.8])
 
 
 def particle_spec_like(inj, **over):

@@ -110,3 +110,38 @@ def test_rings_and_steady_state_match_oracle(F, torch_cuda, orc):
     Jo, So = orc.finalize_steady(p, sums, w)
     assert Jg.shape == (55, 8)
     assert np.allclose(Jg, Jo, rtol=1e-12, atol=0) and np.allclose(Sg, So, rtol=1e-10, atol=1e-300)
+
+
+def test_paper_workload_small_matches_oracle(F, torch_cuda, orc):
+    """The paper's experiment end to end at reduced size (2 AMR levels, the
+    corotating CIR with its frame flow, Eq. 5 with lambda ~ p^(1/3),
+    lambda_perp, region injection, rings, steady state): FP64 trajectories
+    and sums as the oracle's."""
+    c = W.paper_cir(n_levels=2, n_particles=600, n_steps=1500, precision="fp64")
+    g, p, inj = c["grid"], c["params"], c["injection"]
+    raw = W.make_raw(g, c["wind"])
+    sim = F.Simulation(p, g, 600)
+    sim.load_grid(raw)
+    sim.set_launch(256, 50, 150, 2)
+    sim.inject(inj, 600, 0)
+    sim.step(1500)
+    got = sim.particles()
+    sums, w = sim.read_hist()
+    Jg, _ = sim.bin_steady()
+    sim.close()
+    G = orc.Grid(g, raw)
+    ref = orc.inject(p, inj, 600, 0, grid=G)
+    h = np.zeros(orc.hist_size(p))
+    orc.run(p, G, ref, 0, 1500, h)
+    rp = {int(k): i for i, k in enumerate(ref.pid)}
+    idx = np.array([rp[int(k)] for k in got["pid"]])
+    assert np.array_equal(got["status"], ref.status[idx])
+    live = got["status"] == 0
+    assert live.sum() > 300
+    dx = np.abs(got["x"][live] - ref.x[idx][live]).max()
+    assert dx <= 1e-10 * AU, dx
+    assert (h > 0).sum() > 30
+    sc = np.abs(h).max()
+    assert np.all(np.abs(sums - h) <= 1e-9 * np.maximum(np.abs(h), 1e-6 * sc))
+    Jo, _ = orc.finalize_steady(p, sums, w)
+    assert np.allclose(Jg, Jo, rtol=1e-12, atol=0)
