@@ -177,6 +177,9 @@ typedef struct {
                              that level); list order defines leaf ids             */
     int n_snap;           /* snapshots; 1 = steady                                */
     double t_s0, dt_s;    /* snapshot k is at t_s0 + k dt_s                       */
+    int n_slots;          /* snapshot records held on the device: 0 (or >= n_snap)
+                             all of them (fte_load_grid); 2 .. n_snap-1 a ring
+                             that fte_load_snapshot fills as the run advances  */
 } fte_grid_desc;
 
 /* Particle source for fte_inject (the synthetic workloads' injection; with
@@ -284,6 +287,22 @@ fte_status fte_bind_buffers(fte_ctx *ctx, const fte_grid_desc *g, uint64_t n_max
  * vb_sph is only read during the call.  Synchronises `stream`.  Returns
  * FTE_EINVAL if the data hold non-finite values or |B| = 0. */
 fte_status fte_load_grid(fte_ctx *ctx, const double *vb_sph, void *stream);
+
+/* Snapshot streaming (section 2.4 notes that reading whole data sets is the
+ * bottleneck; the lock-step clock needs two snapshots at a time): with
+ * n_slots < n_snap the grid buffer holds n_slots snapshots, snapshot k in
+ * slot k mod n_slots, and this call derives snapshot k into its slot (the
+ * first call also uploads the index and clears counters and sums, like
+ * fte_load_grid).  raw[0..4] are DEVICE arrays [n_leaves][cells][6] (layout
+ * of fte_load_grid) of snapshots k-2 .. k+2; the time derivative reads k-1
+ * and k+1 (k, k+1, k+2 at k = 0 and k-2, k-1, k at the last snapshot; the
+ * other one of two), the rest may be NULL.  fte_step_n returns FTE_ERANGE
+ * while a snapshot its steps interpolate from is not resident, and a region
+ * injection needs the snapshots nearest its first steps.  Loading a slot
+ * replaces the snapshot it held; on the stream the steps run on, that is
+ * ordered after them.  Records are bit-identical to those of fte_load_grid.
+ * Synchronises. */
+fte_status fte_load_snapshot(fte_ctx *ctx, int k, const double *const raw[5], void *stream);
 
 /* Append n particles with pids first_pid .. first_pid+n-1 drawn from `inj`
  * (see fte_injection).  Requires a loaded grid.  FTE_ENOMEM if the state

@@ -21,7 +21,8 @@ struct fte_ctx {
     fte_params p{};
     std::vector<fte_run> runs;     // copy of the ensemble table
     DevParams dp{};
-    bool bound = false, loaded = false;
+    bool bound = false, loaded = false, index_ready = false;
+    std::vector<int> slot_snap;    // snapshot resident in each record slot (-1: none)
     fte_grid_desc g{};
     std::vector<int32_t> leaves, base, child, info;
     DevGrid dg{};
@@ -180,6 +181,8 @@ std::string build_index(const fte_grid_desc *g, std::vector<int32_t> &base, std:
     if (!(g->th_lo >= 0.0) || !(g->th_lo + g->n1[1] * g->dth <= kPi + 1e-12)) return "colatitude range outside [0, pi]";
     if (g->phi_periodic && fabs(g->n1[2] * g->dph - 2 * kPi) > 1e-9) return "periodic phi must span 2 pi";
     if (g->n_snap < 1) return "n_snap must be >= 1";
+    if (g->n_slots < 0 || g->n_slots == 1 || (g->n_slots > 0 && g->n_slots < g->n_snap && g->n_snap < 3))
+        return "n_slots must be 0, >= 2, and streaming needs n_snap >= 3";
     if (g->n_snap >= 2 && !finite_pos(g->dt_s)) return "dt_s must be > 0";
     if (g->n_leaves < 1 || !g->leaves) return "no leaves";
     const int nb1[3] = {g->n1[0] / g->bx[0], g->n1[1] / g->bx[1], g->n1[2] / g->bx[2]};
@@ -254,6 +257,8 @@ std::string build_index(const fte_grid_desc *g, std::vector<int32_t> &base, std:
 
 size_t rec_elem(const fte_params *p) { return p->precision == FTE_FP64 ? 8 : 4; }
 
+int slots_of(const fte_grid_desc *g) { return (g->n_slots <= 0 || g->n_slots >= g->n_snap) ? g->n_snap : g->n_slots; }
+
 struct Layout {
     size_t grid, index, state, hist, work, tangent;
     size_t off_child, off_info;
@@ -268,7 +273,7 @@ Layout layout(const fte_params *p, const fte_grid_desc *g, uint64_t n_max, size_
     Layout L{};
     L.pcells = (g->bx[0] + 2) * (g->bx[1] + 2) * (g->bx[2] + 2);
     L.rs = needs_kperp(p) ? kRSKperp : kRSPlain;
-    L.grid = (size_t)g->n_snap * g->n_leaves * L.pcells * L.rs * rec_elem(p);
+    L.grid = (size_t)slots_of(g) * g->n_leaves * L.pcells * L.rs * rec_elem(p);
     L.off_child = align256(n_base * 4);
     L.off_info = L.off_child + align256(std::max<size_t>(n_child, 8) * 4);
     L.index = L.off_info + align256((size_t)g->n_leaves * 16);
@@ -555,6 +560,7 @@ fte_status fte_bind_buffers(fte_ctx *c, const fte_grid_desc *g, uint64_t n_max, 
     d.n_levels = g->n_levels;
     d.n_leaves = g->n_leaves;
     d.n_snap = g->n_snap;
+    d.n_slots = slots_of(g);
     d.n_base = (int)c->base.size();
     d.n_child = (int)c->child.size();
     d.pcells = L.pcells;
@@ -568,6 +574,8 @@ fte_status fte_bind_buffers(fte_ctx *c, const fte_grid_desc *g, uint64_t n_max, 
     d.nf = L.rs == kRSKperp ? kNF : 10;
     c->bound = true;
     c->loaded = false;
+    c->index_ready = false;
+    c->slot_snap.assign(d.n_slots, -1);
     c->global_step = 0;
     c->n_upper = 0;
     c->injected_since = 0;
@@ -577,11 +585,8 @@ fte_status fte_bind_buffers(fte_ctx *c, const fte_grid_desc *g, uint64_t n_max, 
     return FTE_OK;
 }
 
-fte_status fte_load_grid(fte_ctx *c, const double *vb, void *stream) {
-    if (!c) return FTE_EINVAL;
-    if (!c->bound) return fail(c, FTE_ESTATE, "bind buffers before loading the grid");
-    if (!vb) return fail(c, FTE_EINVAL, "wind data is NULL");
-    hipStream_t s = (hipStream_t)stream;
+// Index upload, counters and sums cleared, ensemble table: the start of a run.
+static fte_status setup_grid(fte_ctx *c, hipStream_t s) {
     const DevGrid &d = c->dg;
     char *ix = (char *)c->b.index;
     HIPCHK(c, hipMemcpyAsync(ix, c->base.data(), c->base.size() * 4, hipMemcpyHostToDevice, s));
@@ -601,17 +606,7 @@ fte_status fte_load_grid(fte_ctx *c, const double *vb, void *stream) {
             dr[r].pad = 0;
         }
         HIPCHK(c, hipMemcpyAsync((void *)c->dp.runs, dr.data(), dr.size() * sizeof(DevRun), hipMemcpyHostToDevice, s));
-        HIPCHK(c, hipStreamSynchronize(s));
     }
-    HIPCHK(c, launch_check_raw(d, vb, c->cnt, s));
-    const int fp32 = c->p.precision == FTE_MIXED;
-    for (int k = 0; k < d.n_snap; ++k) {
-        HIPCHK(c, launch_raw_ghost(d, vb, k, c->cart, c->cnt, s));
-        HIPCHK(c, launch_derive(d, vb, k, c->cart, c->b.grid, fp32, s));
-        HIPCHK(c, launch_record_ghost(d, k, c->b.grid, fp32, c->cnt, s));
-    }
-    unsigned int flags = 0;
-    HIPCHK(c, hipMemcpyAsync(&flags, &c->cnt->flags, sizeof(flags), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     c->cur = 0;
     c->n_upper = 0;
@@ -619,18 +614,118 @@ fte_status fte_load_grid(fte_ctx *c, const double *vb, void *stream) {
     c->pending = false;
     c->global_step = 0;
     c->since_compact = 0;
-    if (flags & kFlagBadInput) {
+    for (auto &v : c->slot_snap) v = -1;
+    c->index_ready = true;
+    return FTE_OK;
+}
+
+// Ghost fill, derived fields and record ghost fill of snapshot w.k into its slot.
+static fte_status derive_snapshot(fte_ctx *c, const RawWin &w, hipStream_t s) {
+    const DevGrid &d = c->dg;
+    const int fp32 = c->p.precision == FTE_MIXED;
+    HIPCHK(c, launch_raw_ghost(d, w, c->cart, c->cnt, s));
+    HIPCHK(c, launch_derive(d, w, c->cart, c->b.grid, fp32, s));
+    HIPCHK(c, launch_record_ghost(d, w.k % d.n_slots, c->b.grid, fp32, c->cnt, s));
+    return FTE_OK;
+}
+
+// Device flags raised while checking or deriving input; clears them.
+static fte_status input_flags(fte_ctx *c, hipStream_t s) {
+    unsigned int flags = 0;
+    HIPCHK(c, hipMemcpyAsync(&flags, &c->cnt->flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (flags & (kFlagBadInput | kFlagAmrDepth)) {
+        HIPCHK(c, launch_zero_counters(c->cnt, s));
+        HIPCHK(c, hipStreamSynchronize(s));
         c->loaded = false;
-        return fail(c, FTE_EINVAL, "wind data hold non-finite values or |B| = 0");
-    }
-    if (flags & kFlagAmrDepth) {
-        c->loaded = false;
+        c->index_ready = false;
+        if (flags & kFlagBadInput) return fail(c, FTE_EINVAL, "wind data hold non-finite values or |B| = 0");
         return fail(c, FTE_EINVAL, "block-boundary rule needed more than one coarser level");
     }
-    HIPCHK(c, launch_zero_counters(c->cnt, s));
-    HIPCHK(c, hipStreamSynchronize(s));
+    return FTE_OK;
+}
+
+// Snapshots the window needs for the time derivative of snapshot k.
+static bool window_needs(int ns, int k, int j) {
+    if (j == k) return true;
+    if (ns == 2) return true;
+    if (ns < 2) return false;
+    if (k == 0) return j == 1 || j == 2;
+    if (k == ns - 1) return j == ns - 2 || j == ns - 3;
+    return j == k - 1 || j == k + 1;
+}
+
+fte_status fte_load_grid(fte_ctx *c, const double *vb, void *stream) {
+    if (!c) return FTE_EINVAL;
+    if (!c->bound) return fail(c, FTE_ESTATE, "bind buffers before loading the grid");
+    if (!vb) return fail(c, FTE_EINVAL, "wind data is NULL");
+    const DevGrid &d = c->dg;
+    if (d.n_slots < d.n_snap) return fail(c, FTE_ESTATE, "a streaming grid is loaded with fte_load_snapshot");
+    hipStream_t s = (hipStream_t)stream;
+    fte_status r = setup_grid(c, s);
+    if (r != FTE_OK) return r;
+    HIPCHK(c, launch_check_raw(d, vb, (size_t)d.n_snap, c->cnt, s));
+    const size_t per = (size_t)d.n_leaves * d.cells * 6;
+    for (int k = 0; k < d.n_snap; ++k) {
+        RawWin w{};
+        w.k = k;
+        for (int i = 0; i < 5; ++i) {
+            const int j = k - 2 + i;
+            w.s[i] = (j >= 0 && j < d.n_snap) ? vb + (size_t)j * per : nullptr;
+        }
+        r = derive_snapshot(c, w, s);
+        if (r != FTE_OK) return r;
+        c->slot_snap[k] = k;
+    }
+    r = input_flags(c, s);
+    if (r != FTE_OK) return r;
     c->loaded = true;
     return FTE_OK;
+}
+
+fte_status fte_load_snapshot(fte_ctx *c, int k, const double *const raw[5], void *stream) {
+    if (!c) return FTE_EINVAL;
+    if (!c->bound) return fail(c, FTE_ESTATE, "bind buffers before loading snapshots");
+    if (!raw) return fail(c, FTE_EINVAL, "raw is NULL");
+    const DevGrid &d = c->dg;
+    if (k < 0 || k >= d.n_snap) return fail(c, FTE_EINVAL, "snapshot index out of range");
+    RawWin w{};
+    w.k = k;
+    for (int i = 0; i < 5; ++i) {
+        const int j = k - 2 + i;
+        const bool need = j >= 0 && j < d.n_snap && window_needs(d.n_snap, k, j);
+        if (need && !raw[i]) return fail(c, FTE_EINVAL, "a snapshot the time derivative needs is NULL");
+        w.s[i] = need ? raw[i] : nullptr;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (!c->index_ready) {
+        fte_status r = setup_grid(c, s);
+        if (r != FTE_OK) return r;
+    }
+    HIPCHK(c, launch_check_raw(d, raw[2], 1, c->cnt, s));
+    fte_status r = derive_snapshot(c, w, s);
+    if (r != FTE_OK) return r;
+    r = input_flags(c, s);
+    if (r != FTE_OK) return r;
+    c->slot_snap[k % d.n_slots] = k;
+    c->loaded = true;
+    return FTE_OK;
+}
+
+// Snapshots the steps n0 .. n0+n-1 interpolate from must be resident.
+static bool steps_resident(const fte_ctx *c, uint64_t n0, uint64_t n) {
+    const DevGrid &d = c->dg;
+    if (d.n_snap < 2) return c->slot_snap[0] == 0;
+    auto ks_of = [&](uint64_t step) {
+        const double t = c->p.t0 + (double)step * c->p.dt;
+        double kf = floor((t - d.t_s0) * d.inv_dt_s);
+        kf = kf < 0.0 ? 0.0 : (kf > (double)(d.n_snap - 2) ? (double)(d.n_snap - 2) : kf);
+        return (int)kf;
+    };
+    const int a = ks_of(n0), b = ks_of(n0 + n - 1);
+    for (int k = a; k <= b + 1; ++k)
+        if (c->slot_snap[k % d.n_slots] != k) return false;
+    return true;
 }
 
 static fte_status refresh_exact(fte_ctx *c, hipStream_t s) {
@@ -680,6 +775,18 @@ fte_status fte_inject(fte_ctx *c, const fte_injection *inj, uint64_t n, uint64_t
     if (inj->region && (!(inj->r_hi >= inj->r) || !isfinite(inj->r_hi) || !isfinite(inj->divv_max) ||
                         inj->max_tries < 1 || !(inj->ph_hi >= inj->ph_lo) || !(inj->th_hi >= inj->th_lo)))
         return fail(c, FTE_EINVAL, "bad injection region");
+    if (inj->region && c->dg.n_slots < c->dg.n_snap) {
+        // the snapshots nearest the first steps of these pids
+        const DevGrid &d = c->dg;
+        const uint64_t k_hi = inj->n_inj_steps > 0 ? (uint64_t)inj->k0 + inj->n_inj_steps : inj->k0;
+        for (uint64_t step : {(uint64_t)inj->k0, k_hi}) {
+            const double t = c->p.t0 + (double)step * c->p.dt;
+            double f = floor((t - d.t_s0) / d.dt_s + 0.5);
+            f = f < 0.0 ? 0.0 : (f > (double)(d.n_snap - 1) ? (double)(d.n_snap - 1) : f);
+            if (c->slot_snap[(int)f % d.n_slots] != (int)f)
+                return fail(c, FTE_ERANGE, "region injection needs a snapshot that is not resident");
+        }
+    }
     if (n == 0) return FTE_OK;
     hipStream_t s = (hipStream_t)stream;
     if (c->n_upper + n > c->n_max) {
@@ -708,6 +815,8 @@ fte_status fte_step_n(fte_ctx *c, uint32_t n_steps, void *stream) {
         if (t_last > t_end * (1 + 1e-15) + 1e-9 || t_first < c->g.t_s0 - 1e-9)
             return fail(c, FTE_ERANGE, "steps leave the snapshot time range");
     }
+    if (!steps_resident(c, c->global_step, n_steps))
+        return fail(c, FTE_ERANGE, "a snapshot these steps interpolate from is not resident");
     hipStream_t s = (hipStream_t)stream;
     uint32_t left = n_steps;
     while (left > 0) {

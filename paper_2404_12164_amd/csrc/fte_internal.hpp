@@ -71,6 +71,7 @@ struct DevGrid {
     int n1[3], bx[3], px[3];     // level-1 cells, block cells, padded block cells
     int nb1[3];                  // level-1 blocks per dimension
     int n_levels, n_leaves, n_snap, n_base, n_child;
+    int n_slots;                 // snapshot record slots held (snapshot k in slot k mod n_slots)
     int pcells;                  // padded cells per block
     int cells;                   // interior cells per block
     const int32_t *base;         // [nb1 product] node codes (>=0 leaf, <0 -(group+1))
@@ -139,12 +140,17 @@ DevTan tangent_view(void *base, uint64_t n_max);
 size_t tangent_bytes(uint64_t n_max);
 
 // Kernel launchers (fte_kernels.hip).
-hipError_t launch_raw_ghost(const DevGrid &g, const double *raw, int snap, double *work_cart, DevCounters *cnt,
-                            hipStream_t s);
-hipError_t launch_derive(const DevGrid &g, const double *raw, int snap, const double *work_cart, void *rec,
-                         int fp32, hipStream_t s);
+// Raw input of snapshot k and its neighbours k-2 .. k+2 (NULL outside the
+// run or where not needed), each a device array [leaf][cell][6] of double.
+struct RawWin {
+    const double *s[5];
+    int k;
+};
+hipError_t launch_raw_ghost(const DevGrid &g, const RawWin &w, double *work_cart, DevCounters *cnt, hipStream_t s);
+hipError_t launch_derive(const DevGrid &g, const RawWin &w, const double *work_cart, void *rec, int fp32,
+                         hipStream_t s);
 hipError_t launch_record_ghost(const DevGrid &g, int snap, void *rec, int fp32, DevCounters *cnt, hipStream_t s);
-hipError_t launch_check_raw(const DevGrid &g, const double *raw, DevCounters *cnt, hipStream_t s);
+hipError_t launch_check_raw(const DevGrid &g, const double *raw, size_t n_snaps, DevCounters *cnt, hipStream_t s);
 hipError_t launch_inject(const DevParams &p, const DevGrid &g, int rec_fp32, const fte_injection &inj, DevState st,
                          DevTan tn, DevCounters *cnt, int slot, uint64_t n, uint64_t first_pid, hipStream_t s);
 hipError_t launch_add_live(DevCounters *cnt, int slot, uint64_t n, hipStream_t s);

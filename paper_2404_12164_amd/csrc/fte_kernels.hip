@@ -20,9 +20,9 @@ namespace fte {
 // ===========================================================================
 // raw input: [snap][leaf][cell][6] double, cell = i + bx (j + by k)
 struct RawSrc {
-    const double *p;
+    const double *p;             // this snapshot: [leaf][cell][6]
     const int32_t *leaf_info;
-    int snap, n_leaves, cells, bx0, bx1, bx2;
+    int n_leaves, cells, bx0, bx1, bx2;
     __device__ void mean_cube(int leaf, const int cm[3], int k, double out[6]) const {
         const int4 li = reinterpret_cast<const int4 *>(leaf_info)[leaf];
         const int l0 = cm[0] - li.y * bx0, l1 = cm[1] - li.z * bx1, l2 = cm[2] - li.w * bx2;
@@ -35,7 +35,7 @@ struct RawSrc {
             for (int c1 = 0; c1 < k; ++c1)
                 for (int c0 = 0; c0 < k; ++c0) {
                     const size_t idx = (l0 + c0) + (size_t)bx0 * ((l1 + c1) + (size_t)bx1 * (l2 + c2));
-                    const double *src = p + (((size_t)snap * n_leaves + leaf) * cells + idx) * 6;
+                    const double *src = p + ((size_t)leaf * cells + idx) * 6;
                     for (int q = 0; q < 6; ++q) out[q] += src[q];
                 }
         const double inv = 1.0 / (double)(k * k * k);
@@ -109,10 +109,12 @@ __global__ void k_check_raw(const double *raw, size_t n_cells, DevCounters *cnt)
     if (bad) atomicOr(&cnt->flags, kFlagBadInput);
 }
 
+__device__ __forceinline__ const double *raw_at(const RawWin &W, int j) { return W.s[j - W.k + 2]; }
+
 // Padded Cartesian (V, b) of one snapshot: interior cells from the input,
 // ghost cells by the block-boundary rule, then rotated with the angles of the
 // (folded) cell centre.
-__global__ void k_raw_ghost(DevGrid G, const double *raw, int snap, double *cart, DevCounters *cnt) {
+__global__ void k_raw_ghost(DevGrid G, RawWin W, double *cart, DevCounters *cnt) {
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= (size_t)G.n_leaves * G.pcells) return;
     const int leaf = (int)(gid / G.pcells), pc = (int)(gid % G.pcells);
@@ -123,10 +125,10 @@ __global__ void k_raw_ghost(DevGrid G, const double *raw, int snap, double *cart
                           loc[2] < G.bx[2];
     if (interior) {
         const size_t idx = loc[0] + (size_t)G.bx[0] * (loc[1] + (size_t)G.bx[1] * loc[2]);
-        const double *src = raw + (((size_t)snap * G.n_leaves + leaf) * G.cells + idx) * 6;
+        const double *src = raw_at(W, W.k) + ((size_t)leaf * G.cells + idx) * 6;
         for (int q = 0; q < 6; ++q) v[q] = src[q];
     } else {
-        RawSrc S{raw, G.leaf_info, snap, G.n_leaves, G.cells, G.bx[0], G.bx[1], G.bx[2]};
+        RawSrc S{raw_at(W, W.k), G.leaf_info, G.n_leaves, G.cells, G.bx[0], G.bx[1], G.bx[2]};
         if (!virtual_value<6>(G, S, L, c, v)) {
             atomicOr(&cnt->flags, kFlagAmrDepth);
             for (int q = 0; q < 6; ++q) v[q] = __builtin_nan("");
@@ -146,9 +148,9 @@ __global__ void k_raw_ghost(DevGrid G, const double *raw, int snap, double *cart
 }
 
 // Cartesian V of an interior cell taken straight from the input of snapshot k.
-__device__ __forceinline__ void cart_v_input(const DevGrid &G, const double *raw, int k, int leaf, size_t idx,
+__device__ __forceinline__ void cart_v_input(const DevGrid &G, const double *snapshot, int leaf, size_t idx,
                                              const double e[3][3], double V[3]) {
-    const double *s = raw + (((size_t)k * G.n_leaves + leaf) * G.cells + idx) * 6;
+    const double *s = snapshot + ((size_t)leaf * G.cells + idx) * 6;
     for (int a = 0; a < 3; ++a) V[a] = s[0] * e[0][a] + s[1] * e[1][a] + s[2] * e[2][a];
 }
 
@@ -157,7 +159,8 @@ __device__ __forceinline__ void cart_v_input(const DevGrid &G, const double *raw
 // uniform (xi, theta, phi) spacing (one-sided at physical edges), chain rule
 // with the analytic Jacobian at the centre, explicit dV/dt across snapshots.
 template <typename R>
-__global__ void k_derive(DevGrid G, const double *raw, int snap, const double *cart, R *rec) {
+__global__ void k_derive(DevGrid G, RawWin W, const double *cart, R *rec) {
+    const int snap = W.k;
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= (size_t)G.n_leaves * G.cells) return;
     const int leaf = (int)(gid / G.cells);
@@ -217,24 +220,24 @@ __global__ void k_derive(DevGrid G, const double *raw, int snap, const double *c
     const int ns = G.n_snap;
     if (ns == 2) {
         double V0[3], V1[3];
-        cart_v_input(G, raw, 0, leaf, idx, e, V0);
-        cart_v_input(G, raw, 1, leaf, idx, e, V1);
+        cart_v_input(G, raw_at(W, 0), leaf, idx, e, V0);
+        cart_v_input(G, raw_at(W, 1), leaf, idx, e, V1);
         for (int a = 0; a < 3; ++a) dVdt[a] = (V1[a] - V0[a]) / G.dt_s;
     } else if (ns >= 3) {
         double Va[3], Vb[3], Vc[3];
         if (snap == 0) {
-            cart_v_input(G, raw, 0, leaf, idx, e, Va);
-            cart_v_input(G, raw, 1, leaf, idx, e, Vb);
-            cart_v_input(G, raw, 2, leaf, idx, e, Vc);
+            cart_v_input(G, raw_at(W, 0), leaf, idx, e, Va);
+            cart_v_input(G, raw_at(W, 1), leaf, idx, e, Vb);
+            cart_v_input(G, raw_at(W, 2), leaf, idx, e, Vc);
             for (int a = 0; a < 3; ++a) dVdt[a] = (-3.0 * Va[a] + 4.0 * Vb[a] - Vc[a]) / (2.0 * G.dt_s);
         } else if (snap == ns - 1) {
-            cart_v_input(G, raw, ns - 1, leaf, idx, e, Va);
-            cart_v_input(G, raw, ns - 2, leaf, idx, e, Vb);
-            cart_v_input(G, raw, ns - 3, leaf, idx, e, Vc);
+            cart_v_input(G, raw_at(W, ns - 1), leaf, idx, e, Va);
+            cart_v_input(G, raw_at(W, ns - 2), leaf, idx, e, Vb);
+            cart_v_input(G, raw_at(W, ns - 3), leaf, idx, e, Vc);
             for (int a = 0; a < 3; ++a) dVdt[a] = (3.0 * Va[a] - 4.0 * Vb[a] + Vc[a]) / (2.0 * G.dt_s);
         } else {
-            cart_v_input(G, raw, snap + 1, leaf, idx, e, Vb);
-            cart_v_input(G, raw, snap - 1, leaf, idx, e, Vc);
+            cart_v_input(G, raw_at(W, snap + 1), leaf, idx, e, Vb);
+            cart_v_input(G, raw_at(W, snap - 1), leaf, idx, e, Vc);
             for (int a = 0; a < 3; ++a) dVdt[a] = (Vb[a] - Vc[a]) / (2.0 * G.dt_s);
         }
     }
@@ -243,9 +246,9 @@ __global__ void k_derive(DevGrid G, const double *raw, int snap, const double *c
     double curv[3];
     for (int a = 0; a < 3; ++a) curv[a] = Gb[a][0] * b[0] + Gb[a][1] * b[1] + Gb[a][2] * b[2];
 
-    const double *s = raw + (((size_t)snap * G.n_leaves + leaf) * G.cells + idx) * 6;
+    const double *s = raw_at(W, snap) + ((size_t)leaf * G.cells + idx) * 6;
     const double Bn = ::sqrt(s[3] * s[3] + s[4] * s[4] + s[5] * s[5]);
-    R *out = rec + (((size_t)snap * G.n_leaves + leaf) * G.pcells + pc) * G.rs;
+    R *out = rec + (((size_t)(snap % G.n_slots) * G.n_leaves + leaf) * G.pcells + pc) * G.rs;
     out[0] = (R)s[0];
     out[1] = (R)s[1];
     out[2] = (R)s[2];
@@ -263,7 +266,8 @@ __global__ void k_derive(DevGrid G, const double *raw, int snap, const double *c
 
 // Ghost layer of the records by the block-boundary rule.
 template <typename R>
-__global__ void k_record_ghost(DevGrid G, int snap, R *rec, DevCounters *cnt) {
+__global__ void k_record_ghost(DevGrid G, int slot, R *rec, DevCounters *cnt) {
+    const int snap = slot;    // records are addressed by slot
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= (size_t)G.n_leaves * G.pcells) return;
     const int leaf = (int)(gid / G.pcells), pc = (int)(gid % G.pcells);
@@ -285,28 +289,26 @@ __global__ void k_record_ghost(DevGrid G, int snap, R *rec, DevCounters *cnt) {
 
 static inline unsigned blocks_for(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
-hipError_t launch_check_raw(const DevGrid &g, const double *raw, DevCounters *cnt, hipStream_t s) {
-    const size_t n = (size_t)g.n_snap * g.n_leaves * g.cells;
+hipError_t launch_check_raw(const DevGrid &g, const double *raw, size_t n_snaps, DevCounters *cnt, hipStream_t s) {
+    const size_t n = n_snaps * g.n_leaves * g.cells;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_check_raw, dim3(blocks_for(n, 256)), dim3(256), 0, s, raw, n, cnt);
     return hipGetLastError();
 }
 
-hipError_t launch_raw_ghost(const DevGrid &g, const double *raw, int snap, double *work_cart, DevCounters *cnt,
-                            hipStream_t s) {
+hipError_t launch_raw_ghost(const DevGrid &g, const RawWin &w, double *work_cart, DevCounters *cnt, hipStream_t s) {
     const size_t n = (size_t)g.n_leaves * g.pcells;
-    hipLaunchKernelGGL(k_raw_ghost, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, raw, snap, work_cart, cnt);
+    hipLaunchKernelGGL(k_raw_ghost, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, w, work_cart, cnt);
     return hipGetLastError();
 }
 
-hipError_t launch_derive(const DevGrid &g, const double *raw, int snap, const double *work_cart, void *rec, int fp32,
+hipError_t launch_derive(const DevGrid &g, const RawWin &w, const double *work_cart, void *rec, int fp32,
                          hipStream_t s) {
     const size_t n = (size_t)g.n_leaves * g.cells;
     if (fp32)
-        hipLaunchKernelGGL(k_derive<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, raw, snap, work_cart,
-                           (float *)rec);
+        hipLaunchKernelGGL(k_derive<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, w, work_cart, (float *)rec);
     else
-        hipLaunchKernelGGL(k_derive<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, raw, snap, work_cart,
+        hipLaunchKernelGGL(k_derive<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, w, work_cart,
                            (double *)rec);
     return hipGetLastError();
 }
@@ -429,7 +431,7 @@ __device__ bool in_region(const DevGrid &G, int rec_fp32, double x, double y, do
         loc[a] = c - B[a] * G.bx[a];
     }
     const size_t pc = (size_t)(loc[0] + 1) + (size_t)G.px[0] * ((loc[1] + 1) + (size_t)G.px[1] * (loc[2] + 1));
-    const size_t at = (((size_t)k * G.n_leaves + leaf) * G.pcells + pc) * G.rs + 6;
+    const size_t at = (((size_t)(k % G.n_slots) * G.n_leaves + leaf) * G.pcells + pc) * G.rs + 6;
     const double dv = rec_fp32 ? (double)reinterpret_cast<const float *>(G.rec)[at]
                                : reinterpret_cast<const double *>(G.rec)[at];
     return dv < divv_max;
@@ -584,7 +586,7 @@ __device__ __forceinline__ bool gather(const DevGrid &G, const int32_t *ibase, c
     const int nsn = G.n_snap >= 2 ? 2 : 1;
     for (int sn = 0; sn < nsn; ++sn) {
         const R ws = (G.n_snap >= 2) ? (sn == 0 ? (R)1 - alpha : alpha) : (R)1;
-        const R *base = rec + (((size_t)(ks + sn) * G.n_leaves + leaf) * G.pcells + pc) * RS;
+        const R *base = rec + (((size_t)((ks + sn) % G.n_slots) * G.n_leaves + leaf) * G.pcells + pc) * RS;
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             const int e0 = d & 1, e1 = (d >> 1) & 1, e2 = (d >> 2) & 1;
@@ -639,7 +641,7 @@ __device__ __forceinline__ bool gather_d(const DevGrid &G, const int32_t *ibase,
     const int nsn = G.n_snap >= 2 ? 2 : 1;
     for (int sn = 0; sn < nsn; ++sn) {
         const R ws = (G.n_snap >= 2) ? (sn == 0 ? (R)1 - alpha : alpha) : (R)1;
-        const R *base = rec + (((size_t)(ks + sn) * G.n_leaves + leaf) * G.pcells + pc) * RS;
+        const R *base = rec + (((size_t)((ks + sn) % G.n_slots) * G.n_leaves + leaf) * G.pcells + pc) * RS;
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             const int e0 = d & 1, e1 = (d >> 1) & 1, e2 = (d >> 2) & 1;

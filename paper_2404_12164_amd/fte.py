@@ -29,7 +29,8 @@ MAX_RUNS = 64
 SYMBOLS = ["fte_create", "fte_destroy", "fte_last_error", "fte_query_sizes", "fte_bind_buffers", "fte_load_grid",
            "fte_inject", "fte_step_n", "fte_bin_observers", "fte_read_hist", "fte_get_stats", "fte_read_particles",
            "fte_set_launch", "fte_reset", "fte_set_timing", "fte_bin_smoothed", "fte_grad", "fte_read_tangents",
-           "fte_state_size", "fte_save_state", "fte_load_state", "fte_autotune", "fte_bin_steady"]
+           "fte_state_size", "fte_save_state", "fte_load_state", "fte_autotune", "fte_bin_steady",
+           "fte_load_snapshot"]
 TANGENT_COLS = 11         # d(x, y, z, mu, lnp)/d lambda_ref, the same for kperp_ratio, d ln w / d gamma_inj
 
 
@@ -62,7 +63,7 @@ class fte_grid_desc(C.Structure):
                 ("th_lo", C.c_double), ("dth", C.c_double), ("ph_lo", C.c_double), ("dph", C.c_double),
                 ("phi_periodic", C.c_int), ("n1", C.c_int * 3), ("bx", C.c_int * 3), ("n_levels", C.c_int),
                 ("n_leaves", C.c_int), ("leaves", C.POINTER(C.c_int32)), ("n_snap", C.c_int),
-                ("t_s0", C.c_double), ("dt_s", C.c_double)]
+                ("t_s0", C.c_double), ("dt_s", C.c_double), ("n_slots", C.c_int)]
 
 
 class fte_injection(C.Structure):
@@ -128,6 +129,7 @@ def lib():
         L.fte_load_state.argtypes = [vp, vp, u64, vp]
         L.fte_autotune.argtypes = [vp, u32, C.POINTER(C.c_int), vp]
         L.fte_bin_steady.argtypes = [vp, dp, dp, vp]
+        L.fte_load_snapshot.argtypes = [vp, C.c_int, C.POINTER(vp), vp]
         for name in SYMBOLS:
             if name not in ("fte_destroy", "fte_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -210,6 +212,7 @@ def make_grid_desc(g: dict):
     d.n_snap = int(g["n_snap"])
     d.t_s0 = g.get("t_s0", 0.0)
     d.dt_s = g.get("dt_s", 1.0)
+    d.n_slots = int(g.get("n_slots", 0))
     return d, leaves
 
 
@@ -275,6 +278,12 @@ def fte_bind_buffers(ctx, grid: dict, n_max: int, bufs: fte_buffers):
 
 def fte_load_grid(ctx, vb_sph_ptr: int, stream: int):
     _check(ctx, lib().fte_load_grid(ctx, C.c_void_p(vb_sph_ptr), C.c_void_p(stream)))
+
+
+def fte_load_snapshot(ctx, k: int, ptrs, stream: int):
+    """ptrs: five device addresses (0 for none) of snapshots k-2 .. k+2."""
+    arr = (C.c_void_p * 5)(*[C.c_void_p(int(v)) if v else None for v in ptrs])
+    _check(ctx, lib().fte_load_snapshot(ctx, int(k), arr, C.c_void_p(stream)))
 
 
 def fte_inject(ctx, inj: dict, n: int, first_pid: int, stream: int):
@@ -459,6 +468,20 @@ class Simulation:
         fte_load_grid(self.ctx, vb.data_ptr(), self.stream)
         del vb
 
+    def load_snapshot(self, k: int, vb_all):
+        """Derive snapshot k of a streaming grid into its slot from vb_all, a
+        device float64 tensor [n_snap][n_leaves][cells][6] (only snapshots
+        k-2 .. k+2 are read)."""
+        t = self.torch
+        if not (isinstance(vb_all, t.Tensor) and vb_all.is_cuda and vb_all.dtype == t.float64
+                and vb_all.is_contiguous()):
+            raise ValueError("vb_all must be a contiguous float64 CUDA tensor")
+        ns = vb_all.shape[0]
+        step = vb_all[0].numel() * 8
+        base = vb_all.data_ptr()
+        ptrs = [base + j * step if 0 <= j < ns else 0 for j in range(k - 2, k + 3)]
+        fte_load_snapshot(self.ctx, k, ptrs, self.stream)
+
     def set_launch(self, block=256, steps_per_launch=32, compact_every=128, spatial_sort=2):
         fte_set_launch(self.ctx, block, steps_per_launch, compact_every, spatial_sort)
 
@@ -517,7 +540,7 @@ class Simulation:
         return fte_read_particles(self.ctx, self.n_max, self.stream)
 
     def records(self):
-        """Grid records as a tensor view [n_snap][n_leaves][pcells][stride]."""
+        """Grid records as a tensor view [n_snap or slots][n_leaves][pcells][stride]."""
         t = self.torch
         bx = self.grid["bx"]
         pc = (bx[0] + 2) * (bx[1] + 2) * (bx[2] + 2)
@@ -525,7 +548,10 @@ class Simulation:
         dt = t.float64 if pp.precision == FTE_FP64 else t.float32
         rs = RECORD_STRIDE_KPERP if (pp.kperp_ratio > 0 or pp.lambda_perp > 0) else RECORD_STRIDE
         nl = len(self.grid["leaves"])
-        return self.t_grid.view(dt)[: self.grid["n_snap"] * nl * pc * rs].view(self.grid["n_snap"], nl, pc, rs)
+        ns = int(self.grid["n_snap"])
+        slots = int(self.grid.get("n_slots", 0))
+        ns = slots if 0 < slots < ns else ns       # a streaming grid holds its slots
+        return self.t_grid.view(dt)[: ns * nl * pc * rs].view(ns, nl, pc, rs)
 
     def close(self):
         if getattr(self, "ctx", None):

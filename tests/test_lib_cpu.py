@@ -144,3 +144,15 @@ def test_ensemble_sizes_and_rejections(F):
                           cfg["grid"], 100)
     with pytest.raises(F.FteError):        # run ids must fit 16 bits
         F.fte_query_sizes(dict(p, runs=runs, run_id=65535), cfg["grid"], 100)
+
+
+def test_streaming_grid_sizes(F):
+    cfg = W.cir_time_dependent(n_particles=1000, n_snap=12)
+    g = cfg["grid"]
+    full = F.fte_query_sizes(cfg["params"], g, 1000)
+    ring = F.fte_query_sizes(cfg["params"], dict(g, n_slots=3), 1000)
+    assert ring.grid_bytes * 12 == full.grid_bytes * 3          # three snapshot slots
+    assert F.fte_query_sizes(cfg["params"], dict(g, n_slots=40), 1000).grid_bytes == full.grid_bytes
+    for bad in (1, -2):
+        with pytest.raises(F.FteError):
+            F.fte_query_sizes(cfg["params"], dict(g, n_slots=bad), 1000)
