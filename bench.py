@@ -58,7 +58,7 @@ def read_traffic(name, algo_bytes_per_launch):
 class Run:
     """One context on the workload plus its lazy continuous-injection plan."""
 
-    def __init__(self, F, cfg, raw, precision, block, spl, compact, sort=1):
+    def __init__(self, F, cfg, raw, precision, block, spl, compact, sort=1, load=True):
         import torch
         self.torch = torch
         self.cfg = cfg
@@ -69,7 +69,8 @@ class Run:
         self.sim = F.Simulation(self.p, cfg["grid"], self.N)
         torch.cuda.synchronize()
         t = time.time()
-        self.sim.load_grid(raw)
+        if load:
+            self.sim.load_grid(raw)
         self.load_s = time.time() - t
         self.sim.set_launch(block, spl, compact, sort)
         self.sim.set_timing(True)
@@ -328,6 +329,69 @@ def paper_leg(F, W, args, levels=(1, 2, 3)):
     return out
 
 
+def stream_leg(F, W, cfg, raw, args, n_slots=3):
+    """The CIR workload with the grid held as a ring of n_slots snapshots:
+    each snapshot is copied from pinned host memory into a five-snapshot
+    device staging window and derived into its slot just before the clock
+    needs it (on the stepping stream, so transfers are timed), against the
+    fully resident grid's value."""
+    import torch
+    dev = torch.device("cuda:0")
+    g = dict(cfg["grid"], n_slots=n_slots)
+    ns = g["n_snap"]
+    host = torch.empty(raw.shape, dtype=torch.float64, pin_memory=True)
+    host.copy_(raw)
+    per_snap = raw[0].numel()
+    # device staging ring: snapshot j in stage[j % 5]; sliding the window by
+    # one snapshot copies one snapshot from the host
+    stage = torch.empty((5,) + tuple(raw.shape[1:]), dtype=torch.float64, device=dev)
+    staged = [-1] * 5
+    run = Run(F, dict(cfg, grid=g), None, args.precision, args.block, args.spl, args.compact, args.sort,
+              load=False)
+    sim = run.sim
+    p = run.p
+    nxt = [0]
+
+    def load_through(k):
+        while nxt[0] <= min(k, ns - 1):
+            j0 = nxt[0]
+            ptrs = []
+            for j in range(j0 - 2, j0 + 3):
+                if 0 <= j < ns:
+                    if staged[j % 5] != j:
+                        stage[j % 5].copy_(host[j], non_blocking=True)
+                        staged[j % 5] = j
+                    ptrs.append(stage[j % 5].data_ptr())
+                else:
+                    ptrs.append(0)
+            F.fte_load_snapshot(sim.ctx, j0, ptrs, sim.stream)
+            nxt[0] += 1
+
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    steps_per_snap = int(round(g["dt_s"] / p["dt"]))
+    total = cfg["n_steps"]
+    done = 0
+    while done < total:
+        k = done // steps_per_snap
+        load_through(k + 1)
+        m = min((k + 1) * steps_per_snap, total) - done
+        run.chunk(m)
+        done += m
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    st = sim.stats()
+    run.close()
+    del host, stage
+    return dict(slots=n_slots, snapshots=ns, ms=round(ms, 1), particle_steps=int(st.particle_steps),
+                value=st.particle_steps / (ms / 1e3),
+                grid_bytes_ring=int(F.fte_query_sizes(p, g, cfg["n_particles"]).grid_bytes),
+                grid_bytes_full=int(F.fte_query_sizes(p, cfg["grid"], cfg["n_particles"]).grid_bytes),
+                host_to_device_bytes_per_snapshot=per_snap * 8)
+
+
 def cpu_baseline(cfg, raw_gpu, n_pids, n_steps, n_threads):
     """The FP64 oracle on the first n_pids particles over the first n_steps
     steps, with the snapshots those steps touch copied to the host."""
@@ -367,6 +431,7 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble workload")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's CIR experiment at 1-3 AMR levels")
+    ap.add_argument("--no-stream", action="store_true", help="skip the snapshot-streaming run of the CIR workload")
     ap.add_argument("--cpu-pids", type=int, default=4000)
     ap.add_argument("--cpu-steps", type=int, default=2800)
     ap.add_argument("--calib-copy", action="store_true", help="also run a 2 GiB device copy (counter calibration)")
@@ -439,6 +504,11 @@ def main():
                 algo_bytes_per_launch=round(per_launch_bytes))
 
     extra = {}
+    if not args.no_stream:
+        log("CIR workload with a 3-snapshot ring streamed from pinned host memory")
+        extra["stream"] = stream_leg(F, W, cfg, raw, args)
+        extra["stream"]["vs_resident"] = round(extra["stream"]["value"] / value, 3)
+
     if not args.no_fp64 and args.precision == "mixed":
         log("FP64 path on the same workload")
         r64 = Run(F, cfg, raw, "fp64", args.block, args.spl, args.compact, args.sort)
