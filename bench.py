@@ -127,7 +127,8 @@ def gradient_leg(F, W, raw, args):
     of the forward pass with smoothed sums, and of the gradient pass (tangents
     + derivative sums), each over the whole run; then the gradient of two
     losses against central differences (h = 1e-3, common random numbers) of
-    the smoothed forward pass on the GPU."""
+    the smoothed forward pass on the GPU, with hard absorbing spheres and
+    again with absorbing layers in front of them."""
     import torch
     cfg = W.cir_differentiation(precision=args.precision)
     n_steps = cfg["n_steps"]
@@ -136,8 +137,8 @@ def gradient_leg(F, W, raw, args):
     p_smooth = dict(p_grad, grad=0)
     p_plain = {k: v for k, v in p_grad.items() if k not in ("smoothing", "grad")}
 
-    def run(params, inj=None, timed_run=True):
-        c = dict(cfg, params=params, injection=inj or cfg["injection"])
+    def run(params, inj=None, timed_run=True, c0=cfg):
+        c = dict(c0, params=params, injection=inj or c0["injection"])
         r = Run(F, c, raw, args.precision, args.block, args.spl, args.compact, args.sort)
         res = timed(r, 10, chunk) if timed_run else None
         return r, res
@@ -168,30 +169,48 @@ def gradient_leg(F, W, raw, args):
     r.close()
     out["grad_over_forward"] = round(out["gradient_ms"] / out["forward_ms"], 3)
     out["grad_over_smoothed_forward"] = round(out["gradient_ms"] / out["forward_smoothed_ms"], 3)
-    # central differences with common random numbers
-    h = 1e-3
-    fd = []
-    for key in ("lambda_ref", "kperp_ratio", "gamma_inj"):
-        Js = []
-        for sgn in (1, -1):
-            if key == "gamma_inj":
-                base = cfg["injection"]["gamma_inj"]
-                rr, _ = run(p_smooth, inj=dict(cfg["injection"], gamma_inj=base * (1 + sgn * h)), timed_run=False)
-            else:
-                base = p_grad[key]
-                rr, _ = run(dict(p_smooth, **{key: base * (1 + sgn * h)}), timed_run=False)
-            for _ in range(10):
-                rr.chunk(chunk)
-            Js.append(rr.sim.bin_smoothed()[0])
-            rr.close()
-        fd.append((Js[0] - Js[1]) / (2 * h * base))
-    rel = []
-    for w, gd in zip(losses, g_dev):
-        gf = np.array([(f * w).sum() for f in fd])
-        rel.append([float(abs(a - b) / abs(b)) if b != 0 else None for a, b in zip(gd, gf)])
+
+    def fd_rel_err(c0, g_dev):
+        """Central differences with common random numbers of the smoothed
+        forward pass of workload c0; relative deviation of g_dev per loss."""
+        h = 1e-3
+        ps = dict(c0["params"], grad=0)
+        fd = []
+        for key in ("lambda_ref", "kperp_ratio", "gamma_inj"):
+            Js = []
+            for sgn in (1, -1):
+                if key == "gamma_inj":
+                    base = c0["injection"]["gamma_inj"]
+                    rr, _ = run(ps, inj=dict(c0["injection"], gamma_inj=base * (1 + sgn * h)), timed_run=False,
+                                c0=c0)
+                else:
+                    base = ps[key]
+                    rr, _ = run(dict(ps, **{key: base * (1 + sgn * h)}), timed_run=False, c0=c0)
+                for _ in range(10):
+                    rr.chunk(chunk)
+                Js.append(rr.sim.bin_smoothed()[0])
+                rr.close()
+            fd.append((Js[0] - Js[1]) / (2 * h * base))
+        rel = []
+        for w, gd in zip(losses, g_dev):
+            gf = np.array([(f * w).sum() for f in fd])
+            rel.append([float(abs(a - b) / abs(b)) if b != 0 else None for a, b in zip(gd, gf)])
+        return rel
+
     out["grad_sum_J"] = [float(v) for v in g_dev[0]]
-    out["fd_rel_err"] = rel
+    out["fd_rel_err"] = fd_rel_err(cfg, g_dev)
     out["J_nonzero"] = int((J > 0).sum())
+    # absorbing layers: the same workload, the pathwise gradient now smooth
+    # across the boundaries
+    cl = W.cir_differentiation(precision=args.precision, layers=True)
+    r, res = run(cl["params"], c0=cl)
+    Jl, _ = r.sim.bin_smoothed()
+    gl = [r.sim.grad_of(w) for w in losses]
+    r.close()
+    out["layers"] = {"absorb_layer_au": cl["params"]["absorb_layer"] / W.AU,
+                     "absorb_rate": cl["params"]["absorb_rate"], "gradient_ms": round(res["ms"], 2),
+                     "grad_sum_J": [float(v) for v in gl[0]], "fd_rel_err": fd_rel_err(cl, gl),
+                     "J_sum_over_hard": float(Jl.sum() / J.sum())}
     return out
 
 

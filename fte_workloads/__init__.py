@@ -329,18 +329,22 @@ def cir_time_dependent(n_particles=10_000_000, n_steps=16920, precision="mixed",
                 n_particles=n_particles, n_steps=n_steps)
 
 
-def cir_differentiation(n_particles=1_000_000, n_steps=8000, precision="mixed", n_snap=48):
+def cir_differentiation(n_particles=1_000_000, n_steps=8000, precision="mixed", n_snap=48, layers=False):
     """Gradient workload: the CIR wind and grid of cir_time_dependent, 10^6
     protons (5-50 keV, E^-4) injected continuously over 8,000 steps of 10 s,
     Eq. 5 scattering with lambda = 0.2 au, kappa_perp / kappa_par = 0.02, and
     intensities at the three 1-au observers smoothed by Gaussians of 0.05 au,
     0.1 in ln E and 10 min; differentiated with respect to (lambda, kappa
-    ratio, injection index)."""
+    ratio, injection index).  layers: absorbing layers 0.02 au wide inside
+    r_in and r_out at a peak rate of 0.047/s (a 50 keV proton crossing at
+    |mu| = 1 keeps e^-15 of its weight)."""
     cfg = cir_time_dependent(n_particles=n_particles, n_steps=n_steps, precision=precision, n_snap=n_snap)
     params = dict(cfg["params"], dmm_model="eq5", eps=0.048, kperp_ratio=0.02,
                   n_t=int(math.ceil(n_steps * 10.0 / 600.0)),
                   smoothing=dict(sigma_x=0.05 * AU, sigma_lne=0.1, sigma_t=600.0), grad=1)
-    return dict(cfg, name="cir_differentiation", params=params)
+    if layers:
+        params.update(absorb_layer=0.02 * AU, absorb_rate=0.047)
+    return dict(cfg, name="cir_differentiation" + ("_layers" if layers else ""), params=params)
 
 
 def cir_ensemble(n_runs=64, precision="mixed", seed=0, n_snap=57, particle_range=(1e4, 1e6),

@@ -151,6 +151,9 @@ std::string check_params(const fte_params *p) {
         }
     }
     if (!(p->sigma_x >= 0.0) || !isfinite(p->sigma_x)) return "sigma_x must be >= 0";
+    if (!(p->absorb_layer >= 0.0) || !isfinite(p->absorb_layer) || !(p->absorb_rate >= 0.0) ||
+        !isfinite(p->absorb_rate))
+        return "absorb_layer and absorb_rate must be finite and >= 0";
     if (p->grad != 0 && p->grad != 1) return "grad must be 0 or 1";
     if (p->grad && !(p->sigma_x > 0.0)) return "the gradient needs the smoothed intensities (sigma_x > 0)";
     if (p->sigma_x > 0.0) {
@@ -372,6 +375,10 @@ void make_devparams(const fte_params *p, DevParams *d) {
     d->n_runs = p->n_runs;
     d->n_runs_eff = runs_eff(p);
     d->kperp_any = needs_kperp(p) ? 1 : 0;
+    if (p->absorb_layer > 0.0 && p->absorb_rate > 0.0) {
+        d->layer_k0dt = p->absorb_rate * p->dt;
+        d->layer_inv_h = 1.0 / p->absorb_layer;
+    }
     // kernel-smoothed intensities
     if (p->sigma_x > 0.0) {
         d->smooth = 1;
@@ -407,7 +414,7 @@ size_t state_bytes(uint64_t n) {
     return 6 * align256(n * 8) + align256(n * 8) + align256(n * 4) + align256(n * 4) + align256(n * 2);
 }
 
-size_t tangent_bytes(uint64_t n) { return 11 * align256(n * 8); }
+size_t tangent_bytes(uint64_t n) { return kTanCols * align256(n * 8); }
 
 DevTan tangent_view(void *base, uint64_t n) {
     DevTan t{};
@@ -1082,10 +1089,10 @@ fte_status fte_read_tangents(fte_ctx *c, double *tan, uint64_t cap, uint64_t *n_
     if (!tan || n == 0) return FTE_OK;
     const DevTan &t = c->tn[c->cur];
     std::vector<double> col(n);
-    for (int q = 0; q < 11; ++q) {
+    for (int q = 0; q < kTanCols; ++q) {
         HIPCHK(c, hipMemcpyAsync(col.data(), t.col(q), n * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
-        for (size_t i = 0; i < n; ++i) tan[11 * i + q] = col[i];
+        for (size_t i = 0; i < n; ++i) tan[kTanCols * i + q] = col[i];
     }
     return FTE_OK;
 }
@@ -1133,7 +1140,7 @@ uint64_t state_fingerprint(const fte_ctx *c) {
     h = fnv_val(h, p.e_min); h = fnv_val(h, p.dlne); h = fnv_val(h, p.n_e); h = fnv_val(h, p.t_ref);
     h = fnv_val(h, p.dT); h = fnv_val(h, p.n_t); h = fnv_val(h, p.n_batch);
     h = fnv_val(h, p.sigma_x); h = fnv_val(h, p.sigma_lne); h = fnv_val(h, p.sigma_t); h = fnv_val(h, p.grad);
-    h = fnv_val(h, p.n_runs);
+    h = fnv_val(h, p.n_runs); h = fnv_val(h, p.absorb_layer); h = fnv_val(h, p.absorb_rate);
     for (int r = 0; r < p.n_runs; ++r) {
         h = fnv_val(h, c->runs[r].lambda_ref);
         h = fnv_val(h, c->runs[r].kperp_ratio);
@@ -1154,7 +1161,7 @@ int state_columns(const DevState &d, void *col[10], size_t esz[10]) {
 
 uint64_t state_blob_bytes(const fte_ctx *c, uint64_t n) {
     uint64_t b = sizeof(StateHeader) + sizeof(DevCounters) + (c->hist_n + c->sm_n) * 8 + n * (6 * 8 + 8 + 4 + 4 + 2);
-    if (c->p.grad) b += n * (kTanLnw + 1) * 8;
+    if (c->p.grad) b += n * kTanCols * 8;
     return b;
 }
 
@@ -1212,7 +1219,7 @@ fte_status fte_save_state(fte_ctx *c, void *blob, uint64_t bytes, void *stream) 
         o += n * esz[k];
     }
     if (c->p.grad)
-        for (int q = 0; q <= kTanLnw; ++q) {
+        for (int q = 0; q < kTanCols; ++q) {
             if (n) HIPCHK(c, hipMemcpyAsync(o, c->tn[c->cur].col(q), n * 8, hipMemcpyDeviceToHost, s));
             o += n * 8;
         }
@@ -1255,7 +1262,7 @@ fte_status fte_load_state(fte_ctx *c, const void *blob, uint64_t bytes, void *st
         o += n * esz[k];
     }
     if (c->p.grad)
-        for (int q = 0; q <= kTanLnw; ++q) {
+        for (int q = 0; q < kTanCols; ++q) {
             if (n) HIPCHK(c, hipMemcpyAsync(c->tn[0].col(q), o, n * 8, hipMemcpyHostToDevice, s));
             o += n * 8;
         }

@@ -525,8 +525,7 @@ __global__ void k_inject(DevParams P, DevGrid G, int rec_fp32, fte_injection inj
         }
         atomicAdd(&wsum[pid % (uint64_t)P.n_batch], wt);
         if (P.grad) {
-            for (int q = 0; q < kTanLnw; ++q) tn.col(q)[j] = 0.0;
-            tn.col(kTanLnw)[j] = dlnw;
+            for (int q = 0; q < kTanCols; ++q) tn.col(q)[j] = q == kTanLnw ? dlnw : 0.0;
             atomicAdd(&wdg, wt * dlnw);
         }
     }
@@ -720,6 +719,16 @@ __device__ __forceinline__ R dmm_g1(const DevParams &P, R mu) {
     return (q - (R)1) * sgn(mu) * M<R>::pow_(amx, q - (R)2) * om - (R)2 * mu * M<R>::pow_(am, q - (R)1);
 }
 
+// Survival factor exp(x) of one step in an absorbing layer.  Out of line in
+// double: the step kernels reach it rarely, and inlined its temporaries would
+// add to the register peak of every step.
+__device__ __noinline__ double layer_survival_f64(double x) { return ::exp(x); }
+template <typename R>
+__device__ __forceinline__ R layer_survival(double x) {
+    if constexpr (std::is_same<R, float>::value) return M<float>::exp_((float)x);
+    else return layer_survival_f64(x);
+}
+
 // MODE 0: histogram estimator only.  MODE 1: also the kernel-smoothed sums.
 // MODE 2: also the pathwise tangents d(x, mu, ln p)/d(lambda_ref,
 // kperp_ratio), propagated by the derivative of the same Euler-Maruyama map
@@ -771,6 +780,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
         double x = st.x[i], y = st.y[i], z = st.z[i];
         R mu = (R)st.mu[i], lnp = (R)st.lnp[i];
         const double w = st.w[i];
+        // absorbing layers: the survival factor of this launch's steps so far
+        // (the weight is w wf) and the rates (u_in^2, u_out^2) summed over them
+        R wf = (R)1, L_in = (R)0, L_out = (R)0;
+        auto w_now = [&]() -> double { return w * (double)wf; };
         const uint64_t pid = st.pid[i];
         const uint32_t kinj = st.kinj[i];
         int status = FTE_PS_ACTIVE;
@@ -789,7 +802,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
             run_id = rr.run_id;
         }
         // tangents (MODE 2)
-        R TX[ND][3], TM[ND], TL[ND];
+        R TX[ND][3], TM[ND], TL[ND], DW[ND];
         R dlnw = (R)0;
         if constexpr (MODE == 2) {
 #pragma unroll
@@ -799,6 +812,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                 TX[k][2] = (R)tn.col(5 * k + 2)[i];
                 TM[k] = (R)tn.col(5 * k + 3)[i];
                 TL[k] = (R)tn.col(5 * k + 4)[i];
+                DW[k] = (R)tn.col(kTanLnwP + k)[i];
             }
             dlnw = (R)tn.col(kTanLnw)[i];
         }
@@ -1071,6 +1085,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                 status = FTE_PS_OUT_OF_DOMAIN;
                 break;
             }
+            // ---- absorbing layers: survival over this step at the post-step
+            // radius, a factor exp(-k0 dt (u_in^2 + u_out^2)) with u = 1 - d / h
+            // where the distance d to a boundary is below h
+            if (P.layer_k0dt > 0.0) {
+                double u_in = 1.0 - (r - P.r_in) * P.layer_inv_h;
+                double u_out = 1.0 - (P.r_out - r) * P.layer_inv_h;
+                u_in = u_in > 0.0 ? u_in : 0.0;
+                u_out = u_out > 0.0 ? u_out : 0.0;
+                if (u_in > 0.0 || u_out > 0.0) {
+                    L_in += (R)(u_in * u_in);
+                    L_out += (R)(u_out * u_out);
+                    wf *= layer_survival<R>(-P.layer_k0dt * (u_in * u_in + u_out * u_out));
+                    if constexpr (MODE == 2) {
+                        // d ln w = -k0 dt (2 / h)(u_out - u_in) dr, dr = x . dx / r
+                        const double g = -P.layer_k0dt * 2.0 * P.layer_inv_h * (u_out - u_in) / r;
+#pragma unroll
+                        for (int k = 0; k < ND; ++k)
+                            DW[k] += (R)(g * (x * (double)TX[k][0] + y * (double)TX[k][1] + z * (double)TX[k][2]));
+                    }
+                }
+            }
             // ---- kernel-smoothed sums of the post-step state, per global step
             // (the time kernel is applied when they are read out)
             if constexpr (MODE >= 1) {
@@ -1078,7 +1113,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                 if (m >= 0 && m < P.n_win) {
                     const R lnE = M<R>::log_((R)P.mass_c2 * M<R>::div_(Pcur * Pcur, gcur + (R)1));
                     const R iE = M<R>::exp_(-lnE);
-                    const R base_w = (R)w * vcur * dt;
+                    const R base_w = (R)w_now() * vcur * dt;
                     const R dlE = M<R>::div_(gcur + (R)1, gcur);        // d ln E / d ln p
                     const R G2n = M<R>::div_((R)1, gcur * gcur);       // d ln v / d ln p
                     for (int o = 0; o < P.n_obs; ++o) {
@@ -1111,7 +1146,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                             if constexpr (MODE == 2) {
                                 const R fe = (-ue * (R)P.inv_sl2 - (R)1) * dlE;
 #pragma unroll
-                                for (int k = 0; k < ND; ++k) atomicAdd(cell + 1 + k, (double)(c * (gx[k] + fe * TL[k])));
+                                for (int k = 0; k < ND; ++k)
+                                    atomicAdd(cell + 1 + k, (double)(c * (gx[k] + fe * TL[k] + DW[k])));
                                 atomicAdd(cell + 3, (double)(c * dlnw));
                             }
                         }
@@ -1139,7 +1175,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                         const int ie = (int)M<R>::floor_(ue);
                         const int it = (int)::floor(ut);
                         const int ib = (int)(pid % (uint64_t)P.n_batch);
-                        const double add = w * (double)vcur * P.dt;
+                        const double add = w_now() * (double)vcur * P.dt;
                         const int lt = it - LD.it_lo;
                         const size_t rob = (size_t)run_r * P.n_obs_bins + obin;
                         if (lt >= 0 && lt < LD.n_tb) {
@@ -1164,13 +1200,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                 tn.col(5 * k + 2)[i] = (double)TX[k][2];
                 tn.col(5 * k + 3)[i] = (double)TM[k];
                 tn.col(5 * k + 4)[i] = (double)TL[k];
+                tn.col(kTanLnwP + k)[i] = (double)DW[k];
             }
+        }
+        const double w_end = w_now();
+        if (w_end != w) {
+            // the removed weight, split between the layers in proportion to
+            // their accumulated rates
+            st.w[i] = w_end;
+            const double lost = w - w_end, f_in = (double)L_in / ((double)L_in + (double)L_out);
+            if (L_in > (R)0) atomicAdd(&cnt->w_retired[FTE_PS_ABSORBED_IN], lost * f_in);
+            if (L_out > (R)0) atomicAdd(&cnt->w_retired[FTE_PS_ABSORBED_OUT], lost - lost * f_in);
         }
         if (status == FTE_PS_ACTIVE && n_win >= step_end) status = FTE_PS_DONE;
         if (status != FTE_PS_ACTIVE) {
             st.status[i] = status;
             atomicAdd(&cnt->retired[status], 1ull);
-            atomicAdd(&cnt->w_retired[status], w);
+            atomicAdd(&cnt->w_retired[status], w_end);
         }
     }
     // block total of particle-steps, one atomic per block
@@ -1278,7 +1324,7 @@ __global__ void k_zero_live(DevCounters *cnt, int slot) {
 __device__ __forceinline__ void copy_tangent(const DevTan &a, const DevTan &b, uint64_t i, uint64_t j) {
     if (!a.base) return;
 #pragma unroll
-    for (int q = 0; q <= kTanLnw; ++q) b.col(q)[j] = a.col(q)[i];
+    for (int q = 0; q < kTanCols; ++q) b.col(q)[j] = a.col(q)[i];
 }
 
 __global__ void k_compact(DevState src, DevState dst, DevTan tsrc, DevTan tdst, DevCounters *cnt, int from) {

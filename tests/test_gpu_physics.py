@@ -1,0 +1,135 @@
+"""Closed-form checks of the HIP path itself (not through the oracle): in a
+spherical grid holding a uniform field B along z and no flow, the SDE of
+section 2.1 reduces to streaming along z and pitch-angle scattering, whose
+moments are known exactly: the pitch-angle correlation <mu(t) mu(0)> =
+<mu0^2> e^{-2 D t} for D_mumu = D (1 - mu^2), the finite-time parallel
+displacement 2 kappa [t - (1 - e^{-2Dt})/(2D)] with kappa = v lambda / 3, the
+long-time kappa_par = v lambda / 3 for Eq. 5, and the cross-field spread
+4 kappa_perp t."""
+import math
+
+import numpy as np
+import pytest
+
+import fte_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+AU = W.AU
+DEG = W.DEG
+E100 = 100 * W.KEV
+EPS100 = E100 / (W.M_P * W.C_LIGHT ** 2)
+P100 = math.sqrt(EPS100 * (EPS100 + 2))
+V100 = W.C_LIGHT * P100 / math.sqrt(1 + P100 ** 2)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def F(torch_cuda):
+    from paper_2404_12164_amd import fte
+    fte.lib()
+    return fte
+
+
+def _uniform_z_grid():
+    """0.9-1.1 au x colatitude 80-100 deg x longitude -10..10 deg, B = 5 nT
+    along z in spherical components, V = 0."""
+    n1, bx = (32, 64, 64), (8, 16, 16)
+    g = W.grid_desc(0, 0.9 * AU, 0.2 * AU / 32, 80 * DEG, 20 * DEG / 64, -10 * DEG, 20 * DEG / 64, n1, bx,
+                    W.uniform_leaves(n1, bx), 1, n_snap=1, phi_periodic=False)
+
+    def wind(r, th, ph, t):
+        z = np.zeros_like(r)
+        return np.stack([z, z, z, 5e-9 * np.cos(th), -5e-9 * np.sin(th), z], axis=-1)
+
+    return g, W.make_raw(g, wind)
+
+
+def _run(F, torch, model, lam, kperp, n, steps, dt=1.0, snap_at=()):
+    g, raw = _uniform_z_grid()
+    p = dict(mass=W.M_P, dmm_model=model, dmm_norm=0, lambda_ref=lam, q=5 / 3, eps=0.048, mu_floor=1e-4,
+             kperp_ratio=kperp, dt=dt, r_in=0.5 * AU, r_out=2 * AU, seed=7, run_id=0, precision="fp64",
+             observers=[], n_batch=1)
+    inj = dict(r=AU, th_lo=90 * DEG, th_hi=90 * DEG, ph_lo=0.0, ph_hi=0.0, e_lo=E100, e_hi=E100,
+               gamma_inj=1.0, w0=1.0, pid0=0, n_total=n, k0=0, n_inj_steps=0)
+    sim = F.Simulation(p, g, n)
+    sim.load_grid(raw)
+    sim.set_launch(256, 50, 0, 0)
+    sim.inject(inj, n, 0)
+    out = [sim.particles()]
+    done = 0
+    for s in list(snap_at) + [steps]:
+        sim.step(s - done)
+        done = s
+        out.append(sim.particles())
+    torch.cuda.synchronize()
+    sim.close()
+    for o in out:
+        assert np.all(o["status"] == 0)
+        assert np.array_equal(o["pid"], out[0]["pid"])
+    return out
+
+
+def test_pitch_angle_correlation_iso(F, torch_cuda):
+    Dc = 1e-3
+    lam = V100 / (2 * Dc)                 # ISO: D = v / (2 lambda)
+    N = 40000
+    out = _run(F, torch_cuda, "iso", lam, 0.0, N, 1500, snap_at=(500, 1000))
+    mu0 = out[0]["mu"]
+    for t, o in zip((500, 1000, 1500), out[1:]):
+        c = mu0 * o["mu"]
+        want = np.mean(mu0 * mu0) * math.exp(-2 * Dc * t)
+        assert abs(c.mean() - want) < 4 * c.std() / math.sqrt(N), (t, c.mean(), want)
+
+
+def test_parallel_displacement_iso_finite_time(F, torch_cuda):
+    Dc = 1e-3
+    lam = V100 / (2 * Dc)
+    kap = V100 * lam / 3
+    N = 40000
+    out = _run(F, torch_cuda, "iso", lam, 0.0, N, 3000, snap_at=(1000, 2000))
+    z0 = out[0]["x"][:, 2]
+    for t, o in zip((1000, 2000, 3000), out[1:]):
+        dz2 = (o["x"][:, 2] - z0) ** 2
+        want = 2 * kap * (t - (1 - math.exp(-2 * Dc * t)) / (2 * Dc))
+        assert abs(dz2.mean() - want) < 4 * dz2.std() / math.sqrt(N) + 6 * Dc * want, (t, dz2.mean(), want)
+        # no cross-field motion without kappa_perp (the field lines are straight)
+        dxy = np.hypot(o["x"][:, 0] - out[0]["x"][:, 0], o["x"][:, 1] - out[0]["x"][:, 1])
+        assert dxy.max() < 1e-3 * math.sqrt(want)      # only the interpolated b wobbles
+
+
+def _eq5_integral(eps):
+    """Int_{-1}^{1} (1 - mu^2) / (|mu| / (1 + |mu|) + eps) dmu by quadrature."""
+    from scipy.integrate import quad
+    return 2 * quad(lambda m: (1 - m * m) / (m / (1 + m) + eps), 0, 1, epsabs=0, epsrel=1e-12)[0]
+
+
+def test_kappa_par_eq5_and_kappa_perp(F, torch_cuda):
+    """Eq. 5 scattering from an isotropic start (mu stationary from t = 0):
+    the displacement along B has <z^2>(t) = 2 kappa_par t - K + (terms that
+    decay with the pitch-angle relaxation), so the slope between two late
+    times is 2 kappa_par, kappa_par = v lambda / 3 for the MFP normalisation
+    of D_mumu; across B the spread is 4 kappa_perp t."""
+    lam = 3e8
+    A = 3 * V100 * _eq5_integral(0.048) / (8 * lam)      # D_mumu = A (1 - mu^2)(|mu|/(1+|mu|) + eps)
+    dt = 1.5e-3 / A
+    ratio = 0.05
+    N = 100000
+    n1, n2 = 10000, 40000                                 # A t = 15 and 60
+    out = _run(F, torch_cuda, "eq5", lam, ratio, N, n2, dt=dt, snap_at=(n1,))
+    z0 = out[0]["x"][:, 2]
+    q = (out[2]["x"][:, 2] - z0) ** 2 - (out[1]["x"][:, 2] - z0) ** 2
+    scale = 2 * (n2 - n1) * dt * (V100 * lam / 3)
+    k = q.mean() / scale
+    s = q.std() / math.sqrt(N) / scale
+    assert abs(k - 1) < 4 * s + 0.02, (k, s)
+    dxy2 = (out[2]["x"][:, 0] - out[0]["x"][:, 0]) ** 2 + (out[2]["x"][:, 1] - out[0]["x"][:, 1]) ** 2
+    want = 4 * ratio * V100 * lam / 3 * n2 * dt
+    assert abs(dxy2.mean() - want) < 4 * dxy2.std() / math.sqrt(N), (dxy2.mean(), want)
