@@ -125,25 +125,28 @@ def gradient_leg(F, W, raw, args):
     """Differentiation workload (10^6 protons, 8,000 steps, smoothed
     intensities at the three 1-au observers): time of the plain forward pass,
     of the forward pass with smoothed sums, and of the gradient pass (tangents
-    + derivative sums), each over the whole run; then the gradient of two
-    losses against central differences (h = 1e-3, common random numbers) of
-    the smoothed forward pass on the GPU, with hard absorbing spheres and
-    again with absorbing layers in front of them."""
+    + derivative sums), each over the whole run.  Then the gradient of the
+    summed intensity against central differences (h = 1e-3, common random
+    numbers) of the smoothed forward pass on the GPU, for several seeds, with
+    the tangents' mu = 0 term of Eq. 5 (kink_sigma) and without it: the mean
+    over seeds of gradient minus difference, relative to the mean difference,
+    with its standard error."""
     import torch
     cfg = W.cir_differentiation(precision=args.precision)
     n_steps = cfg["n_steps"]
     chunk = n_steps // 10
     p_grad = cfg["params"]
     p_smooth = dict(p_grad, grad=0)
-    p_plain = {k: v for k, v in p_grad.items() if k not in ("smoothing", "grad")}
+    p_plain = {k: v for k, v in p_grad.items() if k not in ("smoothing", "grad", "kink_sigma")}
 
-    def run(params, inj=None, timed_run=True, c0=cfg):
-        c = dict(c0, params=params, injection=inj or c0["injection"])
+    def run(params, inj=None, timed_run=True):
+        c = dict(cfg, params=params, injection=inj or cfg["injection"])
         r = Run(F, c, raw, args.precision, args.block, args.spl, args.compact, args.sort)
         res = timed(r, 10, chunk) if timed_run else None
         return r, res
 
-    out = {"workload": cfg["name"], "particles": cfg["n_particles"], "global_steps": n_steps}
+    out = {"workload": cfg["name"], "particles": cfg["n_particles"], "global_steps": n_steps,
+           "kink_sigma": p_grad["kink_sigma"]}
     r, res = run(p_plain)
     r.close()
     # warm the other two modes once, untimed, then time them
@@ -162,55 +165,54 @@ def gradient_leg(F, W, raw, args):
     r, res = run(p_grad)
     out["gradient_ms"] = round(res["ms"], 2)
     out["gradient_kernel_ms"] = round(res["kernel_ms"], 2)
-    J, dJ = r.sim.bin_smoothed()
-    rng = np.random.default_rng(3)
-    losses = [np.ones(J.shape), rng.random(J.shape)]
-    g_dev = [r.sim.grad_of(w) for w in losses]
+    J, _ = r.sim.bin_smoothed()
+    out["J_nonzero"] = int((J > 0).sum())
     r.close()
     out["grad_over_forward"] = round(out["gradient_ms"] / out["forward_ms"], 3)
     out["grad_over_smoothed_forward"] = round(out["gradient_ms"] / out["forward_smoothed_ms"], 3)
 
-    def fd_rel_err(c0, g_dev):
-        """Central differences with common random numbers of the smoothed
-        forward pass of workload c0; relative deviation of g_dev per loss."""
-        h = 1e-3
-        ps = dict(c0["params"], grad=0)
+    def full(params, inj=None):
+        rr, _ = run(params, inj=inj, timed_run=False)
+        for _ in range(10):
+            rr.chunk(chunk)
+        return rr
+
+    h = 1e-3
+    keys = ("lambda_ref", "kperp_ratio", "gamma_inj")
+    rows = {"kink": [], "no_kink": [], "fd": []}
+    for seed in range(args.grad_seeds):
+        ps = dict(p_grad, seed=seed)
+        for name, ks in (("kink", p_grad["kink_sigma"]), ("no_kink", 0.0)):
+            rr = full(dict(ps, kink_sigma=ks))
+            Js, _ = rr.sim.bin_smoothed()
+            rows[name].append(rr.sim.grad_of(np.ones(Js.shape)))
+            rr.close()
         fd = []
-        for key in ("lambda_ref", "kperp_ratio", "gamma_inj"):
-            Js = []
+        for key in keys:
+            Jpm = []
             for sgn in (1, -1):
                 if key == "gamma_inj":
-                    base = c0["injection"]["gamma_inj"]
-                    rr, _ = run(ps, inj=dict(c0["injection"], gamma_inj=base * (1 + sgn * h)), timed_run=False,
-                                c0=c0)
+                    base = cfg["injection"]["gamma_inj"]
+                    rr = full(dict(ps, grad=0), inj=dict(cfg["injection"], gamma_inj=base * (1 + sgn * h)))
                 else:
                     base = ps[key]
-                    rr, _ = run(dict(ps, **{key: base * (1 + sgn * h)}), timed_run=False, c0=c0)
-                for _ in range(10):
-                    rr.chunk(chunk)
-                Js.append(rr.sim.bin_smoothed()[0])
+                    rr = full(dict(ps, grad=0, **{key: base * (1 + sgn * h)}))
+                Jpm.append(rr.sim.bin_smoothed()[0].sum())
                 rr.close()
-            fd.append((Js[0] - Js[1]) / (2 * h * base))
-        rel = []
-        for w, gd in zip(losses, g_dev):
-            gf = np.array([(f * w).sum() for f in fd])
-            rel.append([float(abs(a - b) / abs(b)) if b != 0 else None for a, b in zip(gd, gf)])
-        return rel
-
-    out["grad_sum_J"] = [float(v) for v in g_dev[0]]
-    out["fd_rel_err"] = fd_rel_err(cfg, g_dev)
-    out["J_nonzero"] = int((J > 0).sum())
-    # absorbing layers: the same workload, the pathwise gradient now smooth
-    # across the boundaries
-    cl = W.cir_differentiation(precision=args.precision, layers=True)
-    r, res = run(cl["params"], c0=cl)
-    Jl, _ = r.sim.bin_smoothed()
-    gl = [r.sim.grad_of(w) for w in losses]
-    r.close()
-    out["layers"] = {"absorb_layer_au": cl["params"]["absorb_layer"] / W.AU,
-                     "absorb_rate": cl["params"]["absorb_rate"], "gradient_ms": round(res["ms"], 2),
-                     "grad_sum_J": [float(v) for v in gl[0]], "fd_rel_err": fd_rel_err(cl, gl),
-                     "J_sum_over_hard": float(Jl.sum() / J.sum())}
+            fd.append((Jpm[0] - Jpm[1]) / (2 * h * base))
+        rows["fd"].append(np.array(fd))
+        log(f"  gradient seed {seed}: kink {rows['kink'][-1]}, no kink {rows['no_kink'][-1]}, fd {fd}")
+    fd = np.array(rows["fd"])
+    out["fd_seeds"] = args.grad_seeds
+    for name in ("kink", "no_kink"):
+        g = np.array(rows[name])
+        d = g - fd
+        m = fd.mean(axis=0)
+        out[f"{name}_vs_fd"] = {k: {"rel": float(d[:, q].mean() / m[q]),
+                                    "se": float(d[:, q].std(ddof=1) / math.sqrt(len(d)) / abs(m[q]))
+                                    if len(d) > 1 else None}
+                                for q, k in enumerate(keys)}
+    out["fd_mean"] = [float(v) for v in fd.mean(axis=0)]
     return out
 
 
@@ -295,6 +297,43 @@ def ensemble_leg(F, W, args):
     out.update(sequential_ms=round(seq_ms, 1), sequential_particle_steps=seq_steps,
                sequential_value=seq_steps / (seq_ms / 1e3), ensemble_speedup=round(seq_ms / ms, 3))
     del raw
+    torch.cuda.empty_cache()
+    return out
+
+
+def largest_leg(F, W, args, hours=24):
+    """The largest workload (shocked CIR with compression 3 at both shocks, 3
+    AMR levels, 2,880 leaves, 96 hourly snapshots, kappa_perp, a 10^8-particle
+    store, 5 observers x 20 energies x 288 time bins) over its first `hours`
+    of continuous injection: the step throughput and the memory it holds."""
+    import torch
+    dev = torch.device("cuda:0")
+    c = W.cir_largest(precision=args.precision)
+    g = c["grid"]
+    t = time.time()
+    raw = W.make_raw(g, c["wind"], xp=torch, device=dev)
+    torch.cuda.synchronize()
+    wind_s = time.time() - t
+    r = Run(F, c, raw, args.precision, args.block, args.spl, args.compact, args.sort)
+    del raw
+    torch.cuda.empty_cache()
+    n_steps = int(hours * 3600 / c["params"]["dt"])
+    chunk = 576
+    res = timed(r, n_steps // chunk, chunk)
+    st = res["stats"]
+    sz = F.fte_query_sizes(r.p, g, c["n_particles"])
+    lv = np.asarray(g["leaves"])
+    out = {"workload": c["name"], "leaves": int(len(lv)), "leaf_cells": int(len(lv) * np.prod(g["bx"])),
+           "levels": 3, "snapshots": g["n_snap"], "particle_store": c["n_particles"],
+           "global_steps": n_steps, "of_steps": c["n_steps"], "particles_injected": int(st.n_injected),
+           "particle_steps": res["particle_steps"], "ms": round(res["ms"], 1),
+           "value": res["particle_steps"] / (res["ms"] / 1e3), "grid_GB": round(sz.grid_bytes / 1e9, 2),
+           "state_GB": round(2 * sz.state_bytes / 1e9, 2), "hist_MB": round(sz.hist_bytes / 1e6, 2),
+           "wind_gen_s": round(wind_s, 2), "grid_load_s": round(r.load_s, 2),
+           "device_peak_GB": round(torch.cuda.max_memory_allocated() / 1e9, 1),
+           "retired": list(st.n_retired), "device_flags": int(st.device_flags)}
+    r.close()
+    del r
     torch.cuda.empty_cache()
     return out
 
@@ -448,6 +487,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")
+    ap.add_argument("--grad-seeds", type=int, default=4, help="seeds of the gradient-vs-differences check")
+    ap.add_argument("--no-largest", action="store_true", help="skip the largest workload (first 24 h)")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble workload")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's CIR experiment at 1-3 AMR levels")
     ap.add_argument("--no-stream", action="store_true", help="skip the snapshot-streaming run of the CIR workload")
@@ -517,7 +558,7 @@ def main():
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4),
                 traffic=read_traffic("k_step_cir_traffic.txt", per_launch_bytes),
-                kernel="k_step<float,false,0,false>" if args.precision == "mixed" else "k_step<double,false,0,false>",
+                kernel="k_step<float,false,0,false,false>" if args.precision == "mixed" else "k_step<double,false,0,false,false>",
                 bytes_per_particle_step=b_step, launches=res["launches"],
                 avg_launch_ms=round(res["kernel_ms"] / max(res["launches"], 1), 4),
                 algo_bytes_per_launch=round(per_launch_bytes))
@@ -551,6 +592,10 @@ def main():
     if not args.no_paper:
         log("the paper's CIR experiment: region injection, Green's function, 1-3 AMR levels")
         extra["paper"] = paper_leg(F, W, args)
+
+    if not args.no_largest:
+        log("largest workload: shocked CIR, 3 levels, 96 snapshots, 10^8-particle store, first 24 h")
+        extra["largest"] = largest_leg(F, W, args)
 
     cpu = None
     if not args.no_cpu:

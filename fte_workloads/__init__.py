@@ -220,6 +220,43 @@ def cir_wind_corotating(r, th, ph, t, omega=OMEGA_CIR, **kw):
     return xp.stack([f[..., 0], f[..., 1], vph, f[..., 3], f[..., 4], f[..., 5]], -1)
 
 
+def cir_shocked_wind(r, th, ph, t, Vs=330e3, Vf=650e3, omega=OMEGA_CIR, U=500e3, r_B=0.1 * AU,
+                     psi_R=60 * DEG, psi_F=75 * DEG, psi_S=250 * DEG, comp=3.0, width_shock=0.2 * DEG,
+                     width_if=2.5 * DEG, width_rare=40 * DEG, B0=5e-9 * 100.0):
+    """The CIR pattern of cir_wind with its two compressive ramps turned into
+    shocks of compression ratio comp.
+
+    The pattern is steady in the frame corotating with it, where its surfaces
+    psi = const are spirals whose normal sees the flow component proportional
+    to V_r - U.  Mass flux through a shock of compression comp divides that
+    component by comp, so the fast wind Vf drops to U + (Vf - U)/comp across
+    the reverse shock at psi_R, the slow wind Vs is reached from
+    U - (U - Vs)/comp across the forward shock at psi_F, the two downstream
+    speeds join across a stream interface midway (width width_if), and a wide
+    rarefaction at psi_S returns to Vf.  The shock width (width_shock in psi)
+    is far below a grid cell, so the grid holds each shock as a one-cell
+    jump.  B is radial ~ r^-2, wound by the local speed."""
+    xp = _xp(r)
+    two_pi = 2.0 * math.pi
+    psi = ph - omega * t + omega * (r - r_B) / U
+    psi = psi - two_pi * xp.floor(psi / two_pi)
+    v_r2 = U + (Vf - U) / comp
+    v_f2 = U - (U - Vs) / comp
+
+    def H(x):
+        return 0.5 * (1.0 + xp.tanh(x))
+
+    V = (Vf - (Vf - v_r2) * H((psi - psi_R) / width_shock)
+         - (v_r2 - v_f2) * H((psi - 0.5 * (psi_R + psi_F)) / width_if)
+         - (v_f2 - Vs) * H((psi - psi_F) / width_shock)
+         + (Vf - Vs) * H((psi - psi_S) / (width_rare * (r_B / r) ** 0.5)))
+    Br = B0 * (r_B / r) ** 2
+    Bph = -Br * omega * r * xp.sin(th) / V
+    z = r * 0.0
+    return xp.stack([V, z, z, Br, z, Bph], -1)
+
+
+
 def affine_fields(r_or_xi, th, ph, t, coef):
     """A field affine in (xi, theta, phi, t) for each of the six components;
     coef is [6][5] = constant, d/dxi, d/dtheta, d/dphi, d/dt."""
@@ -329,22 +366,19 @@ def cir_time_dependent(n_particles=10_000_000, n_steps=16920, precision="mixed",
                 n_particles=n_particles, n_steps=n_steps)
 
 
-def cir_differentiation(n_particles=1_000_000, n_steps=8000, precision="mixed", n_snap=48, layers=False):
+def cir_differentiation(n_particles=1_000_000, n_steps=8000, precision="mixed", n_snap=48, kink_sigma=0.03):
     """Gradient workload: the CIR wind and grid of cir_time_dependent, 10^6
     protons (5-50 keV, E^-4) injected continuously over 8,000 steps of 10 s,
     Eq. 5 scattering with lambda = 0.2 au, kappa_perp / kappa_par = 0.02, and
     intensities at the three 1-au observers smoothed by Gaussians of 0.05 au,
     0.1 in ln E and 10 min; differentiated with respect to (lambda, kappa
-    ratio, injection index).  layers: absorbing layers 0.02 au wide inside
-    r_in and r_out at a peak rate of 0.047/s (a 50 keV proton crossing at
-    |mu| = 1 keeps e^-15 of its weight)."""
+    ratio, injection index), the mu = 0 term of Eq. 5 in the tangents carried
+    by a Gaussian of width kink_sigma."""
     cfg = cir_time_dependent(n_particles=n_particles, n_steps=n_steps, precision=precision, n_snap=n_snap)
     params = dict(cfg["params"], dmm_model="eq5", eps=0.048, kperp_ratio=0.02,
                   n_t=int(math.ceil(n_steps * 10.0 / 600.0)),
-                  smoothing=dict(sigma_x=0.05 * AU, sigma_lne=0.1, sigma_t=600.0), grad=1)
-    if layers:
-        params.update(absorb_layer=0.02 * AU, absorb_rate=0.047)
-    return dict(cfg, name="cir_differentiation" + ("_layers" if layers else ""), params=params)
+                  smoothing=dict(sigma_x=0.05 * AU, sigma_lne=0.1, sigma_t=600.0), grad=1, kink_sigma=kink_sigma)
+    return dict(cfg, name="cir_differentiation", params=params)
 
 
 def cir_ensemble(n_runs=64, precision="mixed", seed=0, n_snap=57, particle_range=(1e4, 1e6),
@@ -413,3 +447,66 @@ def particle_spec_like(inj, **over):
     d = dict(inj)
     d.update(over)
     return d
+
+
+def cir_largest_grid(n_snap=96):
+    """Stretched 3-level grid for the shocked CIR: 128 log-spaced radial cells
+    over 0.1-2 au (ratio 20^(1/128) per cell), 32 colatitude cells over 30-150
+    deg (the block rule of three levels needs a multiple of 8 there; 30 would
+    not divide), 96 longitude cells, blocks of 16 x 8 x 16 cells; level 2 on
+    the band the compression region sweeps during the run (the region
+    criterion of section 2.3, Eq. 7, for the pattern speed U) near the
+    equator, level 3 on a narrower band around both shocks."""
+    n1, bx = (128, 32, 96), (16, 8, 16)
+    dxi = math.log(20.0) / n1[0]
+    dth = 120 * DEG / n1[1]
+    dph = 2 * math.pi / n1[2]
+    r_B, U, om = 0.1 * AU, 500e3, OMEGA_CIR
+    sweep = om * (n_snap - 1) * 3600.0
+    bands = {1: (45 * DEG, 90 * DEG + sweep + 15 * DEG, 55 * DEG, 125 * DEG),
+             2: (55 * DEG, 80 * DEG + sweep + 5 * DEG, 65 * DEG, 115 * DEG)}
+
+    def refine(L, I, J, K):
+        if L not in bands:
+            return False
+        lo, hi, t_lo, t_hi = bands[L]
+        h = 2.0 ** (1 - L)
+        th0 = 30 * DEG + J * bx[1] * dth * h
+        th1 = th0 + bx[1] * dth * h
+        if th1 <= t_lo or th0 >= t_hi:
+            return False
+        r0 = r_B * math.exp(I * bx[0] * dxi * h)
+        r1 = r_B * math.exp((I + 1) * bx[0] * dxi * h)
+        p0 = K * bx[2] * dph * h
+        p1 = p0 + bx[2] * dph * h
+        a = p0 + (r0 - r_B) * om / U
+        b = p1 + (r1 - r_B) * om / U
+        two = 2 * math.pi
+        return any(a + sh < hi and b + sh > lo for sh in (-two, 0.0, two))
+
+    leaves = amr_leaves(n1, bx, 3, refine)
+    return grid_desc(1, r_B, dxi, 30 * DEG, dth, 0.0, dph, n1, bx, leaves, 3, n_snap=n_snap, t_s0=0.0,
+                     dt_s=3600.0)
+
+
+def cir_largest(n_particles=100_000_000, precision="mixed", n_snap=96):
+    """Largest workload: the shocked CIR (compression 3 at both shocks) on the
+    3-level grid of cir_largest_grid, 96 hourly snapshots; 10^8 protons of
+    1-100 keV (E^-4) injected continuously at 0.1 au over the 95 h the
+    snapshots span (34,200 steps of 10 s); power-law D_mumu with
+    lambda = 0.2 au, kappa_perp / kappa_par = 0.01; five observers at 0.5,
+    0.75, 1.0, 1.25 and 1.5 au on the equator at longitude 0, 20 log energy
+    bins 1-100 keV x 288 time bins of 20 min."""
+    g = cir_largest_grid(n_snap=n_snap)
+    n_steps = int(round((n_snap - 1) * 3600.0 / 10.0))
+    params = dict(mass=M_P, dmm_model="power_q", dmm_norm=0, lambda_ref=0.2 * AU, p_ref=1.0, alpha=0.0,
+                  q=5.0 / 3.0, eps=0.0, mu_floor=1e-4, kperp_ratio=0.01, lambda_perp=0.0, dt=10.0, t0=0.0,
+                  r_in=0.05 * AU, r_out=2.0 * AU, check_bounds=1, run_id=0, seed=0,
+                  observers=[(r * AU, 90 * DEG, 0.0, 0.05 * AU, 10 * DEG, 10 * DEG)
+                             for r in (0.5, 0.75, 1.0, 1.25, 1.5)],
+                  t_ref=0.0, dT=1200.0, n_t=288, n_batch=32, precision=precision, **_bins(1.0, 100.0, 20))
+    inj = dict(r=0.1 * AU, th_lo=30 * DEG, th_hi=150 * DEG, ph_lo=0.0, ph_hi=2 * math.pi,
+               e_lo=1 * KEV, e_hi=100 * KEV, gamma_inj=4.0, w0=1.0, pid0=0, n_total=n_particles,
+               k0=0, n_inj_steps=n_steps)
+    return dict(name="cir_largest", grid=g, wind=cir_shocked_wind, wind_kw={}, params=params, injection=inj,
+                n_particles=n_particles, n_steps=n_steps)

@@ -166,6 +166,14 @@ typedef struct {
      * kperp_ratio) and dJ includes them.  0 / 0: hard absorption only.      */
     double absorb_layer;  /* m                                                     */
     double absorb_rate;   /* 1/s                                                   */
+    /* Gradient mode with FTE_DMM_EQ5: |mu| in Eq. 5 gives dD/dmu a jump of
+     * 2A at mu = 0, which the derivative of each sampled step does not see
+     * (a.e. d2D/dmu2 has no Dirac term).  kink_sigma > 0 adds to the
+     * tangents' d2D/dmu2 the term 2A G(mu), G a normalised Gaussian of that
+     * width standing for the Dirac (the local time at mu = 0 of the
+     * continuous process); 0: the tangents are the exact derivatives of each
+     * sampled path.  Trajectories are unchanged either way.                   */
+    double kink_sigma;
 } fte_params;
 
 /* Block-AMR spherical grid (section 2.4).  Coordinates (xi, theta, phi), with

@@ -57,6 +57,7 @@ struct DevParams {
     int kperp_any;           // some run has kappa_perp: 13-field records, KPERP kernels
     double layer_k0dt;       // absorbing layers: peak decay per step k0 dt (0: off)
     double layer_inv_h;      // 1 / layer width
+    double kink_norm, kink_inv_2s2;   // tangents: 2 / (sqrt(2 pi) s), 1 / (2 s^2) (0: off)
     uint64_t seed;
     int dmm_model;
     int run_id;

@@ -719,16 +719,6 @@ __device__ __forceinline__ R dmm_g1(const DevParams &P, R mu) {
     return (q - (R)1) * sgn(mu) * M<R>::pow_(amx, q - (R)2) * om - (R)2 * mu * M<R>::pow_(am, q - (R)1);
 }
 
-// Survival factor exp(x) of one step in an absorbing layer.  Out of line in
-// double: the step kernels reach it rarely, and inlined its temporaries would
-// add to the register peak of every step.
-__device__ __noinline__ double layer_survival_f64(double x) { return ::exp(x); }
-template <typename R>
-__device__ __forceinline__ R layer_survival(double x) {
-    if constexpr (std::is_same<R, float>::value) return M<float>::exp_((float)x);
-    else return layer_survival_f64(x);
-}
-
 // MODE 0: histogram estimator only.  MODE 1: also the kernel-smoothed sums.
 // MODE 2: also the pathwise tangents d(x, mu, ln p)/d(lambda_ref,
 // kperp_ratio), propagated by the derivative of the same Euler-Maruyama map
@@ -755,7 +745,7 @@ constexpr int step_wpe() {
     return MODE == 2 ? 1 : (std::is_same<R, float>::value ? FTE_STEP_WPE_F32 : FTE_STEP_WPE_F64);
 }
 
-template <typename R, bool KPERP, int MODE, bool LIDX>
+template <typename R, bool KPERP, int MODE, bool LIDX, bool LAYER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R, MODE>()))) void k_step(DevParams P, DevGrid G, DevState st, DevTan tn, DevCounters *cnt,
                                               int slot, double *hist, double *sm, uint64_t n0, uint32_t n_steps,
                                               StepLds LD) {
@@ -1007,7 +997,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
             // ---- tangent update: derivative of the same map
             if constexpr (MODE == 2) {
                 const R G2 = M<R>::div_((R)1, (R)1 + Pm * Pm);     // (d v / d ln p) / v
-                const R g1 = dmm_g1<R>(P, mu), g2 = dmm_g2<R>(P, mu);
+                const R g1 = dmm_g1<R>(P, mu);
+                R g2 = dmm_g2<R>(P, mu);
+                // Eq. 5's |mu| puts a jump of 2 into dg/dmu at mu = 0, i.e. a
+                // Dirac term 2 delta(mu) into g'' (the local time at mu = 0 in
+                // the tangent of the continuous process); with kink_norm > 0 a
+                // Gaussian of width kink_sigma stands for it
+                if (P.kink_norm > 0.0)
+                    g2 += (R)P.kink_norm * M<R>::exp_(-mu * mu * (R)P.kink_inv_2s2);
                 const R iv = M<R>::div_((R)1, v);
                 const R halfD = D > (R)0 ? M<R>::div_(nmu, (R)2 * D) : (R)0;   // d noise / d D
 #pragma unroll
@@ -1088,7 +1085,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
             // ---- absorbing layers: survival over this step at the post-step
             // radius, a factor exp(-k0 dt (u_in^2 + u_out^2)) with u = 1 - d / h
             // where the distance d to a boundary is below h
-            if (P.layer_k0dt > 0.0) {
+            if constexpr (LAYER) {
                 double u_in = 1.0 - (r - P.r_in) * P.layer_inv_h;
                 double u_out = 1.0 - (P.r_out - r) * P.layer_inv_h;
                 u_in = u_in > 0.0 ? u_in : 0.0;
@@ -1096,7 +1093,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                 if (u_in > 0.0 || u_out > 0.0) {
                     L_in += (R)(u_in * u_in);
                     L_out += (R)(u_out * u_out);
-                    wf *= layer_survival<R>(-P.layer_k0dt * (u_in * u_in + u_out * u_out));
+                    wf *= M<R>::exp_((R)(-P.layer_k0dt * (u_in * u_in + u_out * u_out)));
                     if constexpr (MODE == 2) {
                         // d ln w = -k0 dt (2 / h)(u_out - u_in) dr, dr = x . dx / r
                         const double g = -P.layer_k0dt * 2.0 * P.layer_inv_h * (u_out - u_in) / r;
@@ -1204,7 +1201,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
             }
         }
         const double w_end = w_now();
-        if (w_end != w) {
+        if (LAYER && w_end != w) {
             // the removed weight, split between the layers in proportion to
             // their accumulated rates
             st.w[i] = w_end;
@@ -1244,16 +1241,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
     }
 }
 
+// Instances: the LDS block index only when the build allows it (it is off by
+// default), the absorbing layers only when the context has them, so that the
+// kernels of a plain run carry no code of either.
 template <typename R, bool KPERP, int MODE>
 static void launch_step_m(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
                           double *hist, double *sm, uint64_t n0, uint32_t n_steps, dim3 grid, dim3 blk, StepLds ld,
                           size_t shmem, bool lidx, hipStream_t s) {
-    if (lidx)
-        hipLaunchKernelGGL((k_step<R, KPERP, MODE, true>), grid, blk, shmem, s, p, g, st, tn, cnt, slot, hist, sm, n0,
-                           n_steps, ld);
+    if constexpr (kLdsIndexBytes > 0) {
+        if (lidx) {
+            if (p.layer_k0dt > 0.0)
+                hipLaunchKernelGGL((k_step<R, KPERP, MODE, true, true>), grid, blk, shmem, s, p, g, st, tn, cnt, slot,
+                                   hist, sm, n0, n_steps, ld);
+            else
+                hipLaunchKernelGGL((k_step<R, KPERP, MODE, true, false>), grid, blk, shmem, s, p, g, st, tn, cnt, slot,
+                                   hist, sm, n0, n_steps, ld);
+            return;
+        }
+    }
+    if (p.layer_k0dt > 0.0)
+        hipLaunchKernelGGL((k_step<R, KPERP, MODE, false, true>), grid, blk, shmem, s, p, g, st, tn, cnt, slot, hist,
+                           sm, n0, n_steps, ld);
     else
-        hipLaunchKernelGGL((k_step<R, KPERP, MODE, false>), grid, blk, shmem, s, p, g, st, tn, cnt, slot, hist, sm, n0,
-                           n_steps, ld);
+        hipLaunchKernelGGL((k_step<R, KPERP, MODE, false, false>), grid, blk, shmem, s, p, g, st, tn, cnt, slot, hist,
+                           sm, n0, n_steps, ld);
 }
 
 template <typename R, bool KPERP>

@@ -57,7 +57,7 @@ class fte_params(C.Structure):
                 ("t_ref", C.c_double), ("dT", C.c_double), ("n_t", C.c_int), ("n_batch", C.c_int),
                 ("sigma_x", C.c_double), ("sigma_lne", C.c_double), ("sigma_t", C.c_double), ("grad", C.c_int),
                 ("n_runs", C.c_int), ("runs", C.POINTER(fte_run)),
-                ("absorb_layer", C.c_double), ("absorb_rate", C.c_double)]
+                ("absorb_layer", C.c_double), ("absorb_rate", C.c_double), ("kink_sigma", C.c_double)]
 
 
 class fte_grid_desc(C.Structure):
@@ -196,6 +196,7 @@ def make_params(p: dict) -> fte_params:
         o._runs_keep = arr          # the C call reads the table; keep it alive with the struct
     o.absorb_layer = p.get("absorb_layer", 0.0)
     o.absorb_rate = p.get("absorb_rate", 0.0)
+    o.kink_sigma = p.get("kink_sigma", 0.0)
     return o
 
 

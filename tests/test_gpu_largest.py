@@ -1,0 +1,90 @@
+"""The largest workload at full size: the shocked CIR on the 3-level grid
+(2,880 leaves, 5.9 M leaf cells, 96 snapshots, kappa_perp), the 10^8-particle
+store, the benchmark's launch shape and lazy continuous injection, 1,200
+steps: sampled particles re-run one by one in the oracle agree to 1e-10 on the
+FP64 path, and the mixed path on the same sample stays within a small drift."""
+import math
+
+import numpy as np
+import pytest
+
+import fte_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+AU = W.AU
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def F(torch_cuda):
+    from paper_2404_12164_amd import fte
+    fte.lib()
+    return fte
+
+
+def test_largest_full_size_sampled(F, torch_cuda, orc):
+    torch = torch_cuda
+    n_steps = 1200
+    cfg = W.cir_largest()
+    g = cfg["grid"]
+    dev = torch.device("cuda:0")
+    raw = W.make_raw(g, cfg["wind"], xp=torch, device=dev)
+    N, S = cfg["n_particles"], cfg["injection"]["n_inj_steps"]
+    inj = cfg["injection"]
+    held = {}
+    for prec in ("fp64", "mixed"):
+        p = dict(cfg["params"], precision=prec)
+        sim = F.Simulation(p, g, N)
+        sim.load_grid(raw)
+        sim.set_launch(256, 32, 128, 2)
+        injected, n0 = 0, 0
+        for chunk in (576, 576, n_steps - 1152):
+            n1 = n0 + chunk
+            j_max = min(N, int(math.ceil(n1 * N / S)) + 1)
+            sim.inject(inj, j_max - injected, injected)
+            injected = j_max
+            sim.step(chunk)
+            n0 = n1
+        torch.cuda.synchronize()
+        held[prec] = sim.particles()
+        st = sim.stats()
+        assert st.device_flags == 0
+        assert st.n_injected == injected
+        sim.close()
+        print(prec, "held", len(held[prec]["pid"]), "particle-steps", st.particle_steps, flush=True)
+    rng = np.random.default_rng(11)
+    j_hi = int(1100 * N / S)
+    sample = np.sort(rng.choice(j_hi, size=48, replace=False))
+    k_hi = int(math.floor(n_steps * cfg["params"]["dt"] / g["dt_s"])) + 2
+    G = orc.Grid(g, raw[: k_hi + 1].cpu().numpy())
+    del raw
+    p64 = dict(cfg["params"], precision="fp64")
+    ref = [orc.inject(p64, inj, 1, int(j)) for j in sample]
+    for q in ref:
+        orc.run(p64, G, q, 0, n_steps, None, 1)
+    for prec, tol in (("fp64", 1e-10), ("mixed", None)):
+        got = held[prec]
+        pos = {int(k): i for i, k in enumerate(got["pid"])}
+        drift = []
+        for j, q in zip(sample, ref):
+            if int(j) not in pos:
+                assert q.status[0] != 0, (prec, j)       # retired and compacted away
+                continue
+            i = pos[int(j)]
+            if tol is not None:
+                assert got["status"][i] == q.status[0], (j, got["status"][i], q.status[0])
+                dx = np.abs(got["x"][i] - q.x[0]).max() / max(np.abs(q.x[0]).max(), AU)
+                assert dx < tol and abs(got["mu"][i] - q.mu[0]) < tol, (j, dx)
+                assert abs(got["lnp"][i] - q.lnp[0]) < tol * max(1.0, abs(q.lnp[0]))
+            elif got["status"][i] == 0 and q.status[0] == 0:
+                drift.append(np.linalg.norm(got["x"][i] - q.x[0]) / AU)
+        if tol is None:
+            assert len(drift) > 20 and np.median(drift) < 1e-3, drift

@@ -156,3 +156,47 @@ def test_streaming_grid_sizes(F):
     for bad in (1, -2):
         with pytest.raises(F.FteError):
             F.fte_query_sizes(cfg["params"], dict(g, n_slots=bad), 1000)
+
+
+def test_largest_workload_sizes(F):
+    """The largest workload (shocked CIR, 3 levels, 96 snapshots, kappa_perp,
+    10^8 particles) validates, and its buffers fit one GPU's 288 GB: records
+    of 14 floats per padded cell for every snapshot, the particle state twice
+    (compaction ping-pong), the 5 x 20 x 288 x 32 observer sums."""
+    cfg = W.cir_largest()
+    g, p = cfg["grid"], cfg["params"]
+    s = F.fte_query_sizes(p, g, cfg["n_particles"])
+    nl = len(g["leaves"])
+    assert s.grid_bytes == 96 * nl * 18 * 10 * 18 * 14 * 4
+    assert s.hist_bytes >= 5 * 20 * 288 * 32 * 8
+    total = s.grid_bytes + s.index_bytes + 2 * s.state_bytes + s.hist_bytes + s.work_bytes
+    print("largest workload: grid", s.grid_bytes / 1e9, "GB, state", s.state_bytes / 1e9, "GB, total",
+          total / 1e9, "GB")
+    assert total < 120e9
+
+
+def test_shocked_cir_jump_conditions():
+    """The shocked CIR wind: across each shock the speed normal to the
+    corotating pattern (V_r - U along the spiral's normal) drops by the
+    compression ratio 3, upstream is the slow (forward shock) or fast
+    (reverse shock) wind, and the stream interface between them is
+    compressive too."""
+    U, Vs, Vf = 500e3, 330e3, 650e3
+    deg = W.DEG
+    r = np.full(7, 1.0 * W.AU)
+    th = np.full(7, 90 * deg)
+    # psi = phi at t = 0 and r = r_B; move phi at r = r_B = 0.1 au instead
+    rb = np.full(7, 0.1 * W.AU)
+    ph = np.array([55, 59, 61, 67.5, 74, 76, 80]) * deg
+    # a narrow interface keeps its tanh tails off the shocks' sides
+    V = W.cir_shocked_wind(rb, th, ph, 0.0, width_if=0.1 * deg)[:, 0]
+    assert V[0] == pytest.approx(Vf, rel=5e-4) and V[-1] == pytest.approx(Vs, rel=5e-4)   # rarefaction tails
+    assert (V[1] - U) / (V[2] - U) == pytest.approx(3.0, rel=2e-3)         # reverse shock at 60 deg
+    assert (V[5] - U) / (V[4] - U) == pytest.approx(3.0, rel=2e-3)         # forward shock at 75 deg
+    assert V[2] > V[3] > V[4]                                              # interface, compressive
+    # the pattern is a spiral of speed U: at 1 au the same jumps sit at
+    # longitudes shifted by omega (r - r_B) / U
+    shift = W.OMEGA_CIR * (0.9 * W.AU) / U
+    V1 = W.cir_shocked_wind(r, th, ph - shift, 0.0, width_if=0.1 * deg)[:, 0]
+    assert (V1[1] - U) / (V1[2] - U) == pytest.approx(3.0, rel=2e-3)
+    assert (V1[5] - U) / (V1[4] - U) == pytest.approx(3.0, rel=2e-3)
