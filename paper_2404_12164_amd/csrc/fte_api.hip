@@ -315,6 +315,8 @@ void make_devparams(const fte_params *p, DevParams *d) {
     d->t0 = p->t0;
     d->r_in = p->r_in;
     d->r_out = p->r_out;
+    d->r_in2 = p->r_in * p->r_in;
+    d->r_out2 = p->r_out * p->r_out;
     d->lambda_ref = p->lambda_ref;
     d->inv_p_ref = p->alpha != 0.0 ? 1.0 / p->p_ref : 1.0;
     d->alpha = p->alpha;
@@ -357,6 +359,8 @@ void make_devparams(const fte_params *p, DevParams *d) {
         const fte_observer &ob = p->obs[o];
         d->obs[o][0] = ob.r - 0.5 * ob.dr;
         d->obs[o][1] = ob.r + 0.5 * ob.dr;
+        d->obs_rsq[o][0] = d->obs[o][0] * d->obs[o][0];
+        d->obs_rsq[o][1] = d->obs[o][1] * d->obs[o][1];
         d->obs[o][2] = ob.theta - 0.5 * ob.dtheta;
         d->obs[o][3] = ob.theta + 0.5 * ob.dtheta;
         d->obs[o][4] = ob.phi;
@@ -553,6 +557,7 @@ fte_status fte_bind_buffers(fte_ctx *c, const fte_grid_desc *g, uint64_t n_max, 
     d.dth = g->dth;
     d.dph = g->dph;
     d.inv_dxi = 1.0 / g->dxi;
+    d.inv_r_lo = 1.0 / g->r_lo;
     d.th_lo = g->th_lo;
     d.inv_dth = 1.0 / g->dth;
     d.ph_lo = g->ph_lo;

@@ -29,6 +29,7 @@ struct DevRun {
 struct DevParams {
     double mass_c2;          // m c^2, J
     double dt, t0, r_in, r_out;
+    double r_in2, r_out2;    // squared absorbing radii
     double lambda_ref, inv_p_ref, alpha;
     double q, eps, mu_floor;
     double dmm_scale;        // A = dmm_scale * v / lambda_par
@@ -38,6 +39,7 @@ struct DevParams {
     double t_ref, inv_dT;
     double obs[FTE_MAX_OBS][6];  // r1, r2, th1, th2, phi centre of bin 0, bin width phi
     double obs_omega[FTE_MAX_OBS];   // rotation of each observer's pattern
+    double obs_rsq[FTE_MAX_OBS][2];  // squared radial edges r1^2, r2^2
     int obs_nphi[FTE_MAX_OBS];       // longitude bins per observer
     int obs_off[FTE_MAX_OBS];        // its first observer bin
     int n_obs_bins;
@@ -67,6 +69,7 @@ struct DevParams {
 // Block-AMR grid as the kernels see it.
 struct DevGrid {
     double r_lo, inv_dxi, th_lo, inv_dth, ph_lo, inv_dph;
+    double inv_r_lo;
     double dxi, dth, dph;        // level-1 widths
     double th_hi;                // upper colatitude edge
     double t_s0, inv_dt_s, dt_s;

@@ -335,7 +335,7 @@ struct Fields {
 // Level-1 grid coordinates of a position already reduced to (r, theta, phi),
 // folded into the domain.
 template <typename R>
-__device__ __forceinline__ void grid_coords(const DevGrid &G, double r, R th, R ph, R s[3]);
+__device__ __forceinline__ void grid_coords(const DevGrid &G, R r, R th, R ph, R s[3]);
 
 template <>
 __device__ __forceinline__ void grid_coords<double>(const DevGrid &G, double r, double th, double ph, double s[3]) {
@@ -345,8 +345,8 @@ __device__ __forceinline__ void grid_coords<double>(const DevGrid &G, double r, 
 }
 
 template <>
-__device__ __forceinline__ void grid_coords<float>(const DevGrid &G, double r, float th, float ph, float s[3]) {
-    s[0] = G.xi_map ? __logf((float)(r / G.r_lo)) * (float)G.inv_dxi : (float)((r - G.r_lo) * G.inv_dxi);
+__device__ __forceinline__ void grid_coords<float>(const DevGrid &G, float r, float th, float ph, float s[3]) {
+    s[0] = G.xi_map ? __logf(r * (float)G.inv_r_lo) * (float)G.inv_dxi : (r - (float)G.r_lo) * (float)G.inv_dxi;
     s[1] = (th - (float)G.th_lo) * (float)G.inv_dth;
     s[2] = (ph - (float)G.ph_lo) * (float)G.inv_dph;
 }
@@ -719,6 +719,21 @@ __device__ __forceinline__ R dmm_g1(const DevParams &P, R mu) {
     return (q - (R)1) * sgn(mu) * M<R>::pow_(amx, q - (R)2) * om - (R)2 * mu * M<R>::pow_(am, q - (R)1);
 }
 
+// Radius of a position and the cosine of its colatitude.  The FP64 path takes
+// both in double.  The mixed path keeps the squared radius in double (the
+// absorbing-sphere and observer-shell tests compare it with squared radii)
+// and the radius in float for the grid coordinates and the local basis.
+template <typename R>
+__device__ __forceinline__ R radius_of(double r2) {
+    if constexpr (std::is_same<R, double>::value) return ::sqrt(r2);
+    else return M<float>::sqrt_((float)r2);
+}
+template <typename R>
+__device__ __forceinline__ R cos_colat(double z, R r) {
+    if constexpr (std::is_same<R, double>::value) return z / r;
+    else return M<float>::div_((float)z, r);
+}
+
 // MODE 0: histogram estimator only.  MODE 1: also the kernel-smoothed sums.
 // MODE 2: also the pathwise tangents d(x, mu, ln p)/d(lambda_ref,
 // kperp_ratio), propagated by the derivative of the same Euler-Maruyama map
@@ -807,8 +822,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
             dlnw = (R)tn.col(kTanLnw)[i];
         }
         // spherical coordinates of the current position
-        double r = ::sqrt(x * x + y * y + z * z);
-        R th = M<R>::acos_((R)(z / r));
+        constexpr bool kF64 = std::is_same<R, double>::value;
+        double r2 = x * x + y * y + z * z;
+        R r = radius_of<R>(r2);
+        R th = M<R>::acos_(cos_colat<R>(z, r));
         R ph = M<R>::atan2_((R)y, (R)x);
         if (ph < (R)0) ph += (R)(2.0 * kPi);
         R Pcur = M<R>::exp_(lnp);
@@ -835,9 +852,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
             auto basis_at = [&]() {
                 const R xf = (R)x, yf = (R)y, zf = (R)z;
                 const R rho = M<R>::sqrt_(xf * xf + yf * yf);
-                const R rr = (R)r;
-                st_ = M<R>::div_(rho, rr);
-                ct_ = M<R>::div_(zf, rr);
+                st_ = M<R>::div_(rho, r);
+                ct_ = M<R>::div_(zf, r);
                 sp_ = M<R>::div_(yf, rho);
                 cp_ = M<R>::div_(xf, rho);
             };
@@ -849,7 +865,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
             R dacc[ND][kNF];
             R tth[ND], tph[ND], cot = (R)0;
             if constexpr (MODE == 2) {
-                const R ir = M<R>::div_((R)1, (R)r);
+                const R ir = M<R>::div_((R)1, r);
                 cot = M<R>::div_(ct_, st_);
                 R ds[ND][3];
 #pragma unroll
@@ -1066,16 +1082,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
             gcur = M<R>::sqrt_((R)1 + Pcur * Pcur);
             vcur = M<R>::div_((R)kC * Pcur, gcur);
             // ---- boundaries (radius in double on both paths)
-            r = ::sqrt(x * x + y * y + z * z);
-            if (r < P.r_in) {
+            r2 = x * x + y * y + z * z;
+            r = radius_of<R>(r2);
+            if (kF64 ? (double)r < P.r_in : r2 < P.r_in2) {
                 status = FTE_PS_ABSORBED_IN;
                 break;
             }
-            if (r > P.r_out) {
+            if (kF64 ? (double)r > P.r_out : r2 > P.r_out2) {
                 status = FTE_PS_ABSORBED_OUT;
                 break;
             }
-            th = M<R>::acos_((R)(z / r));
+            th = M<R>::acos_(cos_colat<R>(z, r));
             ph = M<R>::atan2_((R)y, (R)x);
             if (ph < (R)0) ph += (R)(2.0 * kPi);
             if (th < (R)G.th_lo || th > (R)G.th_hi) {
@@ -1086,8 +1103,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
             // radius, a factor exp(-k0 dt (u_in^2 + u_out^2)) with u = 1 - d / h
             // where the distance d to a boundary is below h
             if constexpr (LAYER) {
-                double u_in = 1.0 - (r - P.r_in) * P.layer_inv_h;
-                double u_out = 1.0 - (P.r_out - r) * P.layer_inv_h;
+                double u_in = 1.0 - ((double)r - P.r_in) * P.layer_inv_h;
+                double u_out = 1.0 - (P.r_out - (double)r) * P.layer_inv_h;
                 u_in = u_in > 0.0 ? u_in : 0.0;
                 u_out = u_out > 0.0 ? u_out : 0.0;
                 if (u_in > 0.0 || u_out > 0.0) {
@@ -1096,7 +1113,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                     wf *= M<R>::exp_((R)(-P.layer_k0dt * (u_in * u_in + u_out * u_out)));
                     if constexpr (MODE == 2) {
                         // d ln w = -k0 dt (2 / h)(u_out - u_in) dr, dr = x . dx / r
-                        const double g = -P.layer_k0dt * 2.0 * P.layer_inv_h * (u_out - u_in) / r;
+                        const double g = -P.layer_k0dt * 2.0 * P.layer_inv_h * (u_out - u_in) / (double)r;
 #pragma unroll
                         for (int k = 0; k < ND; ++k)
                             DW[k] += (R)(g * (x * (double)TX[k][0] + y * (double)TX[k][1] + z * (double)TX[k][2]));
@@ -1160,7 +1177,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                 const double t1 = P.t0 + (double)(n + 1) * P.dt;
                 for (int o = 0; o < P.n_obs; ++o) {
                     const double *ob = P.obs[o];
-                    if (!(r >= ob[0] && r < ob[1] && th >= (R)ob[2] && th < (R)ob[3])) continue;
+                    const bool shell = kF64 ? ((double)r >= ob[0] && (double)r < ob[1])
+                                            : (r2 >= P.obs_rsq[o][0] && r2 < P.obs_rsq[o][1]);
+                    if (!(shell && th >= (R)ob[2] && th < (R)ob[3])) continue;
                     R u = M<R>::fmod_(ph - (R)(ob[4] + P.obs_omega[o] * t1 - 0.5 * ob[5]), (R)(2.0 * kPi));
                     if (u < (R)0) u += (R)(2.0 * kPi);
                     const int kb = (int)M<R>::floor_(M<R>::div_(u, (R)ob[5]));
