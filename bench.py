@@ -126,8 +126,8 @@ def gradient_leg(F, W, raw, args):
     intensities at the three 1-au observers): time of the plain forward pass,
     of the forward pass with smoothed sums, and of the gradient pass (tangents
     + derivative sums), each over the whole run.  Then the gradient of the
-    summed intensity against central differences (h = 1e-3, common random
-    numbers) of the smoothed forward pass on the GPU, for several seeds, with
+    summed intensity against central differences (h = 1e-3 and 1e-2, common
+    random numbers) of the smoothed forward pass on the GPU, for several seeds, with
     the tangents' mu = 0 term of Eq. 5 (kink_sigma) and without it: the mean
     over seeds of gradient minus difference, relative to the mean difference,
     with its standard error."""
@@ -177,9 +177,10 @@ def gradient_leg(F, W, raw, args):
             rr.chunk(chunk)
         return rr
 
-    h = 1e-3
     keys = ("lambda_ref", "kperp_ratio", "gamma_inj")
-    rows = {"kink": [], "no_kink": [], "fd": []}
+    steps_h = (1e-3, 1e-2)
+    rows = {"kink": [], "no_kink": []}
+    fds = {h: [] for h in steps_h}
     for seed in range(args.grad_seeds):
         ps = dict(p_grad, seed=seed)
         for name, ks in (("kink", p_grad["kink_sigma"]), ("no_kink", 0.0)):
@@ -187,32 +188,35 @@ def gradient_leg(F, W, raw, args):
             Js, _ = rr.sim.bin_smoothed()
             rows[name].append(rr.sim.grad_of(np.ones(Js.shape)))
             rr.close()
-        fd = []
-        for key in keys:
-            Jpm = []
-            for sgn in (1, -1):
-                if key == "gamma_inj":
-                    base = cfg["injection"]["gamma_inj"]
-                    rr = full(dict(ps, grad=0), inj=dict(cfg["injection"], gamma_inj=base * (1 + sgn * h)))
-                else:
-                    base = ps[key]
-                    rr = full(dict(ps, grad=0, **{key: base * (1 + sgn * h)}))
-                Jpm.append(rr.sim.bin_smoothed()[0].sum())
-                rr.close()
-            fd.append((Jpm[0] - Jpm[1]) / (2 * h * base))
-        rows["fd"].append(np.array(fd))
-        log(f"  gradient seed {seed}: kink {rows['kink'][-1]}, no kink {rows['no_kink'][-1]}, fd {fd}")
-    fd = np.array(rows["fd"])
+        for h in steps_h:
+            fd = []
+            for key in keys:
+                Jpm = []
+                for sgn in (1, -1):
+                    if key == "gamma_inj":
+                        base = cfg["injection"]["gamma_inj"]
+                        rr = full(dict(ps, grad=0), inj=dict(cfg["injection"], gamma_inj=base * (1 + sgn * h)))
+                    else:
+                        base = ps[key]
+                        rr = full(dict(ps, grad=0, **{key: base * (1 + sgn * h)}))
+                    Jpm.append(rr.sim.bin_smoothed()[0].sum())
+                    rr.close()
+                fd.append((Jpm[0] - Jpm[1]) / (2 * h * base))
+            fds[h].append(np.array(fd))
+        log(f"  gradient seed {seed}: kink {rows['kink'][-1]}, no kink {rows['no_kink'][-1]}, "
+            f"fd {[list(fds[h][-1]) for h in steps_h]}")
     out["fd_seeds"] = args.grad_seeds
-    for name in ("kink", "no_kink"):
-        g = np.array(rows[name])
-        d = g - fd
+    for h in steps_h:
+        fd = np.array(fds[h])
         m = fd.mean(axis=0)
-        out[f"{name}_vs_fd"] = {k: {"rel": float(d[:, q].mean() / m[q]),
-                                    "se": float(d[:, q].std(ddof=1) / math.sqrt(len(d)) / abs(m[q]))
-                                    if len(d) > 1 else None}
-                                for q, k in enumerate(keys)}
-    out["fd_mean"] = [float(v) for v in fd.mean(axis=0)]
+        tag = f"h{h:g}"
+        out[f"fd_mean_{tag}"] = [float(v) for v in m]
+        for name in ("kink", "no_kink"):
+            d = np.array(rows[name]) - fd
+            out[f"{name}_vs_fd_{tag}"] = {
+                k: {"rel": float(d[:, q].mean() / m[q]),
+                    "se": float(d[:, q].std(ddof=1) / math.sqrt(len(d)) / abs(m[q])) if len(d) > 1 else None}
+                for q, k in enumerate(keys)}
     return out
 
 
