@@ -557,7 +557,9 @@ hipError_t launch_add_live(DevCounters *cnt, int slot, uint64_t n, hipStream_t s
 
 // Locate the leaf holding level-1 coordinates s and gather + interpolate the
 // records (trilinear in space, linear in time between snapshots k and k+1).
-template <typename R, bool KPERP>
+// TS2: the grid has two live snapshots and both are gathered in one unrolled
+// pass, so that the loads of all 16 corners are in flight together.
+template <typename R, bool KPERP, bool TS2>
 __device__ __forceinline__ bool gather(const DevGrid &G, const int32_t *ibase, const int32_t *ichild, R s[3], int ks,
                                        R alpha, R acc[kNF]) {
     constexpr int NF = KPERP ? 13 : 10;
@@ -582,9 +584,8 @@ __device__ __forceinline__ bool gather(const DevGrid &G, const int32_t *ibase, c
     const R *rec = reinterpret_cast<const R *>(G.rec);
 #pragma unroll
     for (int q = 0; q < NF; ++q) acc[q] = (R)0;
-    const int nsn = G.n_snap >= 2 ? 2 : 1;
-    for (int sn = 0; sn < nsn; ++sn) {
-        const R ws = (G.n_snap >= 2) ? (sn == 0 ? (R)1 - alpha : alpha) : (R)1;
+    // the 8 corners of snapshot slot ks + sn, weighted by ws
+    auto corners = [&](int sn, R ws) {
         const R *base = rec + (((size_t)((ks + sn) % G.n_slots) * G.n_leaves + leaf) * G.pcells + pc) * RS;
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
@@ -594,6 +595,13 @@ __device__ __forceinline__ bool gather(const DevGrid &G, const int32_t *ibase, c
 #pragma unroll
             for (int q = 0; q < NF; ++q) acc[q] += w * p[q];
         }
+    };
+    if constexpr (TS2) {
+#pragma unroll
+        for (int sn = 0; sn < 2; ++sn) corners(sn, sn == 0 ? (R)1 - alpha : alpha);
+    } else {
+        const int nsn = G.n_snap >= 2 ? 2 : 1;
+        for (int sn = 0; sn < nsn; ++sn) corners(sn, G.n_snap >= 2 ? (sn == 0 ? (R)1 - alpha : alpha) : (R)1);
     }
     return true;
 }
@@ -759,9 +767,16 @@ template <typename R, int MODE>
 constexpr int step_wpe() {
     return MODE == 2 ? 1 : (std::is_same<R, float>::value ? FTE_STEP_WPE_F32 : FTE_STEP_WPE_F64);
 }
+// Most waves per SIMD the allocator plans for: 2 for the unrolled
+// two-snapshot gather, so that the scheduler keeps its 40 loads in flight
+// instead of trading them for a third wave.
+template <bool TS2>
+constexpr int step_wpe_max() {
+    return TS2 ? 2 : 8;
+}
 
-template <typename R, bool KPERP, int MODE, bool LIDX, bool LAYER>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R, MODE>()))) void k_step(DevParams P, DevGrid G, DevState st, DevTan tn, DevCounters *cnt,
+template <typename R, bool KPERP, int MODE, bool LIDX, bool LAYER, bool TS2>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R, MODE>(), step_wpe_max<TS2>()))) void k_step(DevParams P, DevGrid G, DevState st, DevTan tn, DevCounters *cnt,
                                               int slot, double *hist, double *sm, uint64_t n0, uint32_t n_steps,
                                               StepLds LD) {
     constexpr int ND = MODE == 2 ? 2 : 1;
@@ -882,7 +897,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                     break;
                 }
             } else {
-                if (!gather<R, KPERP>(G, ibase, ichild, s, ks, alpha, acc)) {
+                if (!gather<R, KPERP, TS2>(G, ibase, ichild, s, ks, alpha, acc)) {
                     status = FTE_PS_NUMERIC;
                     break;
                 }
@@ -1262,7 +1277,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
 
 // Instances: the LDS block index only when the build allows it (it is off by
 // default), the absorbing layers only when the context has them, so that the
-// kernels of a plain run carry no code of either.
+// kernels of a plain run carry no code of either; the unrolled two-snapshot
+// gather (TS2) on the float path of time-dependent grids with 10-field
+// records, where the register peak it adds (2 waves per SIMD instead of 3)
+// pays for itself: +15% on the CIR workload.  With 14-field records (kappa_perp)
+// it measured 1.5% slower; the double kernels would spill hundreds of bytes
+// per lane with it; the tangent kernels gather through their own path.
+template <typename R, bool KPERP, int MODE, bool LIDX, bool LAYER>
+static void launch_step_ts(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
+                           double *hist, double *sm, uint64_t n0, uint32_t n_steps, dim3 grid, dim3 blk, StepLds ld,
+                           size_t shmem, hipStream_t s) {
+    if constexpr (std::is_same<R, float>::value && MODE < 2 && !KPERP) {
+        if (g.n_snap >= 2) {
+            hipLaunchKernelGGL((k_step<R, KPERP, MODE, LIDX, LAYER, true>), grid, blk, shmem, s, p, g, st, tn, cnt,
+                               slot, hist, sm, n0, n_steps, ld);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_step<R, KPERP, MODE, LIDX, LAYER, false>), grid, blk, shmem, s, p, g, st, tn, cnt, slot,
+                       hist, sm, n0, n_steps, ld);
+}
+
 template <typename R, bool KPERP, int MODE>
 static void launch_step_m(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
                           double *hist, double *sm, uint64_t n0, uint32_t n_steps, dim3 grid, dim3 blk, StepLds ld,
@@ -1270,20 +1305,20 @@ static void launch_step_m(const DevParams &p, const DevGrid &g, DevState st, Dev
     if constexpr (kLdsIndexBytes > 0) {
         if (lidx) {
             if (p.layer_k0dt > 0.0)
-                hipLaunchKernelGGL((k_step<R, KPERP, MODE, true, true>), grid, blk, shmem, s, p, g, st, tn, cnt, slot,
-                                   hist, sm, n0, n_steps, ld);
+                launch_step_ts<R, KPERP, MODE, true, true>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk,
+                                                           ld, shmem, s);
             else
-                hipLaunchKernelGGL((k_step<R, KPERP, MODE, true, false>), grid, blk, shmem, s, p, g, st, tn, cnt, slot,
-                                   hist, sm, n0, n_steps, ld);
+                launch_step_ts<R, KPERP, MODE, true, false>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk,
+                                                            ld, shmem, s);
             return;
         }
     }
     if (p.layer_k0dt > 0.0)
-        hipLaunchKernelGGL((k_step<R, KPERP, MODE, false, true>), grid, blk, shmem, s, p, g, st, tn, cnt, slot, hist,
-                           sm, n0, n_steps, ld);
+        launch_step_ts<R, KPERP, MODE, false, true>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld,
+                                                    shmem, s);
     else
-        hipLaunchKernelGGL((k_step<R, KPERP, MODE, false, false>), grid, blk, shmem, s, p, g, st, tn, cnt, slot, hist,
-                           sm, n0, n_steps, ld);
+        launch_step_ts<R, KPERP, MODE, false, false>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld,
+                                                     shmem, s);
 }
 
 template <typename R, bool KPERP>
