@@ -485,9 +485,9 @@ def main():
     ap.add_argument("--particles", type=int, default=10_000_000)
     ap.add_argument("--precision", default="mixed")
     ap.add_argument("--block", type=int, default=256)
-    ap.add_argument("--spl", type=int, default=32)
-    ap.add_argument("--compact", type=int, default=128)
-    ap.add_argument("--sort", type=int, default=2)
+    ap.add_argument("--spl", type=int, default=64)
+    ap.add_argument("--compact", type=int, default=64)
+    ap.add_argument("--sort", type=int, default=1)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")

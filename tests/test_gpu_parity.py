@@ -303,7 +303,7 @@ def test_full_size_cir_sampled(F, torch_cuda, orc):
         p = dict(cfg["params"], precision=prec)
         sim = F.Simulation(p, g, N)
         sim.load_grid(raw)
-        sim.set_launch(256, 32, 128, 2)
+        sim.set_launch(256, 64, 64, 1)
         injected, n0 = 0, 0
         for chunk in (564, 564, n_steps - 1128):
             n1 = n0 + chunk
