@@ -1278,16 +1278,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
 // Instances: the LDS block index only when the build allows it (it is off by
 // default), the absorbing layers only when the context has them, so that the
 // kernels of a plain run carry no code of either; the unrolled two-snapshot
-// gather (TS2) on the float path of time-dependent grids, where the register
-// peak it adds (2 waves per SIMD instead of 3) pays for itself: +15% on the
-// CIR workload, +10% on the kappa_perp ensemble, even on the largest
-// workload.  The double kernels would spill hundreds of bytes per lane with
-// it; the tangent kernels gather through their own path.
+// gather (TS2) on time-dependent grids, where the register peak it adds (2
+// waves per SIMD instead of 3 on the float path) pays for itself: +15% on the
+// CIR workload, +10% on the kappa_perp ensemble, even on the largest workload,
+// +2% on the double path (already at 2 waves).  The tangent kernels gather
+// through their own path.
 template <typename R, bool KPERP, int MODE, bool LIDX, bool LAYER>
 static void launch_step_ts(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
                            double *hist, double *sm, uint64_t n0, uint32_t n_steps, dim3 grid, dim3 blk, StepLds ld,
                            size_t shmem, hipStream_t s) {
-    if constexpr (std::is_same<R, float>::value && MODE < 2) {
+    if constexpr (MODE < 2) {
         if (g.n_snap >= 2) {
             hipLaunchKernelGGL((k_step<R, KPERP, MODE, LIDX, LAYER, true>), grid, blk, shmem, s, p, g, st, tn, cnt,
                                slot, hist, sm, n0, n_steps, ld);
