@@ -502,7 +502,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described, not run",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding of the path is described, not run",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
