@@ -212,11 +212,37 @@ def gradient_leg(F, W, raw, args):
         tag = f"h{h:g}"
         out[f"fd_mean_{tag}"] = [float(v) for v in m]
         for name in ("kink", "no_kink"):
-            d = np.array(rows[name]) - fd
+            g = np.array(rows[name])
+            d = g - fd
+            # rel: mean over seeds of (gradient - difference) relative to the
+            # mean difference; l1: sum |gradient - difference| / sum |difference|
+            # over seeds (meaningful also where the seeds' differences change
+            # sign); per_seed: each seed's relative deviation
             out[f"{name}_vs_fd_{tag}"] = {
                 k: {"rel": float(d[:, q].mean() / m[q]),
-                    "se": float(d[:, q].std(ddof=1) / math.sqrt(len(d)) / abs(m[q])) if len(d) > 1 else None}
+                    "se": float(d[:, q].std(ddof=1) / math.sqrt(len(d)) / abs(m[q])) if len(d) > 1 else None,
+                    "l1": float(np.abs(d[:, q]).sum() / np.abs(fd[:, q]).sum()),
+                    "per_seed": [round(float(v), 4) for v in d[:, q] / fd[:, q]]}
                 for q, k in enumerate(keys)}
+    # control: the same workload and check with ISO scattering (D_mumu smooth
+    # in mu), one seed
+    pi = dict(p_grad, dmm_model="iso", seed=0)
+    rr = full(pi)
+    Js, _ = rr.sim.bin_smoothed()
+    gi = rr.sim.grad_of(np.ones(Js.shape))
+    rr.close()
+    ctl = {}
+    for h in steps_h:
+        fd = []
+        for key in keys[:2]:
+            Jpm = []
+            for sgn in (1, -1):
+                rr = full(dict(pi, grad=0, **{key: pi[key] * (1 + sgn * h)}))
+                Jpm.append(rr.sim.bin_smoothed()[0].sum())
+                rr.close()
+            fd.append((Jpm[0] - Jpm[1]) / (2 * h * pi[key]))
+        ctl[f"h{h:g}"] = {k: round(float((gi[q] - fd[q]) / fd[q]), 4) for q, k in enumerate(keys[:2])}
+    out["iso_control_rel"] = ctl
     return out
 
 
