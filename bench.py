@@ -592,6 +592,23 @@ def main():
                 bytes_per_particle_step=b_step, launches=res["launches"],
                 avg_launch_ms=round(res["kernel_ms"] / max(res["launches"], 1), 4),
                 algo_bytes_per_launch=round(per_launch_bytes))
+    # the bandwidth a plain device copy reaches on this GPU, next to the
+    # nominal peak: 4 GiB read + 4 GiB written per copy
+    src = torch.empty(2 ** 29, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 8 / (c0.elapsed_time(c1) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    roof["measured_copy_GBs"] = round(copy_gbs, 1)
+    roof["frac_of_measured_copy"] = round(achieved / copy_gbs, 4)
 
     extra = {}
     if not args.no_stream:
