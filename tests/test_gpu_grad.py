@@ -327,3 +327,26 @@ def test_absorbing_layer_gradient_matches_differences(F, torch_cuda, orc):
         for k in range(3):
             assert abs(g_dev[k] - g_fd[k]) <= 0.05 * abs(g_fd[k]), (k, g_dev[k], g_fd[k])
     sim.close()
+
+
+def test_kink_term_moves_only_tangents(F, torch_cuda):
+    """kink_sigma adds Eq. 5's mu = 0 term to the tangents only: positions and
+    weights are bit-identical, J and the injection-index derivative equal to
+    the rounding of their atomic sums, the lambda and kappa-ratio derivatives
+    move."""
+    p, g, inj, raw, injs = grad_case()
+    a = gpu_grad_run(F, torch_cuda, p, g, raw, injs, N_STEPS)
+    b = gpu_grad_run(F, torch_cuda, dict(p, kink_sigma=0.03), g, raw, injs, N_STEPS)
+    a["sim"].close()
+    b["sim"].close()
+    oa, ob = np.argsort(a["parts"]["pid"]), np.argsort(b["parts"]["pid"])
+    for k in ("pid", "x", "mu", "lnp", "w", "status"):
+        assert np.array_equal(a["parts"][k][oa], b["parts"][k][ob]), k
+    sj = np.abs(a["J"]).max()
+    assert np.allclose(a["J"], b["J"], rtol=1e-12, atol=1e-14 * sj)       # atomic summation order
+    sg = np.abs(a["dJ"][2]).max()
+    assert np.allclose(a["dJ"][2], b["dJ"][2], rtol=1e-11, atol=1e-13 * sg)
+    assert np.array_equal(a["tan"][oa][:, 10], b["tan"][ob][:, 10])
+    moved = np.abs(a["tan"][oa][:, :10] - b["tan"][ob][:, :10]).max(axis=1) > 0
+    assert moved.sum() > 50
+    assert not np.allclose(a["dJ"][:2], b["dJ"][:2], rtol=1e-6, atol=0)
