@@ -588,7 +588,7 @@ def main():
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4),
                 traffic=read_traffic("k_step_cir_traffic.txt", per_launch_bytes),
-                kernel="k_step<float,false,0,false,false,true>" if args.precision == "mixed" else "k_step<double,false,0,false,false,true>",
+                kernel="k_step<float,false,0,false,false,true,false>" if args.precision == "mixed" else "k_step<double,false,0,false,false,true,false>",
                 bytes_per_particle_step=b_step, launches=res["launches"],
                 avg_launch_ms=round(res["kernel_ms"] / max(res["launches"], 1), 4),
                 algo_bytes_per_launch=round(per_launch_bytes))

@@ -775,7 +775,7 @@ constexpr int step_wpe_max() {
     return TS2 ? 2 : 8;
 }
 
-template <typename R, bool KPERP, int MODE, bool LIDX, bool LAYER, bool TS2>
+template <typename R, bool KPERP, int MODE, bool LIDX, bool LAYER, bool TS2, bool ENS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R, MODE>(), step_wpe_max<TS2>()))) void k_step(DevParams P, DevGrid G, DevState st, DevTan tn, DevCounters *cnt,
                                               int slot, double *hist, double *sm, uint64_t n0, uint32_t n_steps,
                                               StepLds LD) {
@@ -813,7 +813,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
         int run_r = 0, run_id = P.run_id;
         double lam_ref = P.lambda_ref, kratio = P.kperp_ratio;
         uint64_t step_end = ~0ull;
-        if (P.n_runs > 0) {
+        if constexpr (ENS) {
             run_r = st.run[i];
             const DevRun rr = P.runs[run_r];
             lam_ref = rr.lambda_ref;
@@ -1282,20 +1282,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
 // waves per SIMD instead of 3 on the float path) pays for itself: +15% on the
 // CIR workload, +10% on the kappa_perp ensemble, even on the largest workload,
 // +2% on the double path (already at 2 waves).  The tangent kernels gather
-// through their own path.
+// through their own path.  Per-particle run parameters (ENS) only for
+// ensembles: a single run's stay uniform, which frees vector registers (+6%
+// on the double path).
+template <typename R, bool KPERP, int MODE, bool LIDX, bool LAYER, bool TS2>
+static void launch_step_e(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
+                          double *hist, double *sm, uint64_t n0, uint32_t n_steps, dim3 grid, dim3 blk, StepLds ld,
+                          size_t shmem, hipStream_t s) {
+    // ensembles (histogram mode only) read each particle's run parameters; a
+    // single run keeps them uniform, in scalar registers
+    if constexpr (MODE == 0) {
+        if (p.n_runs > 0) {
+            hipLaunchKernelGGL((k_step<R, KPERP, MODE, LIDX, LAYER, TS2, true>), grid, blk, shmem, s, p, g, st, tn,
+                               cnt, slot, hist, sm, n0, n_steps, ld);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_step<R, KPERP, MODE, LIDX, LAYER, TS2, false>), grid, blk, shmem, s, p, g, st, tn, cnt,
+                       slot, hist, sm, n0, n_steps, ld);
+}
+
 template <typename R, bool KPERP, int MODE, bool LIDX, bool LAYER>
 static void launch_step_ts(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
                            double *hist, double *sm, uint64_t n0, uint32_t n_steps, dim3 grid, dim3 blk, StepLds ld,
                            size_t shmem, hipStream_t s) {
     if constexpr (MODE < 2) {
         if (g.n_snap >= 2) {
-            hipLaunchKernelGGL((k_step<R, KPERP, MODE, LIDX, LAYER, true>), grid, blk, shmem, s, p, g, st, tn, cnt,
-                               slot, hist, sm, n0, n_steps, ld);
+            launch_step_e<R, KPERP, MODE, LIDX, LAYER, true>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid,
+                                                             blk, ld, shmem, s);
             return;
         }
     }
-    hipLaunchKernelGGL((k_step<R, KPERP, MODE, LIDX, LAYER, false>), grid, blk, shmem, s, p, g, st, tn, cnt, slot,
-                       hist, sm, n0, n_steps, ld);
+    launch_step_e<R, KPERP, MODE, LIDX, LAYER, false>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld,
+                                                      shmem, s);
 }
 
 template <typename R, bool KPERP, int MODE>
