@@ -550,6 +550,7 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--grad-seeds", type=int, default=4, help="seeds of the gradient-vs-differences check")
     ap.add_argument("--no-largest", action="store_true", help="skip the largest workload (first 24 h)")
+    ap.add_argument("--largest-hours", type=float, default=24.0, help="hours of the largest workload to time")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble workload")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's CIR experiment at 1-3 AMR levels")
     ap.add_argument("--no-stream", action="store_true", help="skip the snapshot-streaming run of the CIR workload")
@@ -673,7 +674,7 @@ def main():
 
     if not args.no_largest:
         log("largest workload: shocked CIR, 3 levels, 96 snapshots, 10^8-particle store, first 24 h")
-        extra["largest"] = largest_leg(F, W, args)
+        extra["largest"] = largest_leg(F, W, args, hours=args.largest_hours)
 
     cpu = None
     if not args.no_cpu:
