@@ -347,8 +347,8 @@ def largest_leg(F, W, args, hours=24):
     r = Run(F, c, raw, args.precision, args.block, args.spl, args.compact, args.sort)
     del raw
     torch.cuda.empty_cache()
-    n_steps = int(hours * 3600 / c["params"]["dt"])
     chunk = 576
+    n_steps = int(hours * 3600 / c["params"]["dt"]) // chunk * chunk
     res = timed(r, n_steps // chunk, chunk)
     st = res["stats"]
     sz = F.fte_query_sizes(r.p, g, c["n_particles"])
