@@ -181,3 +181,72 @@ def test_kappa_par_gradient(F, torch_cuda, model, eps, kink):
     if kink > 0:
         k0, s0 = res[0.0]
         assert k0 < 0.8, (k0, s0)          # without the term the estimate falls well short
+
+
+@pytest.mark.parametrize("rr,lo,hi", [(3.0, 4.35, 5.0), (2.0, 5.6, 6.8)])
+def test_shock_acceleration_index(F, torch_cuda, rr, lo, hi):
+    """First-order Fermi acceleration at a parallel shock on the GPU path: a
+    radial wind jumping from U1 to U1/rr over a width 0.02 kappa/U1 at 20 au
+    (where the shell is planar on the diffusion scale kappa/U2 = 0.13 au and
+    the radial field's focusing length r/2 is 75 times larger), protons of
+    v = 20 U1 injected at the shock with kappa independent of p.  The
+    time-integrated spectrum just downstream follows f ~ p^-q with
+    q = 3 rr / (rr - 1), 4.5 for rr = 3 and 6 for rr = 2 (the oracle's own pin
+    measures ~4.7 and ~6.2 at v = 20 U1: the focused-transport spectrum is
+    steeper by O(U1/v), so the bars are those of the oracle's pin).  The
+    observer sums w v dt per ln E bin, so for E ~ p^2 they grow as p^(4 - q)."""
+    torch = torch_cuda
+    U1 = 4e5
+    U2 = U1 / rr
+    v0 = 20 * U1
+    P0 = v0 / W.C_LIGHT / math.sqrt(1 - (v0 / W.C_LIGHT) ** 2)
+    lam = 1e9
+    kap = v0 * lam / 3
+    w = 0.02 * kap / U1
+    dt = min(0.04 * lam / v0, w / (3 * v0))
+    tacc = 18 * kap / U1 ** 2
+    n_steps = int(6 * tacc / dt)
+    L = kap / U2
+    r_s = 20 * AU
+    up, down = 0.3 * AU, 1.0 * AU
+    dxi = w / 4
+    n_r = int(math.ceil((up + down) / dxi / 16)) * 16
+    d = 1e-3
+    n1, bx = (n_r, 4, 4), (16, 4, 4)
+    g = W.grid_desc(0, r_s - up, dxi, 90 * DEG - 2 * d, d, 0.0, d, n1, bx, W.uniform_leaves(n1, bx), 1,
+                    n_snap=1, phi_periodic=False)
+
+    def wind(r, th, ph, t):
+        z = r * 0.0
+        V = U1 + (U2 - U1) * 0.5 * (1.0 + np.tanh((r - r_s) / w))
+        return np.stack([V, z, z, 5e-9 * (r_s / r) ** 2, z, z], axis=-1)
+
+    raw = W.make_raw(g, wind)
+    E0 = W.M_P * W.C_LIGHT ** 2 * (math.sqrt(1 + P0 * P0) - 1)
+    n_e = 40
+    p = dict(mass=W.M_P, dmm_model="iso", dmm_norm=0, lambda_ref=lam, alpha=-1.0, p_ref=P0, kperp_ratio=0.0,
+             dt=dt, r_in=r_s - up, r_out=r_s + down, seed=11, run_id=0, precision="mixed",
+             observers=[(r_s + 5 * w + 0.5 * L, 90 * DEG, 2 * d, L, 4 * d, 4 * d)],
+             e_min=E0, dlne=2 * math.log(4) / n_e, n_e=n_e, t_ref=0.0, dT=(n_steps + 10) * dt, n_t=1, n_batch=8)
+    N = 200000
+    inj = dict(r=r_s, th_lo=90 * DEG, th_hi=90 * DEG, ph_lo=2 * d, ph_hi=2 * d, e_lo=E0, e_hi=E0, gamma_inj=1.0,
+               w0=1.0, pid0=0, n_total=N, k0=0, n_inj_steps=0)
+    sim = F.Simulation(p, g, N)
+    sim.load_grid(raw)
+    sim.inject(inj, N, 0)
+    left = n_steps
+    while left > 0:
+        k = min(20000, left)
+        sim.step(k)
+        left -= k
+    torch.cuda.synchronize()
+    sums, _ = sim.read_hist()
+    sim.close()
+    H = sums.reshape(n_e, -1).sum(axis=1)
+    lnp = 0.5 * (np.arange(n_e) + 0.5) * p["dlne"]      # ln(p / p0) at the bin centres, E ~ p^2
+    m = (lnp > math.log(1.15)) & (lnp < math.log(2.0)) & (H > 0)
+    assert m.sum() > 10
+    slope = np.polyfit(lnp[m], np.log(H[m]), 1, w=np.sqrt(H[m] / H[m].max()))[0]
+    q = 4.0 - slope
+    print("shock compression", rr, "steps", n_steps, "index q", q)
+    assert lo < q < hi, q
