@@ -250,3 +250,52 @@ def test_shock_acceleration_index(F, torch_cuda, rr, lo, hi):
     q = 4.0 - slope
     print("shock compression", rr, "steps", n_steps, "index q", q)
     assert lo < q < hi, q
+
+
+def test_focusing_invariant_converges(F, torch_cuda):
+    """Scatter-free focusing in a radial field B ~ r^-2 with no flow conserves
+    the magnetic moment, (1 - mu^2) r^2 along each trajectory (through the
+    mirror points of the inward-moving particles).  The HIP path keeps it to
+    the order of the Euler-Maruyama step: the drift falls by half when dt
+    halves."""
+    torch = torch_cuda
+    # fine angular cells: the derived div b takes central differences of the
+    # Cartesian b across cells, whose relative error is ~ (cell angle)^2 / 6
+    # (2.5% in the phi part at 22.5 deg cells, 3e-5 here)
+    n1, bx = (128, 16, 16), (16, 16, 16)
+    g = W.grid_desc(1, 0.1 * AU, math.log(20.0) / 128, 80 * DEG, 20 * DEG / 16, 0.4, 0.2 / 16, n1, bx,
+                    W.uniform_leaves(n1, bx), 1, n_snap=1, phi_periodic=False)
+
+    def wind(r, th, ph, t):
+        z = r * 0.0
+        return np.stack([z, z, z, 5e-9 * (AU / r) ** 2, z, z], axis=-1)
+
+    raw = W.make_raw(g, wind)
+    N = 2000
+    inj = dict(r=0.2 * AU, th_lo=90 * DEG, th_hi=90 * DEG, ph_lo=0.5, ph_hi=0.5, e_lo=E100, e_hi=E100,
+               gamma_inj=1.0, w0=1.0, pid0=0, n_total=N, k0=0, n_inj_steps=0)
+    drift = []
+    for dt in (2.0, 1.0):
+        p = dict(mass=W.M_P, dmm_model="iso", dmm_norm=0, lambda_ref=1e30, kperp_ratio=0.0, dt=dt,
+                 r_in=0.1 * AU, r_out=2 * AU, seed=3, run_id=0, precision="fp64", observers=[], n_batch=1)
+        sim = F.Simulation(p, g, N)
+        sim.load_grid(raw)
+        sim.inject(inj, N, 0)
+        a = sim.particles()
+        sim.step(int(round(20000 / dt)))
+        b = sim.particles()
+        torch.cuda.synchronize()
+        sim.close()
+        # inward particles with |mu0| > 0.87 mirror only below r_in and are
+        # absorbed (and compacted away); the others are all still held
+        pos = {int(q): i for i, q in enumerate(a["pid"])}
+        keep = b["status"] == 0
+        ia = np.array([pos[int(q)] for q in b["pid"][keep]])
+        assert len(ia) > 0.85 * N
+        inv0 = (1 - a["mu"][ia] ** 2) * np.sum(a["x"][ia] ** 2, axis=1)
+        inv1 = (1 - b["mu"][keep] ** 2) * np.sum(b["x"][keep] ** 2, axis=1)
+        assert np.linalg.norm(b["x"][keep], axis=1).max() > 0.6 * AU   # the outward particles went far
+        drift.append(np.median(np.abs(inv1 / inv0 - 1)))
+    print("median relative drift of (1 - mu^2) r^2 at dt = 2, 1 s:", drift)
+    assert drift[1] < 2e-3
+    assert 1.5 < drift[0] / drift[1] < 2.6, drift
