@@ -299,3 +299,45 @@ def test_focusing_invariant_converges(F, torch_cuda):
     print("median relative drift of (1 - mu^2) r^2 at dt = 2, 1 s:", drift)
     assert drift[1] < 2e-3
     assert 1.5 < drift[0] / drift[1] < 2.6, drift
+
+
+def test_adiabatic_deceleration_radial_wind(F, torch_cuda):
+    """Particles scattered to isotropy (lambda << r) in a constant-speed radial
+    wind are carried out with it and lose momentum at the rate div V / 3 =
+    2 V / (3 r): along the flow ln p + (2/3) ln r stays constant, to
+    corrections of order kappa / (V r) (about 1% here)."""
+    torch = torch_cuda
+    n1, bx = (128, 16, 16), (16, 16, 16)
+    g = W.grid_desc(1, 0.1 * AU, math.log(20.0) / 128, 80 * DEG, 20 * DEG / 16, 0.4, 0.2 / 16, n1, bx,
+                    W.uniform_leaves(n1, bx), 1, n_snap=1, phi_periodic=False)
+    V = 4e5
+
+    def wind(r, th, ph, t):
+        z = r * 0.0
+        return np.stack([z + V, z, z, 5e-9 * (AU / r) ** 2, z, z], axis=-1)
+
+    raw = W.make_raw(g, wind)
+    N = 20000
+    lam = 1e8
+    dt = 0.5
+    p = dict(mass=W.M_P, dmm_model="iso", dmm_norm=0, lambda_ref=lam, kperp_ratio=0.0, dt=dt,
+             r_in=0.1 * AU, r_out=2 * AU, seed=5, run_id=0, precision="fp64", observers=[], n_batch=1)
+    inj = dict(r=0.2 * AU, th_lo=90 * DEG, th_hi=90 * DEG, ph_lo=0.5, ph_hi=0.5, e_lo=E100, e_hi=E100,
+               gamma_inj=1.0, w0=1.0, pid0=0, n_total=N, k0=0, n_inj_steps=0)
+    sim = F.Simulation(p, g, N)
+    sim.load_grid(raw)
+    sim.inject(inj, N, 0)
+    a = sim.particles()
+    sim.step(int(2e5 / dt))
+    b = sim.particles()
+    torch.cuda.synchronize()
+    sim.close()
+    assert np.all(b["status"] == 0) and len(b["pid"]) == N
+    oa, ob = np.argsort(a["pid"]), np.argsort(b["pid"])
+    ra = np.linalg.norm(a["x"][oa], axis=1)
+    rb = np.linalg.norm(b["x"][ob], axis=1)
+    change = np.mean(np.log(rb / ra))
+    resid = np.mean(b["lnp"][ob] - a["lnp"][oa] + (2.0 / 3.0) * np.log(rb / ra))
+    print("mean ln(r/r0)", change, "mean of dln p + (2/3) dln r", resid)
+    assert change > 0.9                                  # carried out by a factor > 2.5
+    assert abs(resid) < 0.03 * (2.0 / 3.0) * change, (resid, change)
