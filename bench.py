@@ -128,7 +128,8 @@ def gradient_leg(F, W, raw, args):
     + derivative sums), each over the whole run.  Then the gradient of the
     summed intensity against central differences (h = 1e-3 and 1e-2, common
     random numbers) of the smoothed forward pass on the GPU, for several seeds, with
-    the tangents' mu = 0 term of Eq. 5 (kink_sigma) and without it: the mean
+    the tangents' mu = 0 term of Eq. 5 (kink_sigma: a Gaussian of that width,
+    or, negative, the bridge occupation of mu = 0) and without it: the mean
     over seeds of gradient minus difference, relative to the mean difference,
     with its standard error."""
     import torch
@@ -179,11 +180,11 @@ def gradient_leg(F, W, raw, args):
 
     keys = ("lambda_ref", "kperp_ratio", "gamma_inj")
     steps_h = (1e-3, 1e-2)
-    rows = {"kink": [], "no_kink": []}
+    rows = {"kink": [], "bridge": [], "no_kink": []}
     fds = {h: [] for h in steps_h}
     for seed in range(args.grad_seeds):
         ps = dict(p_grad, seed=seed)
-        for name, ks in (("kink", p_grad["kink_sigma"]), ("no_kink", 0.0)):
+        for name, ks in (("kink", p_grad["kink_sigma"]), ("bridge", -1.0), ("no_kink", 0.0)):
             rr = full(dict(ps, kink_sigma=ks))
             Js, _ = rr.sim.bin_smoothed()
             rows[name].append(rr.sim.grad_of(np.ones(Js.shape)))
@@ -203,7 +204,8 @@ def gradient_leg(F, W, raw, args):
                     rr.close()
                 fd.append((Jpm[0] - Jpm[1]) / (2 * h * base))
             fds[h].append(np.array(fd))
-        log(f"  gradient seed {seed}: kink {rows['kink'][-1]}, no kink {rows['no_kink'][-1]}, "
+        log(f"  gradient seed {seed}: kink {rows['kink'][-1]}, bridge {rows['bridge'][-1]}, "
+            f"no kink {rows['no_kink'][-1]}, "
             f"fd {[list(fds[h][-1]) for h in steps_h]}")
     out["fd_seeds"] = args.grad_seeds
     for h in steps_h:
@@ -211,7 +213,7 @@ def gradient_leg(F, W, raw, args):
         m = fd.mean(axis=0)
         tag = f"h{h:g}"
         out[f"fd_mean_{tag}"] = [float(v) for v in m]
-        for name in ("kink", "no_kink"):
+        for name in ("kink", "bridge", "no_kink"):
             g = np.array(rows[name])
             d = g - fd
             # rel: mean over seeds of (gradient - difference) relative to the

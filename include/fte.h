@@ -171,8 +171,10 @@ typedef struct {
      * (a.e. d2D/dmu2 has no Dirac term).  kink_sigma > 0 adds to the
      * tangents' d2D/dmu2 the term 2A G(mu), G a normalised Gaussian of that
      * width standing for the Dirac (the local time at mu = 0 of the
-     * continuous process); 0: the tangents are the exact derivatives of each
-     * sampled path.  Trajectories are unchanged either way.                   */
+     * continuous process); kink_sigma < 0 weights it by the time each step is
+     * expected to spend at mu = 0 given its end points (a Brownian bridge with
+     * the diffusion at mu = 0), no width; 0: the tangents are the exact
+     * derivatives of each sampled path.  Trajectories are unchanged.          */
     double kink_sigma;
 } fte_params;
 

@@ -154,7 +154,7 @@ std::string check_params(const fte_params *p) {
     if (!(p->absorb_layer >= 0.0) || !isfinite(p->absorb_layer) || !(p->absorb_rate >= 0.0) ||
         !isfinite(p->absorb_rate))
         return "absorb_layer and absorb_rate must be finite and >= 0";
-    if (!(p->kink_sigma >= 0.0) || !isfinite(p->kink_sigma)) return "kink_sigma must be finite and >= 0";
+    if (!isfinite(p->kink_sigma)) return "kink_sigma must be finite";
     if (p->grad != 0 && p->grad != 1) return "grad must be 0 or 1";
     if (p->grad && !(p->sigma_x > 0.0)) return "the gradient needs the smoothed intensities (sigma_x > 0)";
     if (p->sigma_x > 0.0) {
@@ -384,6 +384,7 @@ void make_devparams(const fte_params *p, DevParams *d) {
         d->kink_norm = 2.0 / (sqrt(2.0 * kPi) * p->kink_sigma);
         d->kink_inv_2s2 = 1.0 / (2.0 * p->kink_sigma * p->kink_sigma);
     }
+    if (p->grad && p->dmm_model == FTE_DMM_EQ5 && p->kink_sigma < 0.0) d->kink_bridge = 1;
     if (p->absorb_layer > 0.0 && p->absorb_rate > 0.0) {
         d->layer_k0dt = p->absorb_rate * p->dt;
         d->layer_inv_h = 1.0 / p->absorb_layer;

@@ -60,6 +60,7 @@ struct DevParams {
     double layer_k0dt;       // absorbing layers: peak decay per step k0 dt (0: off)
     double layer_inv_h;      // 1 / layer width
     double kink_norm, kink_inv_2s2;   // tangents: 2 / (sqrt(2 pi) s), 1 / (2 s^2) (0: off)
+    int kink_bridge;                  // tangents: the bridge occupation at mu = 0 instead
     uint64_t seed;
     int dmm_model;
     int run_id;

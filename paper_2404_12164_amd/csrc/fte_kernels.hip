@@ -742,6 +742,30 @@ __device__ __forceinline__ R cos_colat(double z, R r) {
     else return M<float>::div_((float)z, r);
 }
 
+// erfc(z) exp(z^2) for z >= 0.
+template <typename R>
+__device__ __forceinline__ R erfcx_pos(R z) {
+    if (z < (R)8) {
+        if constexpr (std::is_same<R, float>::value) return __expf(z * z) * erfcf(z);
+        else return ::exp(z * z) * ::erfc(z);
+    }
+    const R t = M<R>::div_((R)1, z * z);
+    return M<R>::div_((R)1, z * (R)1.7724538509055160273) * ((R)1 - (R)0.5 * t + (R)0.75 * t * t - (R)1.875 * t * t * t);
+}
+
+// Expected time a Brownian bridge of diffusion s2 (variance s2 h after a time
+// h) from a to b spends per unit length at 0: the convolution of the two free
+// densities through 0 over the bridge density,
+// sqrt(2 pi h) / (2 s) erfcx((|a| + |b|) / (s sqrt(2 h))) exp(-(a b + |a b|) / (s2 h)).
+template <typename R>
+__device__ __forceinline__ R bridge_occupation(R a, R b, R s2, R h) {
+    const R s = M<R>::sqrt_(s2);
+    const R aa = a < (R)0 ? -a : a, ab = b < (R)0 ? -b : b;
+    const R z = M<R>::div_(aa + ab, s * M<R>::sqrt_((R)2 * h));
+    const R e = M<R>::exp_(-M<R>::div_(a * b + aa * ab, s2 * h));
+    return M<R>::div_(M<R>::sqrt_((R)6.283185307179586477 * h), (R)2 * s) * erfcx_pos<R>(z) * e;
+}
+
 // MODE 0: histogram estimator only.  MODE 1: also the kernel-smoothed sums.
 // MODE 2: also the pathwise tangents d(x, mu, ln p)/d(lambda_ref,
 // kperp_ratio), propagated by the derivative of the same Euler-Maruyama map
@@ -1013,6 +1037,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
             }
             const R nmu = M<R>::sqrt_((R)2 * D * dt) * z0;
             R mun = mu + a_mu * dt + nmu;
+            const R mu_end = mun;     // before any reflection
             R flip = (R)1;
             if (mun > (R)1) {
                 mun = (R)2 - mun;
@@ -1036,6 +1061,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                 // Gaussian of width kink_sigma stands for it
                 if (P.kink_norm > 0.0)
                     g2 += (R)P.kink_norm * M<R>::exp_(-mu * mu * (R)P.kink_inv_2s2);
+                // with kink_bridge the Dirac term is weighted instead by the
+                // time the step is expected to spend at mu = 0 given its end
+                // points (a Brownian bridge with the diffusion 2 D(0) of mu = 0)
+                R kink_step = (R)0;
+                if (P.kink_bridge) kink_step = (R)2 * A * bridge_occupation<R>(mu, mu_end, (R)2 * A * (R)P.eps, dt);
                 const R iv = M<R>::div_((R)1, v);
                 const R halfD = D > (R)0 ? M<R>::div_(nmu, (R)2 * D) : (R)0;   // d noise / d D
 #pragma unroll
@@ -1079,7 +1109,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                     }
 #pragma unroll
                     for (int a = 0; a < 3; ++a) TX[k][a] += dax[a] * dt + dnx[a];
-                    TM[k] = flip * (dm + damu * dt + halfD * dD_);
+                    TM[k] = flip * (dm + damu * dt + halfD * dD_ + kink_step * dm);
                     TL[k] = dl + dalnp * dt;
                 }
             }

@@ -148,7 +148,8 @@ def test_kappa_par_eq5_and_kappa_perp(F, torch_cuda):
     assert abs(dxy2.mean() - want) < 4 * dxy2.std() / math.sqrt(N), (dxy2.mean(), want)
 
 
-@pytest.mark.parametrize("model,eps,kink", [("iso", 0.0, 0.0), ("eq5", 1.0, 0.03)])
+@pytest.mark.parametrize("model,eps,kink", [("iso", 0.0, 0.0), ("eq5", 1.0, 0.03), ("eq5", 1.0, -1.0),
+                                            ("eq5", 0.3, -1.0)])
 def test_kappa_par_gradient(F, torch_cuda, model, eps, kink):
     """The tangents against d kappa_par / d lambda = v / 3: the slope of
     <z^2> between late times is 2 kappa_par, so the slope of
@@ -158,7 +159,8 @@ def test_kappa_par_gradient(F, torch_cuda, model, eps, kink):
     eps = 0.048 the tangent's multiplicative noise near mu = 0, of relative
     size sqrt(A dt / (2 eps)) per step, makes the Gaussian stand-in of the
     Dirac either biased, width 0.03, or heavy-tailed, narrower; eps = 1 pins
-    the term itself.)"""
+    the term itself.)  kink_sigma < 0 weights the Dirac by the bridge
+    occupation of mu = 0 over each step instead, with no width to choose."""
     lam = 3e8
     I = _eq5_integral(eps) if model == "eq5" else 4.0 / 3.0
     A = 3 * V100 * I / (8 * lam)
@@ -178,7 +180,7 @@ def test_kappa_par_gradient(F, torch_cuda, model, eps, kink):
         print(model, "eps", eps, "kink_sigma", ks, "d kappa / d lambda over v/3:", res[ks])
     k, s_ = res[kink]
     assert abs(k - 1) < 4 * s_ + 0.04, (k, s_)
-    if kink > 0:
+    if kink != 0:
         k0, s0 = res[0.0]
         assert k0 < 0.8, (k0, s0)          # without the term the estimate falls well short
 
