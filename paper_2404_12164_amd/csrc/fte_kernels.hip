@@ -742,10 +742,11 @@ __device__ __forceinline__ R cos_colat(double z, R r) {
     else return M<float>::div_((float)z, r);
 }
 
-// erfc(z) exp(z^2) for z >= 0.
+// erfc(z) exp(z^2) for z >= 0: directly while erfc(z) stays a normal number,
+// beyond that the asymptotic series to z^-7 (relative error below 7 z^-8).
 template <typename R>
 __device__ __forceinline__ R erfcx_pos(R z) {
-    if (z < (R)8) {
+    if (z < (std::is_same<R, float>::value ? (R)8 : (R)26)) {
         if constexpr (std::is_same<R, float>::value) return __expf(z * z) * erfcf(z);
         else return ::exp(z * z) * ::erfc(z);
     }
