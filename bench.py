@@ -38,7 +38,7 @@ def kernel_source_hash():
 
 def read_traffic(name, algo_bytes_per_launch):
     """HBM bytes per step-kernel launch from the committed counter summary,
-    if it was taken on the current kernel source."""
+    if it was taken on the current kernel source and the same run shape."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -50,6 +50,11 @@ def read_traffic(name, algo_bytes_per_launch):
     if kv.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     try:
+        # only for the workload and launch shape the counters were taken on:
+        # the same algorithmic bytes per launch
+        ref = float(kv["bench_algo_bytes_per_launch"])
+        if abs(algo_bytes_per_launch - ref) > 0.01 * ref:
+            return None
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
@@ -621,7 +626,8 @@ def main():
     per_launch_bytes = b_step * res["particle_steps"] / max(res["launches"], 1)
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4),
-                traffic=read_traffic("k_step_cir_traffic.txt", per_launch_bytes),
+                # the committed counters are those of the float kernel
+                traffic=read_traffic("k_step_cir_traffic.txt", per_launch_bytes) if args.precision == "mixed" else None,
                 kernel="k_step<float,false,0,false,false,true,false>" if args.precision == "mixed" else "k_step<double,false,0,false,false,true,false>",
                 bytes_per_particle_step=b_step, launches=res["launches"],
                 avg_launch_ms=round(res["kernel_ms"] / max(res["launches"], 1), 4),
