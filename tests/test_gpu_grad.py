@@ -217,11 +217,14 @@ def test_gradient_launch_shape_invariance(F, torch_cuda):
     assert np.allclose(a["dJ"], b["dJ"], rtol=1e-11, atol=1e-12 * scale)
 
 
-def test_mixed_precision_gradient(F, torch_cuda):
+@pytest.mark.parametrize("kink", [0.0, -1.0])
+def test_mixed_precision_gradient(F, torch_cuda, kink):
     """The mixed path's gradient of the summed intensity against the FP64
     path's, same particles: within 5% (float step arithmetic moves each
-    trajectory by rounding only)."""
+    trajectory by rounding only); also with the bridge term of Eq. 5's
+    mu = 0 kink, whose float and double evaluations differ in their erfcx."""
     p, g, inj, raw, injs = grad_case()
+    p = dict(p, kink_sigma=kink)
     a = gpu_grad_run(F, torch_cuda, p, g, raw, injs, N_STEPS)
     b = gpu_grad_run(F, torch_cuda, dict(p, precision="mixed"), g, raw, injs, N_STEPS)
     for wts in _losses(a["J"].shape)[:2]:
@@ -329,14 +332,16 @@ def test_absorbing_layer_gradient_matches_differences(F, torch_cuda, orc):
     sim.close()
 
 
-def test_kink_term_moves_only_tangents(F, torch_cuda):
-    """kink_sigma adds Eq. 5's mu = 0 term to the tangents only: positions and
+@pytest.mark.parametrize("kink", [0.03, -1.0])
+def test_kink_term_moves_only_tangents(F, torch_cuda, kink):
+    """kink_sigma adds Eq. 5's mu = 0 term to the tangents only (a Gaussian of
+    that width, or, negative, the bridge occupation of mu = 0): positions and
     weights are bit-identical, J and the injection-index derivative equal to
     the rounding of their atomic sums, the lambda and kappa-ratio derivatives
     move."""
     p, g, inj, raw, injs = grad_case()
     a = gpu_grad_run(F, torch_cuda, p, g, raw, injs, N_STEPS)
-    b = gpu_grad_run(F, torch_cuda, dict(p, kink_sigma=0.03), g, raw, injs, N_STEPS)
+    b = gpu_grad_run(F, torch_cuda, dict(p, kink_sigma=kink), g, raw, injs, N_STEPS)
     a["sim"].close()
     b["sim"].close()
     oa, ob = np.argsort(a["parts"]["pid"]), np.argsort(b["parts"]["pid"])
