@@ -36,9 +36,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(name, algo_bytes_per_launch):
-    """HBM bytes per step-kernel launch from the committed counter summary,
-    if it was taken on the current kernel source and the same run shape."""
+def read_counters(name, algo_bytes_per_launch, key):
+    """A per-launch figure of the step kernel (``key``) from the committed
+    counter summary, if it was taken on the current kernel source and the
+    same run shape."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -55,9 +56,31 @@ def read_traffic(name, algo_bytes_per_launch):
         ref = float(kv["bench_algo_bytes_per_launch"])
         if abs(algo_bytes_per_launch - ref) > 0.01 * ref:
             return None
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
+
+
+def read_traffic(name, algo_bytes_per_launch):
+    """HBM bytes per step-kernel launch (calibrated FETCH_SIZE + WRITE_SIZE)."""
+    return read_counters(name, algo_bytes_per_launch, "hbm_bytes_per_launch")
+
+
+def l1_probe():
+    """Lines per CU per ns that the vector L1 looks up when every lane of a
+    load touches its own line (libl1probe.so, built beside the library), and
+    the CU count; None if the probe is not built."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2404_12164_amd", "libl1probe.so")
+    if not os.path.exists(path):
+        log("l1 probe not built")
+        return None
+    lib = ctypes.CDLL(path)
+    rate, ncu = ctypes.c_double(0), ctypes.c_int(0)
+    rc = lib.l1_probe_lines_per_ns(ctypes.byref(rate), ctypes.byref(ncu))
+    if rc != 0:
+        raise RuntimeError(f"l1 probe failed with HIP error {rc}")
+    return rate.value, ncu.value
 
 
 class Run:
@@ -632,6 +655,20 @@ def main():
                 bytes_per_particle_step=b_step, launches=res["launches"],
                 avg_launch_ms=round(res["kernel_ms"] / max(res["launches"], 1), 4),
                 algo_bytes_per_launch=round(per_launch_bytes))
+    # the gather's binding limit: L1 line lookups (committed TCP counters of
+    # the same run shape) per CU and ns of step-kernel time, against what the
+    # L1 sustains for fully divergent loads on this GPU, measured now
+    probe = l1_probe()
+    lookups = (read_counters("k_step_cir_traffic.txt", per_launch_bytes, "tcp_lookups_per_launch")
+               if args.precision == "mixed" else None)
+    if probe is not None:
+        ceil, ncu = probe
+        l1 = dict(unit="lines/CU/ns", peak_measured=round(ceil, 4), lookups_per_launch=lookups)
+        if lookups is not None:
+            ach = lookups * res["launches"] / ncu / (kernel_s * 1e9)
+            l1.update(achieved=round(ach, 4), frac=round(ach / ceil, 4),
+                      lookups_per_particle_step=round(lookups * res["launches"] / res["particle_steps"], 2))
+        roof["l1"] = l1
     # the bandwidth a plain device copy reaches on this GPU, next to the
     # nominal peak: 4 GiB read + 4 GiB written per copy
     src = torch.empty(2 ** 29, dtype=torch.float64, device=dev)
