@@ -67,20 +67,21 @@ def read_traffic(name, algo_bytes_per_launch):
 
 
 def l1_probe():
-    """Lines per CU per ns that the vector L1 looks up when every lane of a
-    load touches its own line (libl1probe.so, built beside the library), and
-    the CU count; None if the probe is not built."""
+    """What the vector L1 sustains for the step kernel's gather pattern when
+    every access hits in it (libl1probe.so, built beside the library): record
+    pairs and, for fully divergent 16-byte loads, cache lines per CU per ns,
+    and the CU count; None if the probe is not built."""
     import ctypes
     path = os.path.join(ROOT, "paper_2404_12164_amd", "libl1probe.so")
     if not os.path.exists(path):
         log("l1 probe not built")
         return None
     lib = ctypes.CDLL(path)
-    rate, ncu = ctypes.c_double(0), ctypes.c_int(0)
-    rc = lib.l1_probe_lines_per_ns(ctypes.byref(rate), ctypes.byref(ncu))
+    pairs, lines, ncu = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_int(0)
+    rc = lib.l1_probe_rates(ctypes.byref(pairs), ctypes.byref(lines), ctypes.byref(ncu))
     if rc != 0:
         raise RuntimeError(f"l1 probe failed with HIP error {rc}")
-    return rate.value, ncu.value
+    return pairs.value, lines.value, ncu.value
 
 
 class Run:
@@ -655,19 +656,21 @@ def main():
                 bytes_per_particle_step=b_step, launches=res["launches"],
                 avg_launch_ms=round(res["kernel_ms"] / max(res["launches"], 1), 4),
                 algo_bytes_per_launch=round(per_launch_bytes))
-    # the gather's binding limit: L1 line lookups (committed TCP counters of
-    # the same run shape) per CU and ns of step-kernel time, against what the
-    # L1 sustains for fully divergent loads on this GPU, measured now
+    # the gather's on-chip limit: record pairs (80 contiguous bytes, one per
+    # corner row and snapshot: 4 T_s per particle-step) gathered per CU and ns
+    # of step-kernel time, against the rate the L1 serves the same per-lane
+    # pattern when every access hits in it, measured now on this GPU
     probe = l1_probe()
-    lookups = (read_counters("k_step_cir_traffic.txt", per_launch_bytes, "tcp_lookups_per_launch")
-               if args.precision == "mixed" else None)
     if probe is not None:
-        ceil, ncu = probe
-        l1 = dict(unit="lines/CU/ns", peak_measured=round(ceil, 4), lookups_per_launch=lookups)
+        pair_peak, line_peak, ncu = probe
+        ach = 4 * T_s * res["particle_steps"] / ncu / (kernel_s * 1e9)
+        l1 = dict(unit="record pairs/CU/ns", achieved=round(ach, 4), peak_l1_resident=round(pair_peak, 4),
+                  frac=round(ach / pair_peak, 4), pairs_per_particle_step=4 * T_s,
+                  divergent_lines_per_cu_ns=round(line_peak, 4))
+        lookups = (read_counters("k_step_cir_traffic.txt", per_launch_bytes, "tcp_lookups_per_launch")
+                   if args.precision == "mixed" else None)
         if lookups is not None:
-            ach = lookups * res["launches"] / ncu / (kernel_s * 1e9)
-            l1.update(achieved=round(ach, 4), frac=round(ach / ceil, 4),
-                      lookups_per_particle_step=round(lookups * res["launches"] / res["particle_steps"], 2))
+            l1["tcp_accesses_per_cu_ns"] = round(lookups * res["launches"] / ncu / (kernel_s * 1e9), 4)
         roof["l1"] = l1
     # the bandwidth a plain device copy reaches on this GPU, next to the
     # nominal peak: 4 GiB read + 4 GiB written per copy

@@ -1,27 +1,46 @@
-// Measurement aid, not part of the transport path: the rate at which a CU's
-// vector L1 cache processes cache-line lookups when every lane of a
-// wavefront load touches a different 128-B line, the access pattern of the
-// step kernel's corner gather.  The loads stay within a 16 KB array, so they
-// hit in L1 and only the lookup rate limits them.
+// Measurement aid, not part of the transport path: how fast a CU's vector L1
+// cache serves the step kernel's corner gather when every access hits in it.
+// The step kernel reads, per particle-step, 8 pairs of neighbouring 10-float
+// records (2 snapshots x 4 corner rows, 80 contiguous bytes at a 40-byte
+// stride each), one pair per lane, different for each lane of a wavefront.
+// The probe repeats exactly that access pattern over a 10 KB table that stays
+// resident in L1, so only the L1's handling of divergent accesses limits it.
+// A second probe loads one 16-byte vector per lane from 64 distinct 128-byte
+// lines (the L1's rate of line lookups).
 //
-//   int l1_probe_lines_per_ns(double *lines_per_cu_ns, int *n_cu)
-//     Runs the probe three times on the current device's default stream and
-//     returns, in *lines_per_cu_ns, the best rate in lines per CU per
-//     nanosecond and, in *n_cu, the device's compute-unit count.  Allocates
-//     and frees its own 16 KB and output buffers.  Returns 0, or the HIP
-//     error code of the first call that failed.
+//   int l1_probe_rates(double *pairs_per_cu_ns, double *lines_per_cu_ns, int *n_cu)
+//     Runs each probe three times on the current device's default stream and
+//     returns the best rates per compute unit and nanosecond, and the
+//     device's compute-unit count.  Allocates and frees its own buffers.
+//     Returns 0, or the HIP error code of the first call that failed.
 #include <hip/hip_runtime.h>
 
 namespace {
 
-constexpr int kLines = 128;                 // 16 KB of 128-B lines
-constexpr int kBlocks = 2048, kThreads = 256, kIters = 4096;
+constexpr int kRecords = 256;               // 10-float records: 10 KB
+constexpr int kRecFloats = 10;
+constexpr int kLines = 128;                 // 16 KB of 128-B lines for the line probe
+constexpr int kBlocks = 2048, kThreads = 256;
+constexpr int kPairIters = 1024, kLineIters = 4096;
+
+__global__ __launch_bounds__(256) void k_pair_gather(const float *__restrict__ rec, float *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    float acc = 0.f;
+    for (int it = 0; it < kPairIters; ++it) {
+        // distinct records for the 64 lanes (5 lane mod 256 is one-to-one),
+        // rotating with the iteration; records r and r + 1 are read
+        const int r = (lane * 5 + it * 3) & (kRecords - 1);
+        const float *p = rec + (size_t)r * kRecFloats;
+#pragma unroll
+        for (int q = 0; q < 2 * kRecFloats; ++q) acc += p[q];
+    }
+    out[blockIdx.x * blockDim.x + threadIdx.x] = acc;
+}
 
 __global__ __launch_bounds__(256) void k_divergent_lines(const float4 *__restrict__ a, float *__restrict__ out) {
     const int lane = threadIdx.x & 63;
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int it = 0; it < kIters; ++it) {
-        // each lane a different line, rotating so the pattern is not static
+    for (int it = 0; it < kLineIters; ++it) {
         const float4 v = a[((lane + it) & (kLines - 1)) * 8];
         acc.x += v.x;
         acc.y += v.y;
@@ -33,39 +52,47 @@ __global__ __launch_bounds__(256) void k_divergent_lines(const float4 *__restric
 
 }  // namespace
 
-extern "C" int l1_probe_lines_per_ns(double *lines_per_cu_ns, int *n_cu) {
+extern "C" int l1_probe_rates(double *pairs_per_cu_ns, double *lines_per_cu_ns, int *n_cu) {
+    *pairs_per_cu_ns = 0.0;
+    *lines_per_cu_ns = 0.0;
+    *n_cu = 0;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return (int)e;
     hipDeviceProp_t prop;
     if ((e = hipGetDeviceProperties(&prop, dev)) != hipSuccess) return (int)e;
-    float4 *a = nullptr;
+    const double ncu = prop.multiProcessorCount;
+    const size_t table_bytes = (size_t)kLines * 128;                     // covers both probes' tables
+    static_assert((kRecords + 1) * kRecFloats * 4 <= kLines * 128, "record table fits the buffer");
+    void *buf = nullptr;
     float *out = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    double best = 0.0;
-    if ((e = hipMalloc(&a, kLines * 8 * sizeof(float4))) != hipSuccess) goto done;
+    if ((e = hipMalloc(&buf, table_bytes)) != hipSuccess) goto done;
     if ((e = hipMalloc(&out, (size_t)kBlocks * kThreads * sizeof(float))) != hipSuccess) goto done;
-    if ((e = hipMemset(a, 0, kLines * 8 * sizeof(float4))) != hipSuccess) goto done;
+    if ((e = hipMemset(buf, 0, table_bytes)) != hipSuccess) goto done;
     if ((e = hipEventCreate(&e0)) != hipSuccess) goto done;
     if ((e = hipEventCreate(&e1)) != hipSuccess) goto done;
-    for (int rep = 0; rep < 3; ++rep) {
-        if ((e = hipEventRecord(e0, nullptr)) != hipSuccess) goto done;
-        k_divergent_lines<<<kBlocks, kThreads, 0, nullptr>>>(a, out);
-        if ((e = hipEventRecord(e1, nullptr)) != hipSuccess) goto done;
-        if ((e = hipEventSynchronize(e1)) != hipSuccess) goto done;
-        if ((e = hipGetLastError()) != hipSuccess) goto done;
-        float ms = 0.f;
-        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) goto done;
-        const double lines = (double)kBlocks * kThreads * kIters;   // one line per lane-load
-        const double rate = lines / prop.multiProcessorCount / (ms * 1e6);
-        if (rate > best) best = rate;
+    for (int probe = 0; probe < 2; ++probe) {
+        for (int rep = 0; rep < 3; ++rep) {
+            if ((e = hipEventRecord(e0, nullptr)) != hipSuccess) goto done;
+            if (probe == 0) k_pair_gather<<<kBlocks, kThreads, 0, nullptr>>>((const float *)buf, out);
+            else k_divergent_lines<<<kBlocks, kThreads, 0, nullptr>>>((const float4 *)buf, out);
+            if ((e = hipGetLastError()) != hipSuccess) goto done;
+            if ((e = hipEventRecord(e1, nullptr)) != hipSuccess) goto done;
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) goto done;
+            float ms = 0.f;
+            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) goto done;
+            const double n = (double)kBlocks * kThreads * (probe == 0 ? kPairIters : kLineIters);
+            const double rate = n / ncu / (ms * 1e6);
+            double *dst = probe == 0 ? pairs_per_cu_ns : lines_per_cu_ns;
+            if (rate > *dst) *dst = rate;
+        }
     }
+    *n_cu = prop.multiProcessorCount;
 done:
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    if (a) (void)hipFree(a);
+    if (buf) (void)hipFree(buf);
     if (out) (void)hipFree(out);
-    *lines_per_cu_ns = best;
-    *n_cu = prop.multiProcessorCount;
     return (int)e;
 }
