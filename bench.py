@@ -70,18 +70,19 @@ def l1_probe():
     """What the vector L1 sustains for the step kernel's gather pattern when
     every access hits in it (libl1probe.so, built beside the library): record
     pairs and, for fully divergent 16-byte loads, cache lines per CU per ns,
-    and the CU count; None if the probe is not built."""
+    the record pairs LDS serves for the same pattern, and the CU count; None
+    if the probe is not built."""
     import ctypes
     path = os.path.join(ROOT, "paper_2404_12164_amd", "libl1probe.so")
     if not os.path.exists(path):
         log("l1 probe not built")
         return None
     lib = ctypes.CDLL(path)
-    pairs, lines, ncu = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_int(0)
-    rc = lib.l1_probe_rates(ctypes.byref(pairs), ctypes.byref(lines), ctypes.byref(ncu))
+    pairs, lines, lds, ncu = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0), ctypes.c_int(0)
+    rc = lib.l1_probe_rates(ctypes.byref(pairs), ctypes.byref(lines), ctypes.byref(lds), ctypes.byref(ncu))
     if rc != 0:
         raise RuntimeError(f"l1 probe failed with HIP error {rc}")
-    return pairs.value, lines.value, ncu.value
+    return pairs.value, lines.value, lds.value, ncu.value
 
 
 class Run:
@@ -662,11 +663,11 @@ def main():
     # pattern when every access hits in it, measured now on this GPU
     probe = l1_probe()
     if probe is not None:
-        pair_peak, line_peak, ncu = probe
+        pair_peak, line_peak, lds_peak, ncu = probe
         ach = 4 * T_s * res["particle_steps"] / ncu / (kernel_s * 1e9)
         l1 = dict(unit="record pairs/CU/ns", achieved=round(ach, 4), peak_l1_resident=round(pair_peak, 4),
                   frac=round(ach / pair_peak, 4), pairs_per_particle_step=4 * T_s,
-                  divergent_lines_per_cu_ns=round(line_peak, 4))
+                  divergent_lines_per_cu_ns=round(line_peak, 4), lds_pairs_per_cu_ns=round(lds_peak, 4))
         lookups = (read_counters("k_step_cir_traffic.txt", per_launch_bytes, "tcp_lookups_per_launch")
                    if args.precision == "mixed" else None)
         if lookups is not None:

@@ -6,9 +6,11 @@
 // The probe repeats exactly that access pattern over a 10 KB table that stays
 // resident in L1, so only the L1's handling of divergent accesses limits it.
 // A second probe loads one 16-byte vector per lane from 64 distinct 128-byte
-// lines (the L1's rate of line lookups).
+// lines (the L1's rate of line lookups); a third reads the same record pairs
+// from a copy of the table in LDS (what staging records in LDS could serve).
 //
-//   int l1_probe_rates(double *pairs_per_cu_ns, double *lines_per_cu_ns, int *n_cu)
+//   int l1_probe_rates(double *pairs_per_cu_ns, double *lines_per_cu_ns,
+//                      double *lds_pairs_per_cu_ns, int *n_cu)
 //     Runs each probe three times on the current device's default stream and
 //     returns the best rates per compute unit and nanosecond, and the
 //     device's compute-unit count.  Allocates and frees its own buffers.
@@ -37,6 +39,22 @@ __global__ __launch_bounds__(256) void k_pair_gather(const float *__restrict__ r
     out[blockIdx.x * blockDim.x + threadIdx.x] = acc;
 }
 
+__global__ __launch_bounds__(256) void k_pair_gather_lds(const float *__restrict__ rec, float *__restrict__ out) {
+    constexpr int kTab = (kRecords + 1) * kRecFloats;   // record 255 reads its neighbour 256
+    __shared__ float tab[kTab];
+    for (int k = threadIdx.x; k < kTab; k += blockDim.x) tab[k] = rec[k];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    float acc = 0.f;
+    for (int it = 0; it < kPairIters; ++it) {
+        const int r = (lane * 5 + it * 3) & (kRecords - 1);
+        const float *p = tab + r * kRecFloats;
+#pragma unroll
+        for (int q = 0; q < 2 * kRecFloats; ++q) acc += p[q];
+    }
+    out[blockIdx.x * blockDim.x + threadIdx.x] = acc;
+}
+
 __global__ __launch_bounds__(256) void k_divergent_lines(const float4 *__restrict__ a, float *__restrict__ out) {
     const int lane = threadIdx.x & 63;
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -52,9 +70,11 @@ __global__ __launch_bounds__(256) void k_divergent_lines(const float4 *__restric
 
 }  // namespace
 
-extern "C" int l1_probe_rates(double *pairs_per_cu_ns, double *lines_per_cu_ns, int *n_cu) {
+extern "C" int l1_probe_rates(double *pairs_per_cu_ns, double *lines_per_cu_ns, double *lds_pairs_per_cu_ns,
+                              int *n_cu) {
     *pairs_per_cu_ns = 0.0;
     *lines_per_cu_ns = 0.0;
+    *lds_pairs_per_cu_ns = 0.0;
     *n_cu = 0;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -72,19 +92,20 @@ extern "C" int l1_probe_rates(double *pairs_per_cu_ns, double *lines_per_cu_ns, 
     if ((e = hipMemset(buf, 0, table_bytes)) != hipSuccess) goto done;
     if ((e = hipEventCreate(&e0)) != hipSuccess) goto done;
     if ((e = hipEventCreate(&e1)) != hipSuccess) goto done;
-    for (int probe = 0; probe < 2; ++probe) {
+    for (int probe = 0; probe < 3; ++probe) {
         for (int rep = 0; rep < 3; ++rep) {
             if ((e = hipEventRecord(e0, nullptr)) != hipSuccess) goto done;
             if (probe == 0) k_pair_gather<<<kBlocks, kThreads, 0, nullptr>>>((const float *)buf, out);
-            else k_divergent_lines<<<kBlocks, kThreads, 0, nullptr>>>((const float4 *)buf, out);
+            else if (probe == 1) k_divergent_lines<<<kBlocks, kThreads, 0, nullptr>>>((const float4 *)buf, out);
+            else k_pair_gather_lds<<<kBlocks, kThreads, 0, nullptr>>>((const float *)buf, out);
             if ((e = hipGetLastError()) != hipSuccess) goto done;
             if ((e = hipEventRecord(e1, nullptr)) != hipSuccess) goto done;
             if ((e = hipEventSynchronize(e1)) != hipSuccess) goto done;
             float ms = 0.f;
             if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) goto done;
-            const double n = (double)kBlocks * kThreads * (probe == 0 ? kPairIters : kLineIters);
+            const double n = (double)kBlocks * kThreads * (probe == 1 ? kLineIters : kPairIters);
             const double rate = n / ncu / (ms * 1e6);
-            double *dst = probe == 0 ? pairs_per_cu_ns : lines_per_cu_ns;
+            double *dst = probe == 0 ? pairs_per_cu_ns : (probe == 1 ? lines_per_cu_ns : lds_pairs_per_cu_ns);
             if (rate > *dst) *dst = rate;
         }
     }

@@ -185,6 +185,33 @@ def test_launch_shape_invariance(F, torch_cuda):
         assert np.allclose(sa, sb, rtol=1e-12, atol=0)
 
 
+def test_mixed_time_dependent_launch_shape_invariance(F, torch_cuda):
+    """The float forward kernel on a time-dependent grid without cross-field
+    records stages a slab of each workgroup's leaf in LDS and reads the corners
+    that fall in it there: which particles read from LDS depends on the
+    workgroup composition, so trajectories must be bit-identical across block
+    sizes, steps per launch and sort settings (here a whole 8x4x8 block fits,
+    so most gathers take the LDS path)."""
+    p, g, inj = amr_cir_case(kperp=0.0)
+    p = dict(p, precision="mixed")
+    r, th, ph = W.cell_centres(g)
+    raw = np.stack([W.cir_wind(r, th, ph, k * g["dt_s"], width=25 * DEG) for k in range(g["n_snap"])])
+    injs = [(inj, 400, 1000), (inj, 377, 1400)]
+    runs = []
+    for launch, chunks in (((256, 64, 64, 1), [300]), ((64, 16, 32, 1), [100, 200]), ((128, 25, 75, 0), [300]),
+                           ((192, 5, 15, 1), [1, 299])):
+        got, sums, w, st = gpu_run(F, torch_cuda, p, g, raw, injs, 300, launch=launch, step_chunks=chunks)
+        m = got["status"] == 0
+        o = np.argsort(got["pid"][m])
+        runs.append(({k: got[k][m][o] for k in ("x", "mu", "lnp", "pid", "w")}, sums, launch))
+    a, sa, _ = runs[0]
+    assert len(a["pid"]) > 300
+    for b, sb, launch in runs[1:]:
+        for k in ("pid", "x", "mu", "lnp", "w"):
+            assert np.array_equal(a[k], b[k]), (launch, k)
+        assert np.allclose(sa, sb, rtol=1e-12, atol=1e-12 * np.abs(sa).max())
+
+
 def test_edge_cases(F, torch_cuda):
     torch = torch_cuda
     cfg = W.tiny_parker(n_particles=100)
