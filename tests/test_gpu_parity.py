@@ -185,14 +185,13 @@ def test_launch_shape_invariance(F, torch_cuda):
         assert np.allclose(sa, sb, rtol=1e-12, atol=0)
 
 
-def test_mixed_time_dependent_launch_shape_invariance(F, torch_cuda):
-    """The float forward kernel on a time-dependent grid without cross-field
-    records stages a slab of each workgroup's leaf in LDS and reads the corners
-    that fall in it there: which particles read from LDS depends on the
-    workgroup composition, so trajectories must be bit-identical across block
-    sizes, steps per launch and sort settings (here a whole 8x4x8 block fits,
-    so most gathers take the LDS path)."""
-    p, g, inj = amr_cir_case(kperp=0.0)
+@pytest.mark.parametrize("kperp", [0.0, 0.05])
+def test_mixed_time_dependent_launch_shape_invariance(F, torch_cuda, kperp):
+    """The float kernel's unrolled two-snapshot gather (plain and cross-field
+    records) on a 3-level time-dependent grid: trajectories depend only on
+    (pid, step), bit for bit, whatever the block size, steps per launch,
+    compaction, spatial sort and call splitting."""
+    p, g, inj = amr_cir_case(kperp=kperp)
     p = dict(p, precision="mixed")
     r, th, ph = W.cell_centres(g)
     raw = np.stack([W.cir_wind(r, th, ph, k * g["dt_s"], width=25 * DEG) for k in range(g["n_snap"])])
