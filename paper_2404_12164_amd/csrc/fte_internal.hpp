@@ -113,8 +113,18 @@ enum : int { kTanLnw = 10, kTanLnwP = 11, kTanCols = 13 };
 // index can be staged in LDS too (tables up to FTE_LDS_INDEX_BYTES); on the
 // CIR workload its 10 KB stay resident in L1/L2 and staging cost 0.5%, so it
 // is off unless the limit is raised at build time.
+//
+// Record tile: the float forward kernel on time-dependent grids with plain
+// records stages, per workgroup, whole padded k-layers of one leaf for both
+// live snapshots in LDS (as many as FTE_LDS_TILE_BYTES holds, at least two;
+// 0 turns it off), anchored at the workgroup's middle particle; corners that
+// lie in it are read from LDS, the others through the L1.  After the spatial
+// sort a workgroup's particles sit in few k-layers of one leaf, and LDS serves
+// such divergent reads several times faster than the L1.
 struct StepLds {
     int it_lo, n_tb;
+    int tile_layers;  // padded k-layers in the tile (0: no tile)
+    int tile_off;     // byte offset of the tile in the dynamic LDS
 };
 #ifndef FTE_LDS_HIST_BYTES
 #define FTE_LDS_HIST_BYTES 16384
@@ -122,7 +132,11 @@ struct StepLds {
 #ifndef FTE_LDS_INDEX_BYTES
 #define FTE_LDS_INDEX_BYTES 0
 #endif
+#ifndef FTE_LDS_TILE_BYTES
+#define FTE_LDS_TILE_BYTES 61440
+#endif
 constexpr size_t kLdsHistBytes = FTE_LDS_HIST_BYTES;
+constexpr size_t kLdsTileBytes = FTE_LDS_TILE_BYTES;
 constexpr size_t kLdsIndexBytes = FTE_LDS_INDEX_BYTES;
 
 // Device counters (live in the work buffer).

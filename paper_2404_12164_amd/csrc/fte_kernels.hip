@@ -559,9 +559,20 @@ hipError_t launch_add_live(DevCounters *cnt, int slot, uint64_t n, hipStream_t s
 // records (trilinear in space, linear in time between snapshots k and k+1).
 // TS2: the grid has two live snapshots and both are gathered in one unrolled
 // pass, so that the loads of all 16 corners are in flight together.
-template <typename R, bool KPERP, bool TS2>
+// The workgroup's record tile (see StepLds): padded k-layers [k0, k0 +
+// layers) of leaf `leaf` for the snapshot pair starting at ks, laid out as
+// the leaf's own records, snapshot ks first.  The pointer is typed as LDS so
+// that the compiler keeps the tile reads and the global gather apart (a
+// generic pointer would turn both into flat loads).
+typedef const __attribute__((address_space(3))) float lds_float;
+struct RecTile {
+    lds_float *lds;
+    int leaf, k0, layers, ks;
+};
+
+template <typename R, bool KPERP, bool TS2, bool TILE = false>
 __device__ __forceinline__ bool gather(const DevGrid &G, const int32_t *ibase, const int32_t *ichild, R s[3], int ks,
-                                       R alpha, R acc[kNF]) {
+                                       R alpha, R acc[kNF], const RecTile T = RecTile{nullptr, -1, 0, 0, -1}) {
     constexpr int NF = KPERP ? 13 : 10;
     constexpr int RS = KPERP ? kRSKperp : kRSPlain;
     fold_s<R>(G, s);
@@ -584,6 +595,29 @@ __device__ __forceinline__ bool gather(const DevGrid &G, const int32_t *ibase, c
     const R *rec = reinterpret_cast<const R *>(G.rec);
 #pragma unroll
     for (int q = 0; q < NF; ++q) acc[q] = (R)0;
+    if constexpr (TILE) {
+        // both corner layers i[2] + 1 and i[2] + 2 in the tile: the same
+        // values, weights and summation order as the global path below
+        const bool in = leaf == T.leaf && ks == T.ks && i[2] + 1 >= T.k0 && i[2] + 2 < T.k0 + T.layers && i[0] >= -1 &&
+            i[0] + 2 < G.px[0] && i[1] >= -1 && i[1] + 2 < G.px[1];
+        if (in) {
+            const size_t tsnap = (size_t)T.layers * sz * RS;
+            lds_float *tb = T.lds + ((size_t)(i[2] + 1 - T.k0) * sz + (size_t)(i[1] + 1) * sy + (size_t)(i[0] + 1)) * RS;
+#pragma unroll
+            for (int sn = 0; sn < 2; ++sn) {
+                const R ws = sn == 0 ? (R)1 - alpha : alpha;
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                    const int e0 = d & 1, e1 = (d >> 1) & 1, e2 = (d >> 2) & 1;
+                    const R w = ws * (e0 ? f[0] : (R)1 - f[0]) * (e1 ? f[1] : (R)1 - f[1]) * (e2 ? f[2] : (R)1 - f[2]);
+                    lds_float *p = tb + sn * tsnap + (e0 * sx + e1 * sy + e2 * sz) * RS;
+#pragma unroll
+                    for (int q = 0; q < NF; ++q) acc[q] += w * p[q];
+                }
+            }
+            return true;
+        }
+    }
     // the 8 corners of snapshot slot ks + sn, weighted by ws
     auto corners = [&](int sn, R ws) {
         const R *base = rec + (((size_t)((ks + sn) % G.n_slots) * G.n_leaves + leaf) * G.pcells + pc) * RS;
@@ -821,6 +855,56 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
     }
     for (int k = threadIdx.x; k < n_lh; k += blockDim.x) lh[k] = 0.0;
     if (LIDX || n_lh > 0) __syncthreads();
+    // record tile (float forward kernel, time-dependent grid, plain records):
+    // anchored at the leaf and k-layer of the workgroup's middle particle, for
+    // the snapshot pair of the launch's first step
+    constexpr bool kTile = std::is_same<R, float>::value && !KPERP && MODE == 0 && TS2 && !ENS && !LAYER && !LIDX;
+    RecTile tile{nullptr, -1, 0, 0, -1};
+    if constexpr (kTile) {
+        if (LD.tile_layers > 0) {
+            __shared__ int anchor[2];
+            if (threadIdx.x == 0) anchor[0] = -1;
+            __syncthreads();
+            const uint64_t im = (uint64_t)blockIdx.x * blockDim.x + (blockDim.x >> 1);
+            if (threadIdx.x == (blockDim.x >> 1) && im < n_live && st.status[im] == FTE_PS_ACTIVE) {
+                const double ax = st.x[im], ay = st.y[im], az = st.z[im];
+                const R ar = radius_of<R>(ax * ax + ay * ay + az * az);
+                R aph = M<R>::atan2_((R)ay, (R)ax);
+                if (aph < (R)0) aph += (R)(2.0 * kPi);
+                R as[3], aS[3];
+                int aB[3];
+                grid_coords<R>(G, ar, M<R>::acos_(cos_colat<R>(az, ar)), aph, as);
+                fold_s<R>(G, as);
+                const int aleaf = descend<R>(G, ibase, ichild, as, aS, aB);
+                if (aleaf >= 0) {
+                    anchor[0] = aleaf;
+                    anchor[1] = (int)M<R>::floor_(aS[2] - (R)(aB[2] * G.bx[2]) - (R)0.5) + 1;
+                }
+            }
+            __syncthreads();
+            if (anchor[0] >= 0) {
+                const int TL = LD.tile_layers, pz = G.px[2];
+                int k0 = anchor[1] - (TL - 2) / 2;
+                k0 = k0 > pz - TL ? pz - TL : k0;
+                k0 = k0 < 0 ? 0 : k0;
+                const double tau = (P.t0 + (double)n0 * P.dt - G.t_s0) * G.inv_dt_s;
+                double kf = ::floor(tau);
+                kf = kf < 0.0 ? 0.0 : (kf > (double)(G.n_snap - 2) ? (double)(G.n_snap - 2) : kf);
+                const int ks0 = (int)kf;
+                float *t = reinterpret_cast<float *>(k_step_lds + LD.tile_off);
+                const size_t layer = (size_t)G.px[0] * G.px[1] * kRSPlain;
+                const size_t nfl = layer * TL;
+                const float *recf = reinterpret_cast<const float *>(G.rec);
+                for (int sn = 0; sn < 2; ++sn) {
+                    const float *src = recf + (((size_t)((ks0 + sn) % G.n_slots) * G.n_leaves + anchor[0]) * G.pcells) *
+                                                  kRSPlain + (size_t)k0 * layer;
+                    for (size_t q = threadIdx.x; q < nfl; q += blockDim.x) t[sn * nfl + q] = src[q];
+                }
+                tile = RecTile{(lds_float *)t, anchor[0], k0, TL, ks0};
+            }
+            __syncthreads();
+        }
+    }
     if (i < n_live && st.status[i] == FTE_PS_ACTIVE) {
         double x = st.x[i], y = st.y[i], z = st.z[i];
         R mu = (R)st.mu[i], lnp = (R)st.lnp[i];
@@ -922,7 +1006,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                     break;
                 }
             } else {
-                if (!gather<R, KPERP, TS2>(G, ibase, ichild, s, ks, alpha, acc)) {
+                if (!gather<R, KPERP, TS2, kTile>(G, ibase, ichild, s, ks, alpha, acc, tile)) {
                     status = FTE_PS_NUMERIC;
                     break;
                 }
@@ -1388,7 +1472,7 @@ static void launch_step_t(const DevParams &p, const DevGrid &g, DevState st, Dev
 // when their histogram fits kLdsHistBytes; the block index when it fits
 // kLdsIndexBytes.
 StepLds plan_step_lds(const DevParams &p, const DevGrid &g, uint64_t n0, uint32_t n_steps, size_t *shmem, bool *lidx) {
-    StepLds ld{0, 0};
+    StepLds ld{0, 0, 0, 0};
     if (p.n_obs > 0 && n_steps > 0) {
         const double t_a = p.t0 + (double)n0 * p.dt, t_b = p.t0 + (double)(n0 + n_steps - 1) * p.dt;
         double fa = ::floor((t_a + p.dt - p.t_ref) * p.inv_dT), fb = ::floor((t_b + p.dt - p.t_ref) * p.inv_dT);
@@ -1418,7 +1502,19 @@ hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevTan
     dim3 grid(blocks_for(n_upper, block)), blk(block);
     size_t shmem = 0;
     bool lidx = false;
-    const StepLds ld = plan_step_lds(p, g, n0, n_steps, &shmem, &lidx);
+    StepLds ld = plan_step_lds(p, g, n0, n_steps, &shmem, &lidx);
+    if (fp32 && !kp && !lidx && g.n_snap >= 2 && !p.grad && !p.smooth && p.n_runs == 0 && !(p.layer_k0dt > 0.0) &&
+        kLdsTileBytes > 0) {
+        // as many whole padded k-layers of both snapshots as fit, at least two
+        const size_t layer_bytes = (size_t)g.px[0] * g.px[1] * kRSPlain * sizeof(float);
+        size_t tl = kLdsTileBytes / (2 * layer_bytes);
+        if (tl > (size_t)g.px[2]) tl = (size_t)g.px[2];
+        if (tl >= 2) {
+            ld.tile_off = (int)((shmem + 15) & ~(size_t)15);
+            ld.tile_layers = (int)tl;
+            shmem = (size_t)ld.tile_off + 2 * tl * layer_bytes;
+        }
+    }
     if (fp32) {
         if (kp) launch_step_t<float, true>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld, shmem, lidx, s);
         else launch_step_t<float, false>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld, shmem, lidx, s);

@@ -211,6 +211,47 @@ def test_mixed_time_dependent_launch_shape_invariance(F, torch_cuda, kperp):
         assert np.allclose(sa, sb, rtol=1e-12, atol=1e-12 * np.abs(sa).max())
 
 
+def test_cir_grid_launch_shape_invariance(F, torch_cuda):
+    """The mixed path on the CIR grid (16x12x16 blocks, so a workgroup's LDS
+    record tile holds 3 of a leaf's 18 padded k-layers and many corners come
+    from L1 instead): trajectories bit-identical across block sizes, steps per
+    launch and compaction intervals, which change every workgroup's
+    composition, tile anchor and so which gathers read LDS."""
+    torch = torch_cuda
+    cfg = W.cir_time_dependent(n_particles=3_000_000, n_snap=5)
+    g = cfg["grid"]
+    dev = torch.device("cuda:0")
+    raw = W.make_raw(g, cfg["wind"], xp=torch, device=dev)
+    N, S = cfg["n_particles"], cfg["injection"]["n_inj_steps"]
+    inj = cfg["injection"]
+    p = dict(cfg["params"], precision="mixed")
+    runs = []
+    for launch in ((256, 64, 64, 1), (128, 32, 64, 1), (192, 16, 48, 1)):
+        sim = F.Simulation(p, g, 250_000)
+        sim.load_grid(raw)
+        sim.set_launch(*launch)
+        injected, n0 = 0, 0
+        for chunk in (564, 564):
+            n1 = n0 + chunk
+            j_max = min(N, int(math.ceil(n1 * N / S)) + 1)
+            sim.inject(inj, j_max - injected, injected)
+            injected = j_max
+            sim.step(chunk)
+            n0 = n1
+        torch.cuda.synchronize()
+        got = sim.particles()
+        assert sim.stats().device_flags == 0
+        sim.close()
+        m = got["status"] == 0
+        o = np.argsort(got["pid"][m])
+        runs.append(({k: got[k][m][o] for k in ("pid", "x", "mu", "lnp")}, launch))
+    a, _ = runs[0]
+    assert len(a["pid"]) > 100_000
+    for b, launch in runs[1:]:
+        for k in ("pid", "x", "mu", "lnp"):
+            assert np.array_equal(a[k], b[k]), (launch, k)
+
+
 def test_edge_cases(F, torch_cuda):
     torch = torch_cuda
     cfg = W.tiny_parker(n_particles=100)
