@@ -855,10 +855,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
     }
     for (int k = threadIdx.x; k < n_lh; k += blockDim.x) lh[k] = 0.0;
     if (LIDX || n_lh > 0) __syncthreads();
-    // record tile (float forward kernel, time-dependent grid, plain records):
-    // anchored at the leaf and k-layer of the workgroup's middle particle, for
-    // the snapshot pair of the launch's first step
-    constexpr bool kTile = std::is_same<R, float>::value && !KPERP && MODE == 0 && TS2 && !ENS && !LAYER && !LIDX;
+    // record tile (float forward kernel, time-dependent grid): anchored at the
+    // leaf and k-layer of the workgroup's middle particle, for the snapshot
+    // pair of the launch's first step
+    constexpr bool kTile = std::is_same<R, float>::value && MODE == 0 && TS2 && !LAYER && !LIDX;
+    constexpr int kTileRS = KPERP ? kRSKperp : kRSPlain;
     RecTile tile{nullptr, -1, 0, 0, -1};
     if constexpr (kTile) {
         if (LD.tile_layers > 0) {
@@ -892,12 +893,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                 kf = kf < 0.0 ? 0.0 : (kf > (double)(G.n_snap - 2) ? (double)(G.n_snap - 2) : kf);
                 const int ks0 = (int)kf;
                 float *t = reinterpret_cast<float *>(k_step_lds + LD.tile_off);
-                const size_t layer = (size_t)G.px[0] * G.px[1] * kRSPlain;
+                const size_t layer = (size_t)G.px[0] * G.px[1] * kTileRS;
                 const size_t nfl = layer * TL;
                 const float *recf = reinterpret_cast<const float *>(G.rec);
                 for (int sn = 0; sn < 2; ++sn) {
                     const float *src = recf + (((size_t)((ks0 + sn) % G.n_slots) * G.n_leaves + anchor[0]) * G.pcells) *
-                                                  kRSPlain + (size_t)k0 * layer;
+                                                  kTileRS + (size_t)k0 * layer;
                     for (size_t q = threadIdx.x; q < nfl; q += blockDim.x) t[sn * nfl + q] = src[q];
                 }
                 tile = RecTile{(lds_float *)t, anchor[0], k0, TL, ks0};
@@ -1503,10 +1504,9 @@ hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevTan
     size_t shmem = 0;
     bool lidx = false;
     StepLds ld = plan_step_lds(p, g, n0, n_steps, &shmem, &lidx);
-    if (fp32 && !kp && !lidx && g.n_snap >= 2 && !p.grad && !p.smooth && p.n_runs == 0 && !(p.layer_k0dt > 0.0) &&
-        kLdsTileBytes > 0) {
+    if (fp32 && !lidx && g.n_snap >= 2 && !p.grad && !p.smooth && !(p.layer_k0dt > 0.0) && kLdsTileBytes > 0) {
         // as many whole padded k-layers of both snapshots as fit, at least two
-        const size_t layer_bytes = (size_t)g.px[0] * g.px[1] * kRSPlain * sizeof(float);
+        const size_t layer_bytes = (size_t)g.px[0] * g.px[1] * (kp ? kRSKperp : kRSPlain) * sizeof(float);
         size_t tl = kLdsTileBytes / (2 * layer_bytes);
         if (tl > (size_t)g.px[2]) tl = (size_t)g.px[2];
         if (tl >= 2) {
