@@ -855,10 +855,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
     }
     for (int k = threadIdx.x; k < n_lh; k += blockDim.x) lh[k] = 0.0;
     if (LIDX || n_lh > 0) __syncthreads();
-    // record tile (float forward kernel, time-dependent grid): anchored at the
-    // leaf and k-layer of the workgroup's middle particle, for the snapshot
-    // pair of the launch's first step
-    constexpr bool kTile = std::is_same<R, float>::value && MODE == 0 && TS2 && !LAYER && !LIDX;
+    // record tile (float forward kernels, time-dependent grid): anchored at
+    // the leaf and k-layer of the workgroup's middle particle, for the
+    // snapshot pair of the launch's first step
+    constexpr bool kTile = std::is_same<R, float>::value && TS2 && !LAYER && !LIDX;
     constexpr int kTileRS = KPERP ? kRSKperp : kRSPlain;
     RecTile tile{nullptr, -1, 0, 0, -1};
     if constexpr (kTile) {
@@ -1504,7 +1504,7 @@ hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevTan
     size_t shmem = 0;
     bool lidx = false;
     StepLds ld = plan_step_lds(p, g, n0, n_steps, &shmem, &lidx);
-    if (fp32 && !lidx && g.n_snap >= 2 && !p.grad && !p.smooth && !(p.layer_k0dt > 0.0) && kLdsTileBytes > 0) {
+    if (fp32 && !lidx && g.n_snap >= 2 && !p.grad && !(p.layer_k0dt > 0.0) && kLdsTileBytes > 0) {
         // as many whole padded k-layers of both snapshots as fit, at least two
         const size_t layer_bytes = (size_t)g.px[0] * g.px[1] * (kp ? kRSKperp : kRSPlain) * sizeof(float);
         size_t tl = kLdsTileBytes / (2 * layer_bytes);
