@@ -899,7 +899,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                 for (int sn = 0; sn < 2; ++sn) {
                     const float *src = recf + (((size_t)((ks0 + sn) % G.n_slots) * G.n_leaves + anchor[0]) * G.pcells) *
                                                   kTileRS + (size_t)k0 * layer;
-                    for (size_t q = threadIdx.x; q < nfl; q += blockDim.x) t[sn * nfl + q] = src[q];
+                    if ((nfl & 3) == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+                        // 16-byte copies (the tile offset is 16-byte aligned)
+                        const float4 *s4 = reinterpret_cast<const float4 *>(src);
+                        float4 *t4 = reinterpret_cast<float4 *>(t + sn * nfl);
+                        for (size_t q = threadIdx.x; q < (nfl >> 2); q += blockDim.x) t4[q] = s4[q];
+                    } else {
+                        for (size_t q = threadIdx.x; q < nfl; q += blockDim.x) t[sn * nfl + q] = src[q];
+                    }
                 }
                 tile = RecTile{(lds_float *)t, anchor[0], k0, TL, ks0};
             }
