@@ -114,10 +114,9 @@ enum : int { kTanLnw = 10, kTanLnwP = 11, kTanCols = 13 };
 // CIR workload its 10 KB stay resident in L1/L2 and staging cost 0.5%, so it
 // is off unless the limit is raised at build time.
 //
-// Record tile: the float forward kernels (histogram and smoothed modes,
-// single runs and ensembles, with or without cross-field records; the
-// tangent kernel ran 7% slower with it) on time-dependent grids stage, per
-// workgroup, whole padded k-layers of one leaf for both
+// Record tile: the float step kernels (histogram, smoothed and tangent
+// modes, single runs and ensembles, with or without cross-field records) on
+// time-dependent grids stage, per workgroup, whole padded k-layers of one leaf for both
 // live snapshots in LDS (as many as FTE_LDS_TILE_BYTES holds, at least two;
 // 0 turns it off), anchored at the workgroup's middle particle; corners that
 // lie in it are read from LDS, the others through the L1.  After the spatial

@@ -643,9 +643,10 @@ __device__ __forceinline__ bool gather(const DevGrid &G, const int32_t *ibase, c
 // Directional derivatives of the gathered (spherical-component) fields along
 // ND tangent directions: ds[k] holds the derivative of the level-1
 // coordinates along direction k; axes clamped by the fold contribute none.
-template <typename R, bool KPERP, int ND>
+template <typename R, bool KPERP, int ND, bool TILE = false>
 __device__ __forceinline__ bool gather_d(const DevGrid &G, const int32_t *ibase, const int32_t *ichild, R s[3],
-                                         const R ds[ND][3], int ks, R alpha, R acc[kNF], R dacc[ND][kNF]) {
+                                         const R ds[ND][3], int ks, R alpha, R acc[kNF], R dacc[ND][kNF],
+                                         const RecTile T = RecTile{nullptr, -1, 0, 0, -1}) {
     constexpr int NF = KPERP ? 13 : 10;
     constexpr int RS = KPERP ? kRSKperp : kRSPlain;
     const R s_in[3] = {s[0], s[1], s[2]};
@@ -680,6 +681,39 @@ __device__ __forceinline__ bool gather_d(const DevGrid &G, const int32_t *ibase,
         for (int k = 0; k < ND; ++k) dacc[k][q] = (R)0;
     }
     const int nsn = G.n_snap >= 2 ? 2 : 1;
+    if constexpr (TILE) {
+        // both corner layers in the workgroup's tile (see gather): the same
+        // values, weights and summation order as the loop below
+        if (nsn == 2 && leaf == T.leaf && ks == T.ks && i[2] + 1 >= T.k0 && i[2] + 2 < T.k0 + T.layers &&
+            i[0] >= -1 && i[0] + 2 < G.px[0] && i[1] >= -1 && i[1] + 2 < G.px[1]) {
+            const size_t tsnap = (size_t)T.layers * sz * RS;
+            lds_float *tb = T.lds + ((size_t)(i[2] + 1 - T.k0) * sz + (size_t)(i[1] + 1) * sy + (size_t)(i[0] + 1)) * RS;
+#pragma unroll
+            for (int sn = 0; sn < 2; ++sn) {
+                const R ws = sn == 0 ? (R)1 - alpha : alpha;
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                    const int e0 = d & 1, e1 = (d >> 1) & 1, e2 = (d >> 2) & 1;
+                    const R w0 = e0 ? f[0] : (R)1 - f[0], w1 = e1 ? f[1] : (R)1 - f[1], w2 = e2 ? f[2] : (R)1 - f[2];
+                    const R g0 = e0 ? (R)1 : (R)-1, g1 = e1 ? (R)1 : (R)-1, g2 = e2 ? (R)1 : (R)-1;
+                    const R w = ws * w0 * w1 * w2;
+                    R dw[ND];
+#pragma unroll
+                    for (int k = 0; k < ND; ++k)
+                        dw[k] = ws * (g0 * w1 * w2 * dS[k][0] + w0 * g1 * w2 * dS[k][1] + w0 * w1 * g2 * dS[k][2]);
+                    lds_float *p = tb + sn * tsnap + (e0 * sx + e1 * sy + e2 * sz) * RS;
+#pragma unroll
+                    for (int q = 0; q < NF; ++q) {
+                        const R v = p[q];
+                        acc[q] += w * v;
+#pragma unroll
+                        for (int k = 0; k < ND; ++k) dacc[k][q] += dw[k] * v;
+                    }
+                }
+            }
+            return true;
+        }
+    }
     for (int sn = 0; sn < nsn; ++sn) {
         const R ws = (G.n_snap >= 2) ? (sn == 0 ? (R)1 - alpha : alpha) : (R)1;
         const R *base = rec + (((size_t)((ks + sn) % G.n_slots) * G.n_leaves + leaf) * G.pcells + pc) * RS;
@@ -855,10 +889,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
     }
     for (int k = threadIdx.x; k < n_lh; k += blockDim.x) lh[k] = 0.0;
     if (LIDX || n_lh > 0) __syncthreads();
-    // record tile (float forward kernels, time-dependent grid): anchored at
-    // the leaf and k-layer of the workgroup's middle particle, for the
-    // snapshot pair of the launch's first step
-    constexpr bool kTile = std::is_same<R, float>::value && TS2 && !LAYER && !LIDX;
+    // record tile (float kernels, time-dependent grid): anchored at the leaf
+    // and k-layer of the workgroup's middle particle, for the snapshot pair of
+    // the launch's first step
+    constexpr bool kTile = std::is_same<R, float>::value && (TS2 || MODE == 2) && !LAYER && !LIDX;
     constexpr int kTileRS = KPERP ? kRSKperp : kRSPlain;
     RecTile tile{nullptr, -1, 0, 0, -1};
     if constexpr (kTile) {
@@ -1009,7 +1043,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                     ds[k][1] = tth[k] * (R)G.inv_dth;
                     ds[k][2] = M<R>::div_(tph[k], st_) * (R)G.inv_dph;
                 }
-                if (!gather_d<R, KPERP, ND>(G, ibase, ichild, s, ds, ks, alpha, acc, dacc)) {
+                if (!gather_d<R, KPERP, ND, kTile>(G, ibase, ichild, s, ds, ks, alpha, acc, dacc, tile)) {
                     status = FTE_PS_NUMERIC;
                     break;
                 }
@@ -1511,7 +1545,7 @@ hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevTan
     size_t shmem = 0;
     bool lidx = false;
     StepLds ld = plan_step_lds(p, g, n0, n_steps, &shmem, &lidx);
-    if (fp32 && !lidx && g.n_snap >= 2 && !p.grad && !(p.layer_k0dt > 0.0) && kLdsTileBytes > 0) {
+    if (fp32 && !lidx && g.n_snap >= 2 && !(p.layer_k0dt > 0.0) && kLdsTileBytes > 0) {
         // as many whole padded k-layers of both snapshots as fit, at least two
         const size_t layer_bytes = (size_t)g.px[0] * g.px[1] * (kp ? kRSKperp : kRSPlain) * sizeof(float);
         size_t tl = kLdsTileBytes / (2 * layer_bytes);
