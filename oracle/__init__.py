@@ -11,7 +11,10 @@ marshals them into its own structures.
 Parity status of each function (see the tests under ``tests/test_oracle_*.py``):
   philox4x32/normals      pinned: round structure against numpy's Philox4x64-10,
                           4x32 against rocRAND's host-compiled engine, moments
-  dmm / dmm_integral      pinned: numerical quadrature of the definition
+  dmm / dmm_integral      pinned: numerical quadrature of the definition;
+                          the rigidity scaling lambda_par = lambda_ref (P/P_ref)^alpha
+                          of D_mumu and kappa_perp by the parallel and cross-field
+                          spreads at two momenta (alpha = 1/3 and -1)
   grid lookups/derive     pinned: brute-force leaf search, affine-field
                           exactness, Parker closed forms (2nd-order convergence)
   run (SDE step)          pinned: pitch-angle relaxation, parallel/perpendicular
@@ -38,14 +41,24 @@ BG = {"grid": 0, "uniform": 1, "par_flow": 2, "perp_flow": 3, "radial": 4}
 STATUS = {"active": 0, "abs_in": 1, "abs_out": 2, "out_of_domain": 3, "numeric": 4}
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
-               "-o", _LIB + ".tmp", _SRC, "-lm"]
+def build(force: bool = False, native: bool = False, out: str = None) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math).
+
+    ``native`` builds the timing copy instead: -O3 -march=native for the
+    host it is compiled on (so it must be built on the machine that runs it),
+    with floating-point contraction off so that its arithmetic is the same as
+    the portable build's; ``out`` is its path."""
+    lib = out or _LIB
+    if native:
+        flags = ["-O3", "-march=native", "-ffp-contract=off"]
+    else:
+        flags = ["-O2"]
+    if force or native or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        cmd = ["gcc"] + flags + ["-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
+                                 "-o", lib + ".tmp", _SRC, "-lm"]
         subprocess.check_call(cmd)
-        os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+        os.replace(lib + ".tmp", lib)
+    return lib
 
 
 class OrParams(C.Structure):
@@ -89,11 +102,23 @@ class OrInjection(C.Structure):
 _lib = None
 
 
-def lib():
+def use_native_build(out: str) -> str:
+    """Build the -O3 -march=native timing copy at ``out`` on this host and
+    make every later call of this module use it (the CPU-baseline timing);
+    returns its path."""
+    global _lib
+    path = build(native=True, out=out)
+    _lib = None
+    lib(path)
+    return path
+
+
+def lib(path: str = None):
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(_LIB)
+        if path is None:
+            build()
+        L = C.CDLL(path or _LIB)
         dp = C.POINTER(C.c_double)
         u32p = C.POINTER(C.c_uint32)
         u64p = C.POINTER(C.c_uint64)

@@ -384,3 +384,76 @@ def test_smoothed_intensity_profile(orc):
         assert J[0, e, 3] < 1e-6 * want
     # the second observer sits 0.5 au away from the population
     assert np.all(J[1] == 0.0)
+
+
+def _rigidity_case(orc, alpha, kperp_ratio=0.0, N=10000):
+    """ISO scattering in a uniform field along x, no flow (P stays constant),
+    at two momenta on either side of P_ref, each run with its own step so
+    that D_c dt = 2e-3 and D_c t = 2 for the D_c = v / (2 lambda_par) that
+    lambda_par = lambda_ref (P/P_ref)^alpha predicts.  Returns per momentum
+    (v, expected lambda_par, D_c, t, dt, MSD along B and its standard error,
+    cross-field MSD and its standard error)."""
+    E1, E2, Eref = 100 * W.KEV, 4000 * W.KEV, 1000 * W.KEV     # P_ref at 1 MeV (section 2.1)
+    lam_ref = 2e8
+    out = []
+    for E in (E1, E2):
+        eps = E / (W.M_P * W.C_LIGHT ** 2)
+        P = math.sqrt(eps * (eps + 2))
+        v = W.C_LIGHT * P / math.sqrt(1 + P * P)
+        er = Eref / (W.M_P * W.C_LIGHT ** 2)
+        Pref = math.sqrt(er * (er + 2))
+        lam = lam_ref * (P / Pref) ** alpha
+        Dc = v / (2 * lam)
+        dt = 2e-3 / Dc
+        n_steps = 1000
+        par = dict(mass=W.M_P, dmm_model="iso", lambda_ref=lam_ref, p_ref=Pref, alpha=alpha, dt=dt,
+                   bg_kind="uniform", bg=[0, 0, 0, 1, 0, 0], check_bounds=0, kperp_ratio=kperp_ratio)
+        p = mk(orc, N, P=P)
+        p.mu[:] = np.linspace(-1, 1, N + 2)[1:-1]
+        orc.run(par, None, p, 0, n_steps, None)
+        zz = p.x[:, 0] ** 2
+        pp = p.x[:, 1] ** 2 + p.x[:, 2] ** 2
+        out.append(dict(v=v, lam=lam, Dc=Dc, t=n_steps * dt, dt=dt, msd=zz.mean(), se=zz.std() / math.sqrt(N),
+                        perp=pp.mean(), perp_se=pp.std() / math.sqrt(N)))
+    return out
+
+
+@pytest.mark.parametrize("alpha", [1.0 / 3.0, -1.0])
+def test_rigidity_scaling_of_mean_free_path(orc, alpha):
+    """lambda_par = lambda_ref (P/P_ref)^alpha: the particle's rigidity sets the
+    scattering rate (section 2.1, Eq. 5 and the text after it).  With ISO
+    scattering, D_c = v / (2 lambda_par) and the exact finite-time MSD along B,
+    2 kappa [t - (1 - e^{-2 D_c t})/(2 D_c)] with kappa = v lambda_par / 3, is
+    measured at two momenta on either side of P_ref; the ratio of the two
+    kappas must be (v2/v1)(P2/P1)^alpha.  A wrong sign of alpha or an
+    inverted ratio P_ref/P changes that ratio by (P2/P1)^(2 alpha), a factor
+    of 2.6 (alpha = 1/3) or 40 (alpha = -1)."""
+    res = _rigidity_case(orc, alpha)
+    kap = []
+    for r in res:
+        shape = 2 * (r["t"] - (1 - math.exp(-2 * r["Dc"] * r["t"])) / (2 * r["Dc"]))
+        want = r["v"] * r["lam"] / 3 * shape
+        # Euler-Maruyama's weak bias of the ISO MSD is ~ -5.4 D_c dt (measured)
+        allow = 6 * r["Dc"] * r["dt"] * want
+        assert abs(r["msd"] - want) < 3 * r["se"] + allow, (alpha, r["msd"], want, r["se"])
+        kap.append((r["msd"] / shape, r["se"] / shape))
+    (k1, s1), (k2, s2) = kap
+    ratio = k2 / k1
+    want_ratio = (res[1]["v"] / res[0]["v"]) * (res[1]["lam"] / res[0]["lam"])
+    se = ratio * math.hypot(s1 / k1, s2 / k2)
+    assert abs(ratio - want_ratio) < 3 * se + 0.01 * want_ratio, (alpha, ratio, want_ratio, se)
+    # the wrong exponent sign is far outside the band
+    wrong = (res[1]["v"] / res[0]["v"]) * (res[0]["lam"] / res[1]["lam"])
+    assert abs(ratio - wrong) > 10 * se
+
+
+@pytest.mark.parametrize("alpha", [1.0 / 3.0, -1.0])
+def test_rigidity_scaling_of_cross_field_diffusion(orc, alpha):
+    """kappa_perp = ratio v lambda_par / 3 follows lambda_par's rigidity scaling
+    (section 2.1: lambda_perp given relative to lambda_par).  In a uniform
+    field the cross-field spread is exactly 4 kappa_perp t at each momentum."""
+    ratio_k = 0.05
+    res = _rigidity_case(orc, alpha, kperp_ratio=ratio_k, N=8000)
+    for r in res:
+        want = 4 * ratio_k * r["v"] * r["lam"] / 3 * r["t"]
+        assert abs(r["perp"] - want) < 3 * r["perp_se"], (alpha, r["perp"], want, r["perp_se"])
