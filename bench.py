@@ -36,10 +36,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_counters(name, algo_bytes_per_launch, key):
-    """A per-launch figure of the step kernel (``key``) from the committed
-    counter summary, if it was taken on the current kernel source and the
-    same run shape."""
+def read_counters(name, kernel):
+    """Per-particle-step figures of a step-kernel instance from a committed
+    counter summary (profiles/), if they were taken on the current kernel
+    source; None otherwise."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -48,41 +48,15 @@ def read_counters(name, algo_bytes_per_launch, key):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash() or kv.get("kernel") != kernel:
         return None
-    try:
-        # only for the workload and launch shape the counters were taken on:
-        # the same algorithmic bytes per launch
-        ref = float(kv["bench_algo_bytes_per_launch"])
-        if abs(algo_bytes_per_launch - ref) > 0.01 * ref:
-            return None
-        return float(kv[key])
-    except (KeyError, ValueError):
-        return None
-
-
-def read_traffic(name, algo_bytes_per_launch):
-    """HBM bytes per step-kernel launch (calibrated FETCH_SIZE + WRITE_SIZE)."""
-    return read_counters(name, algo_bytes_per_launch, "hbm_bytes_per_launch")
-
-
-def l1_probe():
-    """What the vector L1 sustains for the step kernel's gather pattern when
-    every access hits in it (libl1probe.so, built beside the library): record
-    pairs and, for fully divergent 16-byte loads, cache lines per CU per ns,
-    the record pairs LDS serves for the same pattern, and the CU count; None
-    if the probe is not built."""
-    import ctypes
-    path = os.path.join(ROOT, "paper_2404_12164_amd", "libl1probe.so")
-    if not os.path.exists(path):
-        log("l1 probe not built")
-        return None
-    lib = ctypes.CDLL(path)
-    pairs, lines, lds, ncu = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0), ctypes.c_int(0)
-    rc = lib.l1_probe_rates(ctypes.byref(pairs), ctypes.byref(lines), ctypes.byref(lds), ctypes.byref(ncu))
-    if rc != 0:
-        raise RuntimeError(f"l1 probe failed with HIP error {rc}")
-    return pairs.value, lines.value, lds.value, ncu.value
+    out = {}
+    for k, v in kv.items():
+        try:
+            out[k] = float(v)
+        except ValueError:
+            pass
+    return out
 
 
 class Run:
@@ -129,15 +103,21 @@ class Run:
         self.sim.close()
 
 
-def timed(run, K, chunk):
+def timed(run, K, chunk, total=None):
+    """K bench steps of `chunk` global steps each; with `total`, the last ones
+    are cut so that the K steps take exactly `total` global steps."""
     torch = run.torch
     st0 = run.sim.stats()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.time()
     e0.record()
+    done = 0
     for k in range(K):
-        run.chunk(chunk)
+        n = chunk if total is None else max(0, min(chunk, total - done))
+        if n > 0:
+            run.chunk(n)
+        done += n
         if (k + 1) % max(1, K // 6) == 0:
             log(f"  chunk {k + 1}/{K} enqueued")
     e1.record()
@@ -148,7 +128,8 @@ def timed(run, K, chunk):
     steps = st1.particle_steps - st0.particle_steps
     kms = st1.step_kernel_ms - st0.step_kernel_ms
     nl = st1.step_launches - st0.step_launches
-    return dict(ms=ms, wall=wall, particle_steps=int(steps), kernel_ms=kms, launches=int(nl), stats=st1)
+    return dict(ms=ms, wall=wall, particle_steps=int(steps), kernel_ms=kms, launches=int(nl), stats=st1,
+                global_steps=done)
 
 
 def gradient_leg(F, W, raw, args):
@@ -363,11 +344,12 @@ def ensemble_leg(F, W, args):
     return out
 
 
-def largest_leg(F, W, args, hours=24):
+def largest_leg(F, W, args, hours=None):
     """The largest workload (shocked CIR with compression 3 at both shocks, 3
-    AMR levels, 2,880 leaves, 96 hourly snapshots, kappa_perp, a 10^8-particle
-    store, 5 observers x 20 energies x 288 time bins) over its first `hours`
-    of continuous injection: the step throughput and the memory it holds."""
+    AMR levels, 2,880 leaves, 96 hourly snapshots, kappa_perp, 10^8
+    particles, 5 observers x 20 energies x 288 time bins) over its whole
+    run (or its first `hours` of continuous injection): the step throughput
+    and the memory it holds."""
     import torch
     dev = torch.device("cuda:0")
     c = W.cir_largest(precision=args.precision)
@@ -380,8 +362,8 @@ def largest_leg(F, W, args, hours=24):
     del raw
     torch.cuda.empty_cache()
     chunk = 576
-    n_steps = int(hours * 3600 / c["params"]["dt"]) // chunk * chunk
-    res = timed(r, n_steps // chunk, chunk)
+    n_steps = c["n_steps"] if hours is None else min(c["n_steps"], int(hours * 3600 / c["params"]["dt"]))
+    res = timed(r, -(-n_steps // chunk), chunk, total=n_steps)
     st = res["stats"]
     sz = F.fte_query_sizes(r.p, g, c["n_particles"])
     lv = np.asarray(g["leaves"])
@@ -449,14 +431,14 @@ def paper_leg(F, W, args, levels=(1, 2, 3)):
     return out
 
 
-def stream_leg(F, W, cfg, raw, args, n_slots=3, j_resident=None):
+def stream_leg(F, W, cfg, raw, args, total, n_slots=3, j_resident=None):
     """The CIR workload with the grid held as a ring of n_slots snapshots:
     each snapshot is copied from pinned host memory into a five-snapshot
     device staging window on a copy stream, one snapshot ahead of the clock,
     while the step kernels run; it is derived into its slot (on the stepping
     stream, after its copy's event) just before the clock needs it.  The
-    whole run is timed, transfers included, against the fully resident
-    grid's value."""
+    `total` steps (those of the resident run it is compared with) are timed,
+    transfers included, against the fully resident grid's value."""
     import torch
     dev = torch.device("cuda:0")
     g = dict(cfg["grid"], n_slots=n_slots)
@@ -515,7 +497,6 @@ def stream_leg(F, W, cfg, raw, args, n_slots=3, j_resident=None):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     steps_per_snap = int(round(g["dt_s"] / p["dt"]))
-    total = cfg["n_steps"]
     done = 0
     while done < total:
         k = done // steps_per_snap
@@ -543,26 +524,49 @@ def stream_leg(F, W, cfg, raw, args, n_slots=3, j_resident=None):
                 host_to_device_bytes_per_snapshot=per_snap * 8, max_abs_diff_j_vs_resident=dj)
 
 
-def cpu_baseline(cfg, raw_gpu, n_pids, n_steps, n_threads):
-    """The FP64 oracle on the first n_pids particles over the first n_steps
-    steps, with the snapshots those steps touch copied to the host."""
+def cpu_info():
+    """Host CPU model and counts, for the CPU-baseline record."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(cpu_model=model, nproc=os.cpu_count(), affinity=len(os.sched_getaffinity(0)))
+
+
+def cpu_baseline(cfg, raw_gpu, samples):
+    """The FP64 oracle, built -O3 -march=native on this host, on the first
+    n_pids particles over the first n_steps steps of the workload, with the
+    snapshots those steps touch copied to the host; one timing per
+    (n_pids, n_steps, threads) sample."""
+    import tempfile
     import oracle
+    path = oracle.use_native_build(os.path.join(tempfile.mkdtemp(prefix="fte_oracle_"), "liboracle_native.so"))
     g = cfg["grid"]
     p = dict(cfg["params"], precision="fp64")
-    t_last = p["t0"] + (n_steps - 1) * p["dt"]
+    n_max = max(s[1] for s in samples)
+    t_last = p["t0"] + (n_max - 1) * p["dt"]
     k_hi = min(g["n_snap"] - 1, int(math.floor((t_last - g["t_s0"]) / g["dt_s"])) + 2)
     raw = raw_gpu[: k_hi + 1].cpu().numpy()
-    G = oracle.Grid(g, raw, snap0=0)
-    parts = oracle.inject(p, cfg["injection"], n_pids, cfg["injection"].get("pid0", 0))
     # only the snapshots held are valid: the grid description keeps its full
     # snapshot count so the time derivative uses the run's own stencil
-    h = np.zeros(oracle.hist_size(p))
-    t = time.time()
-    steps = oracle.run(p, G, parts, 0, n_steps, h, n_threads)
-    dt = time.time() - t
-    return dict(value=steps / dt, unit="particle-steps/s", cores=n_threads, kind="oracle",
-                sample=f"pids 0..{n_pids - 1} (the first injected) x global steps 0..{n_steps - 1} "
-                       f"of the same workload, FP64, {steps} particle-steps in {dt:.1f} s")
+    G = oracle.Grid(g, raw, snap0=0)
+    out = []
+    for n_pids, n_steps, n_threads in samples:
+        parts = oracle.inject(p, cfg["injection"], n_pids, cfg["injection"].get("pid0", 0))
+        h = np.zeros(oracle.hist_size(p))
+        t = time.time()
+        steps = oracle.run(p, G, parts, 0, n_steps, h, n_threads)
+        dt = time.time() - t
+        out.append(dict(value=steps / dt, unit="particle-steps/s", cores=n_threads, kind="oracle",
+                        sample=f"pids 0..{n_pids - 1} (the first injected) x global steps 0..{n_steps - 1} "
+                               f"of the same workload, FP64, {steps} particle-steps in {dt:.1f} s",
+                        build="gcc -O3 -march=native -ffp-contract=off -fopenmp (built on this host)"))
+    os.remove(path)
+    return out
 
 
 def main():
@@ -570,7 +574,6 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--chunk", type=int, default=564)
     ap.add_argument("--particles", type=int, default=10_000_000)
     ap.add_argument("--precision", default="mixed")
     ap.add_argument("--block", type=int, default=256)
@@ -580,13 +583,15 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")
-    ap.add_argument("--grad-seeds", type=int, default=4, help="seeds of the gradient-vs-differences check")
-    ap.add_argument("--no-largest", action="store_true", help="skip the largest workload (first 24 h)")
-    ap.add_argument("--largest-hours", type=float, default=24.0, help="hours of the largest workload to time")
+    ap.add_argument("--grad-seeds", type=int, default=8, help="seeds of the gradient-vs-differences check")
+    ap.add_argument("--no-largest", action="store_true", help="skip the largest workload")
+    ap.add_argument("--largest-hours", type=float, default=None,
+                    help="hours of the largest workload to time (default: the whole 95 h run)")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble workload")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's CIR experiment at 1-3 AMR levels")
     ap.add_argument("--no-stream", action="store_true", help="skip the snapshot-streaming run of the CIR workload")
     ap.add_argument("--cpu-pids", type=int, default=4000)
+    ap.add_argument("--cpu-pids-1", type=int, default=250, help="pids of the single-thread oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=2800)
     ap.add_argument("--calib-copy", action="store_true", help="also run a 2 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -604,10 +609,11 @@ def main():
     cfg = W.cir_time_dependent(n_particles=args.particles, precision=args.precision)
     g = cfg["grid"]
     total_steps = cfg["n_steps"]
-    if args.chunk * (args.steps + 0) > total_steps:
-        log(f"note: {args.steps} x {args.chunk} steps exceed the run's {total_steps}; clipping the chunk")
-        args.chunk = total_steps // args.steps
-    log(f"workload {cfg['name']}: {len(g['leaves'])} leaves, {g['n_snap']} snapshots, {args.particles} particles")
+    # the K bench steps always cover the whole run
+    K = max(1, args.steps)
+    chunk = -(-total_steps // K)
+    log(f"workload {cfg['name']}: {len(g['leaves'])} leaves, {g['n_snap']} snapshots, {args.particles} particles, "
+        f"{total_steps} steps in {K} bench steps of <= {chunk}")
 
     t = time.time()
     raw = W.make_raw(g, cfg["wind"], xp=torch, device=dev)
@@ -628,51 +634,64 @@ def main():
     run = Run(F, cfg, raw, args.precision, args.block, args.spl, args.compact, args.sort)
     log(f"grid loaded in {run.load_s:.2f} s")
     if args.warmup > 0:
-        for _ in range(args.warmup):
-            run.chunk(args.chunk)
+        timed(run, args.warmup, chunk, total=total_steps)
         torch.cuda.synchronize()
         run.reset()
     log("timed region")
-    res = timed(run, args.steps, args.chunk)
+    res = timed(run, K, chunk, total=total_steps)
     value = res["particle_steps"] / (res["ms"] / 1e3)
     js, _ = run.sim.bin_observers()
     st = res["stats"]
     grid_load_s = run.load_s
     run.close()
     del run
+    log(f"  {value:.4g} particle-steps/s over {res['global_steps']} global steps")
 
-    # roofline of the step kernel: algorithmic bytes per particle-step
+    # ---- rooflines of the step kernel, per launch, from the live event
+    # timing of the launches and the committed counters (per particle-step)
     F_fields = 13 if (cfg["params"].get("kperp_ratio", 0) > 0 or cfg["params"].get("lambda_perp", 0) > 0) else 10
     T_s = 2 if g["n_snap"] >= 2 else 1
     s_f = 4 if args.precision == "mixed" else 8
+    kern = ("k_step<float,false,0,false,false,true,false>" if args.precision == "mixed"
+            else "k_step<double,false,0,false,false,true,false>")
+    nl = max(res["launches"], 1)
+    launch_s = res["kernel_ms"] / 1e3 / nl
+    ps_launch = res["particle_steps"] / nl
+    # the corner bytes the gather asks for (8 T_s F s_f, plus the state each
+    # launch reads and writes once): mostly served by the LDS tile, L1 and L2
     b_step = 8 * T_s * F_fields * s_f + 2 * 64 / args.spl
-    kernel_s = res["kernel_ms"] / 1e3
-    achieved = b_step * res["particle_steps"] / kernel_s / 1e9
-    per_launch_bytes = b_step * res["particle_steps"] / max(res["launches"], 1)
-    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4),
-                # the committed counters are those of the float kernel
-                traffic=read_traffic("k_step_cir_traffic.txt", per_launch_bytes) if args.precision == "mixed" else None,
-                kernel="k_step<float,false,0,false,false,true,false>" if args.precision == "mixed" else "k_step<double,false,0,false,false,true,false>",
-                bytes_per_particle_step=b_step, launches=res["launches"],
-                avg_launch_ms=round(res["kernel_ms"] / max(res["launches"], 1), 4),
-                algo_bytes_per_launch=round(per_launch_bytes))
-    # the gather's on-chip limit: record pairs (80 contiguous bytes, one per
-    # corner row and snapshot: 4 T_s per particle-step) gathered per CU and ns
-    # of step-kernel time, against the rate the L1 serves the same per-lane
-    # pattern when every access hits in it, measured now on this GPU
-    probe = l1_probe()
-    if probe is not None:
-        pair_peak, line_peak, lds_peak, ncu = probe
-        ach = 4 * T_s * res["particle_steps"] / ncu / (kernel_s * 1e9)
-        l1 = dict(unit="record pairs/CU/ns", achieved=round(ach, 4), peak_l1_resident=round(pair_peak, 4),
-                  frac=round(ach / pair_peak, 4), pairs_per_particle_step=4 * T_s,
-                  divergent_lines_per_cu_ns=round(line_peak, 4), lds_pairs_per_cu_ns=round(lds_peak, 4))
-        lookups = (read_counters("k_step_cir_traffic.txt", per_launch_bytes, "tcp_lookups_per_launch")
-                   if args.precision == "mixed" else None)
-        if lookups is not None:
-            l1["tcp_accesses_per_cu_ns"] = round(lookups * res["launches"] / ncu / (kernel_s * 1e9), 4)
-        roof["l1"] = l1
+    gathered = dict(unit="GB/s", bytes_per_particle_step=b_step, achieved=round(b_step * ps_launch / launch_s / 1e9, 1),
+                    note="bytes the gather requests; served mostly on chip, not an HBM figure")
+    ctr = read_counters("k_step_cir_counters.txt" if args.precision == "mixed" else "k_step_cir_fp64_counters.txt", kern)
+    roof = dict(kernel=kern, launches=res["launches"], avg_launch_ms=round(launch_s * 1e3, 4),
+                particle_steps_per_launch=round(ps_launch), gathered=gathered)
+    VALU_PEAK = 256 * 4 * 2.4e9 / 4       # wave64 VALU instructions/s: 256 CUs x 4 SIMDs, 4 cycles each
+    if ctr is not None:
+        hbm = ctr["hbm_bytes_per_particle_step"] * ps_launch
+        hbm_rate = hbm / launch_s / 1e9
+        valu = ctr["valu_insts_per_particle_step"] * ps_launch / launch_s
+        roof["hbm_measured"] = dict(unit="GB/s", achieved=round(hbm_rate, 1), peak=HBM_PEAK_GBS,
+                                    frac=round(hbm_rate / HBM_PEAK_GBS, 4))
+        roof["valu"] = dict(unit="wave64 VALU instructions/s", achieved=round(valu, 1), peak=VALU_PEAK,
+                            frac=round(valu / VALU_PEAK, 4),
+                            insts_per_particle_step=ctr["valu_insts_per_particle_step"])
+        if "trans_insts_per_particle_step" in ctr:
+            # transcendental instructions occupy the SIMD 4x as long
+            busy = (ctr["valu_insts_per_particle_step"] + 3 * ctr["trans_insts_per_particle_step"]) * ps_launch / launch_s
+            roof["valu"]["frac_trans_weighted"] = round(busy / VALU_PEAK, 4)
+        # the binding roof: VALU issue when it is the larger fraction
+        if roof["valu"]["frac"] >= roof["hbm_measured"]["frac"]:
+            roof.update(bound="alu", achieved=roof["valu"]["achieved"], peak=VALU_PEAK,
+                        unit=roof["valu"]["unit"], frac=roof["valu"]["frac"])
+        else:
+            roof.update(bound="hbm", achieved=round(hbm_rate, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=roof["hbm_measured"]["frac"])
+        roof["traffic"] = round(hbm)
+        roof["counters"] = "profiles/" + ("k_step_cir_counters.txt" if args.precision == "mixed"
+                                          else "k_step_cir_fp64_counters.txt")
+    else:
+        roof.update(bound="hbm", achieved=None, peak=HBM_PEAK_GBS, unit="GB/s", frac=None, traffic=None,
+                    note="no counters for the current kernel source")
     # the bandwidth a plain device copy reaches on this GPU, next to the
     # nominal peak: 4 GiB read + 4 GiB written per copy
     src = torch.empty(2 ** 29, dtype=torch.float64, device=dev)
@@ -689,25 +708,32 @@ def main():
     del src, dst
     torch.cuda.empty_cache()
     roof["measured_copy_GBs"] = round(copy_gbs, 1)
-    roof["frac_of_measured_copy"] = round(achieved / copy_gbs, 4)
 
     extra = {}
     if not args.no_stream:
         log("CIR workload with a 3-snapshot ring streamed from pinned host memory")
-        extra["stream"] = stream_leg(F, W, cfg, raw, args, j_resident=js)
+        extra["stream"] = stream_leg(F, W, cfg, raw, args, total_steps, j_resident=js)
         extra["stream"]["vs_resident"] = round(extra["stream"]["value"] / value, 3)
 
     if not args.no_fp64 and args.precision == "mixed":
         log("FP64 path on the same workload")
         r64 = Run(F, cfg, raw, "fp64", args.block, args.spl, args.compact, args.sort)
-        res64 = timed(r64, args.steps, args.chunk)
+        res64 = timed(r64, K, chunk, total=total_steps)
         r64.close()
         del r64
         extra["fp64_value"] = res64["particle_steps"] / (res64["ms"] / 1e3)
         extra["mixed_over_fp64"] = round(value / extra["fp64_value"], 3)
-        b64 = 8 * T_s * F_fields * 8 + 2 * 64 / args.spl
-        extra["fp64_roofline_frac"] = round(b64 * res64["particle_steps"] / (res64["kernel_ms"] / 1e3) / 1e9
-                                            / HBM_PEAK_GBS, 4)
+        kern64 = "k_step<double,false,0,false,false,true,false>"
+        c64 = read_counters("k_step_cir_fp64_counters.txt", kern64)
+        if c64 is not None:
+            nl64 = max(res64["launches"], 1)
+            ls64 = res64["kernel_ms"] / 1e3 / nl64
+            ps64 = res64["particle_steps"] / nl64
+            v64 = c64["valu_insts_per_particle_step"] * ps64 / ls64
+            h64 = c64["hbm_bytes_per_particle_step"] * ps64 / ls64 / 1e9
+            extra["fp64_roofline"] = dict(kernel=kern64, avg_launch_ms=round(ls64 * 1e3, 4),
+                                          valu_frac=round(v64 / VALU_PEAK, 4), hbm_frac=round(h64 / HBM_PEAK_GBS, 4),
+                                          traffic=round(c64["hbm_bytes_per_particle_step"] * ps64))
 
     if not args.no_grad:
         log("differentiation workload: forward, smoothed forward, gradient, central differences")
@@ -722,30 +748,33 @@ def main():
         extra["paper"] = paper_leg(F, W, args)
 
     if not args.no_largest:
-        log("largest workload: shocked CIR, 3 levels, 96 snapshots, 10^8-particle store, first 24 h")
+        log("largest workload: shocked CIR, 3 levels, 96 snapshots, 10^8 particles")
         extra["largest"] = largest_leg(F, W, args, hours=args.largest_hours)
 
     cpu = None
     if not args.no_cpu:
-        n_threads = min(16, len(os.sched_getaffinity(0)))
-        log(f"oracle CPU baseline on {n_threads} threads")
-        cpu = cpu_baseline(cfg, raw, args.cpu_pids, args.cpu_steps, n_threads)
+        info = cpu_info()
+        n_all = min(16, info["affinity"])      # the host CPU share of one GPU
+        log(f"oracle CPU baseline on 1 and {n_all} threads ({info['cpu_model']}, nproc {info['nproc']})")
+        one, allc = cpu_baseline(cfg, raw, [(args.cpu_pids_1, args.cpu_steps, 1),
+                                            (args.cpu_pids, args.cpu_steps, n_all)])
+        cpu = dict(allc, single_thread=dict(value=one["value"], sample=one["sample"]), **info)
 
     out = {
         "metric": "pseudo-particle steps/s on 1 MI355X (mixed vs FP64); adjoint/forward cost",
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": res["ms"] / args.steps,
+        "ms_per_step": res["ms"] / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": cfg["name"], "particles": args.particles, "global_steps": args.steps * args.chunk,
-                   "chunk": args.chunk, "snapshots": g["n_snap"], "leaves": int(len(g["leaves"])),
+        "config": {"workload": cfg["name"], "particles": args.particles, "global_steps": res["global_steps"],
+                   "chunk": chunk, "snapshots": g["n_snap"], "leaves": int(len(g["leaves"])),
                    "levels": g["n_levels"], "precision": args.precision, "block": args.block,
                    "steps_per_launch": args.spl, "compact_every": args.compact, "spatial_sort": args.sort},
         "roofline": roof,

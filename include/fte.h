@@ -423,6 +423,16 @@ fte_status fte_set_timing(fte_ctx *ctx, int enable);
  * 1, 2, 3 sort by cubes of 1, 2, 4 cells per edge.  Defaults 256 / 32 / 128 / 2. */
 fte_status fte_set_launch(fte_ctx *ctx, int block, int steps_per_launch, int compact_every, int spatial_sort);
 
+/* LDS record tile of the float (FTE_MIXED) step kernels on time-dependent
+ * grids: each workgroup stages whole padded k-layers of one leaf for both
+ * live snapshots in LDS, as many as tile_bytes holds (at least two layers,
+ * else no tile), and reads the corners that lie in it from LDS instead of
+ * through the cache.  Values, weights and summation order are those of the
+ * global gather, so trajectories do not depend on it.  0 turns it off;
+ * default 61440, at most FTE_MAX_TILE_BYTES.  FTE_EINVAL outside 0..max. */
+#define FTE_MAX_TILE_BYTES 131072
+fte_status fte_set_record_tile(fte_ctx *ctx, int tile_bytes);
+
 /* Self-tuning of the launch shape: from the current state, run trial_steps
  * global steps under each candidate (block size x compaction interval, steps
  * per launch fixed), timing the step and compaction kernels with HIP events,

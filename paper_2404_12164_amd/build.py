@@ -9,8 +9,6 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfte.so")
 SOURCES = ["fte_api.hip", "fte_kernels.hip"]
 HEADERS = ["fte_internal.hpp", "fte_device.hpp"]
-PROBE_SRC = "l1_probe.hip"          # measurement aid for bench.py, its own library
-PROBE_LIB = os.path.join(HERE, "libl1probe.so")
 
 
 def hipcc():
@@ -39,21 +37,7 @@ def build(verbose: bool = False, defines=(), out: str = None) -> str:
     os.replace(tmp, lib)
     for o in objs:
         os.remove(o)
-    if out is None:
-        build_probe(verbose)
     return lib
-
-
-def build_probe(verbose: bool = False) -> str:
-    """The L1 lookup-rate probe that bench.py runs beside the step kernel."""
-    tmp = PROBE_LIB + ".tmp"
-    cmd = [hipcc(), "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-Wall",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", os.path.join(CSRC, PROBE_SRC), "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, PROBE_LIB)
-    return PROBE_LIB
 
 
 if __name__ == "__main__":

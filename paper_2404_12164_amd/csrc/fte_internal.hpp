@@ -118,7 +118,8 @@ enum : int { kTanLnw = 10, kTanLnwP = 11, kTanCols = 13 };
 // modes, single runs and ensembles, with or without cross-field records) on
 // time-dependent grids stage, per workgroup, whole padded k-layers of one leaf for both
 // live snapshots in LDS (as many as FTE_LDS_TILE_BYTES holds, at least two;
-// 0 turns it off), anchored at the workgroup's middle particle; corners that
+// 0 turns it off; fte_set_record_tile sets it at run time), anchored at the
+// workgroup's middle particle; corners that
 // lie in it are read from LDS, the others through the L1.  After the spatial
 // sort a workgroup's particles sit in few k-layers of one leaf, and LDS serves
 // such divergent reads several times faster than the L1.
@@ -179,7 +180,7 @@ hipError_t launch_inject(const DevParams &p, const DevGrid &g, int rec_fp32, con
 hipError_t launch_add_live(DevCounters *cnt, int slot, uint64_t n, hipStream_t s);
 hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
                        double *hist, double *sm, uint64_t n0, uint32_t n_steps, uint64_t n_upper, int block, int fp32,
-                       hipStream_t s);
+                       size_t tile_bytes, hipStream_t s);
 hipError_t launch_compact(DevState src, DevState dst, DevTan tsrc, DevTan tdst, DevCounters *cnt, int from,
                           uint64_t n_upper, int block, hipStream_t s);
 hipError_t launch_zero_live(DevCounters *cnt, int slot, hipStream_t s);

@@ -1538,17 +1538,17 @@ StepLds plan_step_lds(const DevParams &p, const DevGrid &g, uint64_t n0, uint32_
 
 hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
                        double *hist, double *sm, uint64_t n0, uint32_t n_steps, uint64_t n_upper, int block, int fp32,
-                       hipStream_t s) {
+                       size_t tile_bytes, hipStream_t s) {
     if (n_upper == 0 || n_steps == 0) return hipSuccess;
     const bool kp = p.kperp_any != 0;
     dim3 grid(blocks_for(n_upper, block)), blk(block);
     size_t shmem = 0;
     bool lidx = false;
     StepLds ld = plan_step_lds(p, g, n0, n_steps, &shmem, &lidx);
-    if (fp32 && !lidx && g.n_snap >= 2 && !(p.layer_k0dt > 0.0) && kLdsTileBytes > 0) {
+    if (fp32 && !lidx && g.n_snap >= 2 && !(p.layer_k0dt > 0.0) && tile_bytes > 0) {
         // as many whole padded k-layers of both snapshots as fit, at least two
         const size_t layer_bytes = (size_t)g.px[0] * g.px[1] * (kp ? kRSKperp : kRSPlain) * sizeof(float);
-        size_t tl = kLdsTileBytes / (2 * layer_bytes);
+        size_t tl = tile_bytes / (2 * layer_bytes);
         if (tl > (size_t)g.px[2]) tl = (size_t)g.px[2];
         if (tl >= 2) {
             ld.tile_off = (int)((shmem + 15) & ~(size_t)15);

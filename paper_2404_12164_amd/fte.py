@@ -30,7 +30,7 @@ SYMBOLS = ["fte_create", "fte_destroy", "fte_last_error", "fte_query_sizes", "ft
            "fte_inject", "fte_step_n", "fte_bin_observers", "fte_read_hist", "fte_get_stats", "fte_read_particles",
            "fte_set_launch", "fte_reset", "fte_set_timing", "fte_bin_smoothed", "fte_grad", "fte_read_tangents",
            "fte_state_size", "fte_save_state", "fte_load_state", "fte_autotune", "fte_bin_steady",
-           "fte_load_snapshot"]
+           "fte_load_snapshot", "fte_set_record_tile"]
 TANGENT_COLS = 13         # d(x, y, z, mu, lnp)/d lambda_ref, the same for kperp_ratio, d ln w / d gamma_inj,
 #                           d ln w / d lambda_ref, d ln w / d kperp_ratio
 
@@ -121,6 +121,7 @@ def lib():
         L.fte_read_particles.argtypes = [vp, dp, dp, dp, dp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32),
                                          C.POINTER(C.c_int32), u64, C.POINTER(C.c_uint64), vp]
         L.fte_set_launch.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.fte_set_record_tile.argtypes = [vp, C.c_int]
         L.fte_reset.argtypes = [vp, vp]
         L.fte_set_timing.argtypes = [vp, C.c_int]
         L.fte_bin_smoothed.argtypes = [vp, dp, dp, vp]
@@ -407,6 +408,10 @@ def fte_set_launch(ctx, block: int, steps_per_launch: int, compact_every: int, s
     _check(ctx, lib().fte_set_launch(ctx, int(block), int(steps_per_launch), int(compact_every), int(spatial_sort)))
 
 
+def fte_set_record_tile(ctx, tile_bytes: int):
+    _check(ctx, lib().fte_set_record_tile(ctx, int(tile_bytes)))
+
+
 def fte_reset(ctx, stream: int):
     _check(ctx, lib().fte_reset(ctx, C.c_void_p(stream)))
 
@@ -489,6 +494,9 @@ class Simulation:
 
     def set_launch(self, block=256, steps_per_launch=32, compact_every=128, spatial_sort=2):
         fte_set_launch(self.ctx, block, steps_per_launch, compact_every, spatial_sort)
+
+    def set_record_tile(self, tile_bytes):
+        fte_set_record_tile(self.ctx, tile_bytes)
 
     def reset(self):
         fte_reset(self.ctx, self.stream)

@@ -1,5 +1,5 @@
 """bench.py host logic: the one-GPU guard and the rule that committed counter
-figures apply only to the kernel source and run shape they were taken on."""
+figures apply only to the kernel source and instance they were taken on."""
 import json
 import os
 import subprocess
@@ -20,19 +20,26 @@ def test_more_than_one_gpu_is_refused():
     assert line["n_gpus"] == 2 and "one GPU" in line["error"]
 
 
-def _profile(tmp_path, sha, algo):
+def _profile(tmp_path, sha, kernel):
     d = tmp_path / "profiles"
     d.mkdir()
-    (d / "p.txt").write_text(f"# header: not a value\nkernel_source_sha256_16: {sha}\n"
-                             f"bench_algo_bytes_per_launch: {algo}\nhbm_bytes_per_launch: 1.5e10\n")
+    (d / "p.txt").write_text(f"# header: not a value\nkernel_source_sha256_16: {sha}\nkernel: {kernel}\n"
+                             f"hbm_bytes_per_particle_step: 250.5\nvalu_insts_per_particle_step: 21.0\n")
     return d
 
 
-@pytest.mark.parametrize("same_source,algo,want", [(True, 1.0e11, 1.5e10), (True, 1.005e11, 1.5e10),
-                                                   (True, 1.2e11, None), (False, 1.0e11, None)])
-def test_counters_apply_only_to_their_run(tmp_path, monkeypatch, same_source, algo, want):
-    sha = bench.kernel_source_hash() if same_source else "0000000000000000"
-    _profile(tmp_path, sha, 1.0e11)
+@pytest.mark.parametrize("same_source,same_kernel", [(True, True), (True, False), (False, True)])
+def test_counters_apply_only_to_their_kernel(tmp_path, monkeypatch, same_source, same_kernel):
+    """Committed counter figures are per particle-step (so they apply to any
+    number of bench steps) and only to the kernel source and instance they
+    were taken on."""
+    sha = "1234567890abcdef"
+    k = "k_step<float,false,0,false,false,true,false>"
+    _profile(tmp_path, sha, k)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: sha if same_source else "ffffffffffffffff")
-    assert bench.read_traffic("p.txt", algo) == want
+    got = bench.read_counters("p.txt", k if same_kernel else "k_step<double,false,0,false,false,true,false>")
+    if same_source and same_kernel:
+        assert got["hbm_bytes_per_particle_step"] == 250.5 and got["valu_insts_per_particle_step"] == 21.0
+    else:
+        assert got is None

@@ -52,11 +52,13 @@ def grad_case(precision="fp64"):
     return p, g, inj, raw, injs
 
 
-def gpu_grad_run(F, torch, p, g, raw, injs, n_steps, launch=(128, 25, 75, 2), chunks=None):
+def gpu_grad_run(F, torch, p, g, raw, injs, n_steps, launch=(128, 25, 75, 2), chunks=None, tile=None):
     n_tot = sum(n for _, n, _ in injs)
     sim = F.Simulation(p, g, n_tot)
     sim.load_grid(raw)
     sim.set_launch(*launch)
+    if tile is not None:
+        sim.set_record_tile(tile)
     for inj, n, first in injs:
         sim.inject(inj, n, first)
     for c in chunks or [n_steps]:
@@ -198,23 +200,39 @@ def test_gradient_matches_oracle_differences(F, torch_cuda, orc):
     sim.close()
 
 
-def test_gradient_launch_shape_invariance(F, torch_cuda):
-    """Tangents depend only on (pid, step): block size, launch length,
-    compaction and the spatial sort move them with their particles."""
-    p, g, inj, raw, injs = grad_case()
+@pytest.mark.parametrize("precision,grad", [("fp64", 1), ("mixed", 1), ("mixed", 0)])
+def test_gradient_launch_shape_invariance(F, torch_cuda, precision, grad):
+    """Tangents and smoothed sums depend only on (pid, step): block size,
+    launch length, compaction and the spatial sort move them with their
+    particles.  On the mixed path every launch shape also moves each
+    workgroup's LDS record tile (the tangent kernel's and, with grad = 0, the
+    smoothed forward kernel's), so this also checks the tile paths against
+    each other and against the tile switched off."""
+    p, g, inj, raw, injs = grad_case(precision)
+    p = dict(p, grad=grad)
     a = gpu_grad_run(F, torch_cuda, p, g, raw, injs, N_STEPS, launch=(256, 300, 0, 0))
     b = gpu_grad_run(F, torch_cuda, p, g, raw, injs, N_STEPS, launch=(64, 7, 21, 3), chunks=[13, 200, 87])
-    a["sim"].close()
-    b["sim"].close()
+    runs = [a, b]
+    if precision == "mixed":
+        c = gpu_grad_run(F, torch_cuda, p, g, raw, injs, N_STEPS, launch=(128, 25, 75, 2), tile=0)
+        runs.append(c)
+    for r in runs:
+        r["sim"].close()
     oa = np.argsort(a["parts"]["pid"])
-    ob = np.argsort(b["parts"]["pid"])
     ma = a["parts"]["status"][oa] == 0
-    mb = b["parts"]["status"][ob] == 0
-    pa, pb = a["parts"]["pid"][oa][ma], b["parts"]["pid"][ob][mb]
-    assert np.array_equal(pa, pb)
-    assert np.array_equal(a["tan"][oa][ma], b["tan"][ob][mb])
-    scale = np.abs(a["dJ"]).max()
-    assert np.allclose(a["dJ"], b["dJ"], rtol=1e-11, atol=1e-12 * scale)
+    for r in runs[1:]:
+        ob = np.argsort(r["parts"]["pid"])
+        mb = r["parts"]["status"][ob] == 0
+        assert np.array_equal(a["parts"]["pid"][oa][ma], r["parts"]["pid"][ob][mb])
+        for k in ("x", "mu", "lnp"):
+            assert np.array_equal(a["parts"][k][oa][ma], r["parts"][k][ob][mb]), k
+        if grad:
+            assert np.array_equal(a["tan"][oa][ma], r["tan"][ob][mb])
+        scale = np.abs(a["J"]).max()
+        assert np.allclose(a["J"], r["J"], rtol=1e-11, atol=1e-12 * scale)
+        if grad:
+            scale = np.abs(a["dJ"]).max()
+            assert np.allclose(a["dJ"], r["dJ"], rtol=1e-11, atol=1e-12 * scale)
 
 
 @pytest.mark.parametrize("kink", [0.0, -1.0])

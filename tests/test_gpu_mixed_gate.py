@@ -1,0 +1,226 @@
+"""The benchmark's own mixed-precision kernels against the FP64 oracle, by
+binned intensity (section 2.3: j = p^2 f at observers), on the full-size
+grids they run on.
+
+- CIR workload: the full 2-level grid (2,346 leaves, 48 snapshots), the
+  benchmark's launch shape (256 threads, 64 steps per launch, compaction with
+  a per-cell sort every 64 steps) and its float kernel with the unrolled
+  two-snapshot gather and the LDS record tile; 2,800 steps.
+- Largest workload: the 3-level shocked-CIR grid (2,880 leaves, 96
+  snapshots) with cross-field records (the tile's 14-float instance).
+
+Particles: 40 blocks of consecutive pids spread over those that start during
+the 2,800 steps, with the workload's own stratified continuous injection, so
+that the GPU and the oracle integrate the same pids under the same Philox
+streams.  Observers: the workload's own boxes plus boxes near the injection
+sphere that the particles reach within the run.  Gate: every nonzero bin
+within 3 standard errors (batch means of both sides) and the summed and L1
+differences within 1% of the oracle's total; per-trajectory drift quantiles
+are printed.
+
+Also: the LDS record tile switched off at run time gives bit-identical
+trajectories and equal sums on both grids (the tile path reads the same
+values with the same weights in the same order as the global gather)."""
+import math
+
+import numpy as np
+import pytest
+
+import fte_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+AU = W.AU
+DEG = W.DEG
+N_STEPS = 2800
+LAUNCH = (256, 64, 64, 1)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def F(torch_cuda):
+    from paper_2404_12164_amd import fte
+    fte.lib()
+    return fte
+
+
+def pid_blocks(cfg, n_blocks, per_block, n_steps):
+    """n_blocks runs of per_block consecutive pids, evenly spread over the
+    pids whose stratified first step falls before 0.9 n_steps."""
+    N, S = cfg["n_particles"], cfg["injection"]["n_inj_steps"]
+    j_hi = int(0.9 * n_steps * N / S)
+    starts = np.linspace(0, j_hi - per_block, n_blocks).astype(np.int64)
+    assert n_blocks == 1 or starts[1] - starts[0] >= per_block, "pid blocks overlap"
+    return [(int(s), per_block) for s in starts]
+
+
+def gpu_subset_run(F, torch, p, g, raw, inj, blocks, n_steps, tile=None, launch=LAUNCH):
+    n = sum(b for _, b in blocks)
+    sim = F.Simulation(p, g, n)
+    sim.load_grid(raw)
+    sim.set_launch(*launch)
+    if tile is not None:
+        sim.set_record_tile(tile)
+    for first, cnt in blocks:
+        sim.inject(inj, cnt, first)
+    left = n_steps
+    while left > 0:
+        k = min(564, left)
+        sim.step(k)
+        left -= k
+    torch.cuda.synchronize()
+    out = sim.particles()
+    sums, w = sim.read_hist()
+    st = sim.stats()
+    sim.close()
+    assert st.device_flags == 0
+    return out, sums, w, st
+
+
+def oracle_subset_run(orc, p64, g, raw, inj, blocks, n_steps):
+    k_hi = min(g["n_snap"] - 1, int(math.floor(n_steps * p64["dt"] / g["dt_s"])) + 2)
+    G = orc.Grid(g, raw[: k_hi + 1].cpu().numpy())
+    parts = [orc.inject(p64, inj, cnt, first) for first, cnt in blocks]
+    P = parts[0]
+    for q in parts[1:]:
+        for k in ("x", "mu", "lnp", "w", "pid", "kinj", "status"):
+            setattr(P, k, np.concatenate([getattr(P, k), getattr(q, k)]))
+    h = np.zeros(orc.hist_size(p64))
+    orc.run(p64, G, P, 0, n_steps, h)
+    return P, h
+
+
+def intensity_gate(orc, p64, got, sums, w, ref, h, tag):
+    jg, sg = orc.finalize(p64, sums, float(np.sum(w)))
+    jo, so = orc.finalize(p64, h, float(ref.w.sum()))
+    sig = np.sqrt(sg ** 2 + so ** 2)
+    m = (jo > 0) | (jg > 0)
+    n_nz = int(m.sum())
+    z = np.abs(jg - jo)[m] / np.maximum(sig[m], 1e-300)
+    tot = jg.sum() / jo.sum() - 1
+    l1 = np.abs(jg - jo).sum() / jo.sum()
+    # per-trajectory drift of the survivors common to both (same noise)
+    both = np.intersect1d(got["pid"][got["status"] == 0], ref.pid[ref.status == 0])
+    og, orf = np.argsort(got["pid"]), np.argsort(ref.pid)
+    gi = og[np.searchsorted(got["pid"][og], both)]
+    ri = orf[np.searchsorted(ref.pid[orf], both)]
+    dx = np.linalg.norm(got["x"][gi] - ref.x[ri], axis=1) / AU
+    dmu = np.abs(got["mu"][gi] - ref.mu[ri])
+    dl = np.abs(got["lnp"][gi] - ref.lnp[ri])
+    print(f"{tag}: {n_nz} nonzero bins, max z {z.max():.3f}, total {tot:+.2e}, L1 {l1:.2e}; "
+          f"survivors {len(both)} of {int((ref.status == 0).sum())}; drift median/p99 "
+          f"|dx| {np.median(dx):.2e}/{np.quantile(dx, 0.99):.2e} au, |dmu| {np.median(dmu):.2e}/"
+          f"{np.quantile(dmu, 0.99):.2e}, |dlnp| {np.median(dl):.2e}/{np.quantile(dl, 0.99):.2e}", flush=True)
+    assert n_nz > 200, n_nz
+    assert np.all(z < 3.0), z.max()
+    assert abs(tot) < 0.01 and l1 < 0.01, (tot, l1)
+    assert len(both) > 0.9 * (ref.status == 0).sum()
+    return z
+
+
+def cir_gate_params(cfg):
+    """The CIR workload's parameters with five more boxes near the injection
+    sphere (0.2 and 0.3 au on the equator) and 12 batches, so that the
+    histogram of a launch's time bins still fits the kernel's LDS budget."""
+    p = dict(cfg["params"])
+    near = [(r * AU, 90 * DEG, ph * DEG, 0.05 * AU, 20 * DEG, 20 * DEG) for r, ph in
+            ((0.2, 0), (0.2, 120), (0.2, 240), (0.3, 0), (0.3, 180))]
+    p["observers"] = list(p["observers"]) + near
+    p["n_batch"] = 12
+    return p
+
+
+def largest_gate_params(cfg):
+    """The largest workload's parameters: three of its observers (0.5, 1.0,
+    1.5 au) and three boxes near the injection sphere, 8 batches."""
+    p = dict(cfg["params"])
+    far = [ob for ob in p["observers"] if abs(ob[0] / AU - 0.75) > 0.01 and abs(ob[0] / AU - 1.25) > 0.01]
+    near = [(r * AU, 90 * DEG, ph * DEG, 0.05 * AU, 20 * DEG, 20 * DEG) for r, ph in
+            ((0.2, 0), (0.2, 180), (0.3, 90))]
+    p["observers"] = far + near
+    p["n_batch"] = 8
+    return p
+
+
+@pytest.fixture(scope="module")
+def cir(torch_cuda):
+    cfg = W.cir_time_dependent()
+    raw = W.make_raw(cfg["grid"], cfg["wind"], xp=torch_cuda, device=torch_cuda.device("cuda:0"))
+    yield cfg, raw
+    del raw
+    torch_cuda.cuda.empty_cache()
+
+
+def test_mixed_gate_cir(F, torch_cuda, orc, cir):
+    cfg, raw = cir
+    g, inj = cfg["grid"], cfg["injection"]
+    blocks = pid_blocks(cfg, 40, 400, N_STEPS)
+    pm = dict(cir_gate_params(cfg), precision="mixed")
+    print(f"CIR gate: {len(blocks)} pid blocks, {N_STEPS} steps", flush=True)
+    got, sums, w, st = gpu_subset_run(F, torch_cuda, pm, g, raw, inj, blocks, N_STEPS)
+    p64 = dict(pm, precision="fp64")
+    ref, h = oracle_subset_run(orc, p64, g, raw, inj, blocks, N_STEPS)
+    intensity_gate(orc, p64, got, sums, w, ref, h, "CIR mixed vs FP64 oracle")
+
+
+def test_record_tile_bit_identical_cir(F, torch_cuda, cir):
+    """The first 6 x 10^5 particles of the CIR workload, 1,280 steps: the
+    record tile on (the default, 3 of 18 k-layers) and off give identical
+    trajectories."""
+    cfg, raw = cir
+    g, inj = cfg["grid"], cfg["injection"]
+    blocks = pid_blocks(cfg, 1, 600_000, 1280)
+    pm = dict(cfg["params"], precision="mixed")
+    a = gpu_subset_run(F, torch_cuda, pm, g, raw, inj, blocks, 1280)
+    b = gpu_subset_run(F, torch_cuda, pm, g, raw, inj, blocks, 1280, tile=0)
+    assert_same_run(a, b)
+
+
+def assert_same_run(a, b):
+    (ga, sa, wa, sta), (gb, sb, wb, stb) = a, b
+    oa, ob = np.argsort(ga["pid"]), np.argsort(gb["pid"])
+    assert np.array_equal(ga["pid"][oa], gb["pid"][ob])
+    for k in ("x", "mu", "lnp", "w", "status"):
+        assert np.array_equal(ga[k][oa], gb[k][ob]), k
+    assert sta.particle_steps == stb.particle_steps
+    assert np.allclose(sa, sb, rtol=1e-12, atol=1e-12 * max(np.abs(sa).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def largest(torch_cuda):
+    cfg = W.cir_largest()
+    raw = W.make_raw(cfg["grid"], cfg["wind"], xp=torch_cuda, device=torch_cuda.device("cuda:0"))
+    yield cfg, raw
+    del raw
+    torch_cuda.cuda.empty_cache()
+
+
+def test_mixed_gate_largest(F, torch_cuda, orc, largest):
+    cfg, raw = largest
+    g, inj = cfg["grid"], cfg["injection"]
+    blocks = pid_blocks(cfg, 40, 300, N_STEPS)
+    pm = dict(largest_gate_params(cfg), precision="mixed")
+    print(f"largest gate: {len(blocks)} pid blocks, {N_STEPS} steps", flush=True)
+    got, sums, w, st = gpu_subset_run(F, torch_cuda, pm, g, raw, inj, blocks, N_STEPS, launch=(256, 64, 64, 1))
+    p64 = dict(pm, precision="fp64")
+    ref, h = oracle_subset_run(orc, p64, g, raw, inj, blocks, N_STEPS)
+    intensity_gate(orc, p64, got, sums, w, ref, h, "largest mixed vs FP64 oracle")
+
+
+def test_record_tile_bit_identical_largest(F, torch_cuda, largest):
+    """Cross-field records (14 floats): tile on and off give identical
+    trajectories on the 3-level grid, 10^6 particles, 1,152 steps."""
+    cfg, raw = largest
+    g, inj = cfg["grid"], cfg["injection"]
+    blocks = pid_blocks(cfg, 10, 100_000, 1152)
+    pm = dict(cfg["params"], precision="mixed")
+    a = gpu_subset_run(F, torch_cuda, pm, g, raw, inj, blocks, 1152)
+    b = gpu_subset_run(F, torch_cuda, pm, g, raw, inj, blocks, 1152, tile=0)
+    assert_same_run(a, b)
