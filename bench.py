@@ -382,6 +382,89 @@ def largest_leg(F, W, args, hours=None):
     return out
 
 
+def pool_leg(F, W, args, hours=12.0, wind_max=800e3):
+    """The largest workload over its first `hours` with the grid held as a
+    ring of 3 snapshot slots that each hold only the leaves the particles can
+    reach (fte_plan_snapshot: the held particles and the injection shell,
+    speeds up to 1.5 v_max + wind_max): per snapshot, the leaves the gather
+    may read, the leaves held and the leaves whose input is copied into the
+    load window (from device copies of the snapshot data standing in for
+    the snapshot files); the record bytes against a ring of whole snapshots
+    and the fully resident grid, and the input bytes copied against whole
+    snapshots; the throughput with the planning, copies and loads in the
+    timed region."""
+    import torch
+    dev = torch.device("cuda:0")
+    c = W.cir_largest(precision=args.precision)
+    g = c["grid"]
+    p = dict(c["params"], precision=args.precision)
+    inj = c["injection"]
+    N, S = c["n_particles"], inj["n_inj_steps"]
+    raw = W.make_raw(g, c["wind"], xp=torch, device=dev)     # stands in for the snapshot files
+    nl = len(g["leaves"])
+    cells = int(np.prod(g["bx"]))
+    per = int(round(g["dt_s"] / p["dt"]))
+    n_steps = min(c["n_steps"], int(hours * 3600 / p["dt"]))
+    gs = dict(g, n_slots=3, n_pool=nl)
+    sim = F.Simulation(p, gs, N)
+    sim.set_launch(args.block, args.spl, args.compact, args.sort)
+    sim.set_timing(True)
+    stage = torch.empty((5,) + tuple(raw.shape[1:]), dtype=torch.float64, device=dev)
+    counts, copied = [], 0
+    injected = [0]
+
+    def load(k):
+        # copy only the input leaves of snapshots k-2 .. k+2 into the window
+        leaves, cnt = sim.plan_snapshot(k, [inj], wind_max)
+        counts.append(cnt)
+        idx = torch.from_numpy(leaves.astype(np.int64)).to(dev)
+        nonlocal copied
+        for j in range(max(0, k - 2), min(g["n_snap"], k + 3)):
+            stage[j - k + 2].index_copy_(0, idx, raw[j].index_select(0, idx))
+            copied += len(leaves) * cells * 48
+        ptrs = [stage[i].data_ptr() if 0 <= k - 2 + i < g["n_snap"] else 0 for i in range(5)]
+        F.fte_load_snapshot(sim.ctx, k, ptrs, sim.stream)
+
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    load(0)
+    load(1)
+    done = 0
+    while done < n_steps:
+        k = done // per
+        if k > 0 and done % per == 0 and k + 1 < g["n_snap"]:
+            load(k + 1)
+        m = min((k + 1) * per, n_steps) - done
+        n1 = done + m
+        j_max = min(N, int(math.ceil(n1 * N / S)) + 1)
+        if j_max > injected[0]:
+            sim.inject(inj, j_max - injected[0], injected[0])
+            injected[0] = j_max
+        sim.step(m)
+        done = n1
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    st = sim.stats()
+    rec_ring_pool = F.fte_query_sizes(p, dict(gs, n_pool=max(cc[1] for cc in counts)), N).grid_bytes
+    rec_ring_full = F.fte_query_sizes(p, dict(g, n_slots=3), N).grid_bytes
+    rec_full = F.fte_query_sizes(p, g, N).grid_bytes
+    sim.close()
+    del stage, raw
+    torch.cuda.empty_cache()
+    frac = [round(cc[0] / nl, 3) for cc in counts]
+    return dict(workload=c["name"], hours=hours, global_steps=n_steps, leaves=nl, snapshots_loaded=len(counts),
+                gather_leaves_min_max=[min(cc[0] for cc in counts), max(cc[0] for cc in counts)],
+                held_leaves_max=max(cc[1] for cc in counts), input_leaves_max=max(cc[2] for cc in counts),
+                gather_fraction_per_snapshot=frac, device_flags=int(st.device_flags),
+                record_bytes_pool_at_peak=int(rec_ring_pool), record_bytes_ring_whole=int(rec_ring_full),
+                record_bytes_resident=int(rec_full), input_bytes_copied=int(copied),
+                input_bytes_whole_snapshots=int(len(counts) * 5 * nl * cells * 48),
+                particle_steps=int(st.particle_steps), ms=round(ms, 1),
+                value=st.particle_steps / (ms / 1e3))
+
+
 def paper_leg(F, W, args, levels=(1, 2, 3)):
     """The paper's own experiment (section 2.3) on the synthetic CIR in its
     corotating frame: a Green's-function run of 10^6 protons of 1 MeV injected
@@ -590,6 +673,7 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble workload")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's CIR experiment at 1-3 AMR levels")
     ap.add_argument("--no-stream", action="store_true", help="skip the snapshot-streaming run of the CIR workload")
+    ap.add_argument("--no-pool", action="store_true", help="skip the leaf-pool streaming run of the largest workload")
     ap.add_argument("--cpu-pids", type=int, default=4000)
     ap.add_argument("--cpu-pids-1", type=int, default=250, help="pids of the single-thread oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=2800)
@@ -750,6 +834,10 @@ def main():
     if not args.no_largest:
         log("largest workload: shocked CIR, 3 levels, 96 snapshots, 10^8 particles")
         extra["largest"] = largest_leg(F, W, args, hours=args.largest_hours)
+
+    if not args.no_pool:
+        log("largest workload, first 12 h, ring of 3 slots holding only the reachable leaves")
+        extra["pool"] = pool_leg(F, W, args)
 
     cpu = None
     if not args.no_cpu:

@@ -202,6 +202,11 @@ typedef struct {
     int n_slots;          /* snapshot records held on the device: 0 (or >= n_snap)
                              all of them (fte_load_grid); 2 .. n_snap-1 a ring
                              that fte_load_snapshot fills as the run advances  */
+    int n_pool;           /* with a ring: 0 holds every leaf of each snapshot;
+                             1 .. n_leaves holds at most that many leaf blocks
+                             per slot, only those fte_plan_snapshot finds the
+                             particles can reach (section 4: load only the
+                             blocks that are needed)                          */
 } fte_grid_desc;
 
 /* Particle source for fte_inject (the synthetic workloads' injection; with
@@ -266,7 +271,9 @@ typedef struct {
                                  the weight the absorbing layers removed at
                                  r_in (index 1) and r_out (index 2)             */
     uint64_t global_step;     /* next global step index                         */
-    uint32_t device_flags;    /* nonzero: a kernel met an unsupported case      */
+    uint32_t device_flags;    /* nonzero: a kernel met an unsupported case (bit
+                                 8: a step reached a leaf a streamed subset
+                                 does not hold)                                 */
     uint32_t step_launches;   /* step-kernel launches timed since the last reset */
     double step_kernel_ms;    /* their summed duration (HIP events on `stream`) */
 } fte_stats;
@@ -328,6 +335,32 @@ fte_status fte_load_grid(fte_ctx *ctx, const double *vb_sph, void *stream);
  * Synchronises. */
 fte_status fte_load_snapshot(fte_ctx *ctx, int k, const double *const raw[5], void *stream);
 
+/* Loading only the blocks the particles can reach (section 4 names this as
+ * the remedy for the cost of reading whole snapshots).  With n_pool > 0,
+ * snapshot k is loaded in two calls: this one decides which leaves its slot
+ * holds, then fte_load_snapshot derives them.  Snapshot k serves the steps
+ * between snapshots k-1 and k+1; over the time from the current clock to
+ * snapshot k+1 a particle moves at most (1.5 v_max + wind_speed_max) times
+ * that time, v_max the speed of the fastest held particle or source (1.5 an
+ * allowance for acceleration).  The level-1 blocks within that distance of a
+ * level-1 block holding a held particle (active or not yet started) or
+ * overlapping a source region (each fte_injection: radius r, or r .. r_hi
+ * with region = 1, x [th_lo, th_hi] x [ph_lo, ph_hi], energies up to e_hi)
+ * hold the gather's set C of leaves; C and the leaves the ghost layers of C
+ * read (within three cells of the next coarser level) are held; those and
+ * the leaves their own ghost fill reads are the leaves whose input the load
+ * reads.  counts[0..2] receive the leaves of
+ * the three sets; leaves_out (HOST, may be NULL) the ids of the last, in
+ * increasing order, so that the caller copies only their blocks into the
+ * raw arrays of fte_load_snapshot (other leaves of those arrays are not
+ * read).  FTE_ENOMEM when more than n_pool leaves must be held; FTE_EINVAL
+ * without a pool.  A step that still reaches a leaf outside C retires the
+ * particle as FTE_PS_NUMERIC and raises bit 8 of fte_stats.device_flags.
+ * Not combined with smoothing, ensembles or absorbing layers.
+ * Synchronises. */
+fte_status fte_plan_snapshot(fte_ctx *ctx, int k, const fte_injection *sources, int n_sources, double wind_speed_max,
+                             int32_t *leaves_out, uint64_t cap, uint64_t counts[3], void *stream);
+
 /* Append n particles with pids first_pid .. first_pid+n-1 drawn from `inj`
  * (see fte_injection).  Requires a loaded grid.  FTE_ENOMEM if the state
  * capacity would be exceeded. */
@@ -346,6 +379,18 @@ fte_status fte_step_n(fte_ctx *ctx, uint32_t n_steps, void *stream);
  * (either may be NULL); for an ensemble [run][o][e][t] with each run's own
  * W_inj.  reset != 0 clears the sums afterwards.  Synchronises. */
 fte_status fte_bin_observers(fte_ctx *ctx, double *j, double *sigma, int reset, void *stream);
+
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): fte_bin_observers with
+ * the finalize output staged in a fixed device array the library holds
+ * (2 x FTE_STATIC_BINS doubles, 4 MiB, on every GPU it runs on, until the
+ * process ends) instead of the context's work buffer; same results and
+ * arguments.  Allocates nothing.  FTE_EINVAL when the context has more than
+ * FTE_STATIC_BINS observer bins (n_obs_bins * n_e * n_t, times the runs of
+ * an ensemble).  Calls on one GPU share that array: calls that overlap in
+ * time on one GPU (from several threads or streams) race.  Synchronises. */
+#define FTE_STATIC_BINS 262144
+fte_status fte_bin_observers_static(fte_ctx *ctx, double *j, double *sigma, int reset, void *stream);
 
 /* Steady state of a Green's-function run (all particles started at one
  * time; section 2.3): the time integral of the intensity, J[o][e] =

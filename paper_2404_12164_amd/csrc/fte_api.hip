@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -23,6 +24,17 @@ struct fte_ctx {
     DevParams dp{};
     bool bound = false, loaded = false, index_ready = false;
     std::vector<int> slot_snap;    // snapshot resident in each record slot (-1: none)
+    // streamed subset of leaves (n_pool > 0): the plan of each slot
+    struct SlotPlan {
+        int snap = -1;
+        std::vector<int32_t> map;          // [leaf]: pool block, -2 - block (neighbour only) or -1
+        std::vector<int32_t> held, gather; // leaves held (pool order) and those the gather may read
+        std::vector<int32_t> input;        // leaves whose input the load reads
+    };
+    std::vector<SlotPlan> plans;
+    int32_t *d_lists = nullptr;    // device: held, gather and input lists of the load in progress
+    double *scratch = nullptr;     // this device's copy of the static finalize scratch
+    uint32_t *d_occ = nullptr;     // device: level-1 block occupancy + the largest ln p (last entry)
     fte_grid_desc g{};
     std::vector<int32_t> leaves, base, child, info;
     DevGrid dg{};
@@ -178,7 +190,7 @@ std::string build_index(const fte_grid_desc *g, std::vector<int32_t> &base, std:
         return "grid origin and widths must be > 0";
     if (g->n_levels < 1 || g->n_levels > FTE_MAX_LEVELS) return "n_levels out of range";
     for (int a = 0; a < 3; ++a) {
-        if (g->bx[a] < 4 || (g->bx[a] & 1)) return "block cells must be even and >= 4";
+        if (g->bx[a] < 4 || (g->bx[a] & 1) || g->bx[a] > 64) return "block cells must be even, 4 .. 64";
         if (g->n_levels >= 3 && (g->bx[a] & 3)) return "block cells must be divisible by 4 with >= 3 levels";
         if (g->n1[a] < g->bx[a] || g->n1[a] % g->bx[a]) return "n1 must be a positive multiple of bx";
         if ((long)g->n1[a] << (g->n_levels - 1) > (1L << 26)) return "grid too fine";
@@ -190,6 +202,8 @@ std::string build_index(const fte_grid_desc *g, std::vector<int32_t> &base, std:
         return "n_slots must be 0, >= 2, and streaming needs n_snap >= 3";
     if (g->n_snap >= 2 && !finite_pos(g->dt_s)) return "dt_s must be > 0";
     if (g->n_leaves < 1 || !g->leaves) return "no leaves";
+    if (g->n_pool < 0 || g->n_pool > g->n_leaves) return "n_pool must be 0 .. n_leaves";
+    if (g->n_pool > 0 && !(g->n_slots > 0 && g->n_slots < g->n_snap)) return "n_pool needs a snapshot ring (n_slots < n_snap)";
     const int nb1[3] = {g->n1[0] / g->bx[0], g->n1[1] / g->bx[1], g->n1[2] / g->bx[2]};
     const long nbase = (long)nb1[0] * nb1[1] * nb1[2];
     const int32_t EMPTY = INT_MIN;
@@ -266,7 +280,8 @@ int slots_of(const fte_grid_desc *g) { return (g->n_slots <= 0 || g->n_slots >= 
 
 struct Layout {
     size_t grid, index, state, hist, work, tangent;
-    size_t off_child, off_info;
+    size_t off_child, off_info, off_map;
+    size_t off_lists, off_occ;
     size_t off_j, off_s, off_cart, off_keys, off_counts, off_tsum;
     size_t off_sm, off_fin_sm, off_dl, off_out4, sm_n, off_runs;
     uint32_t n_keys;
@@ -274,14 +289,21 @@ struct Layout {
     int rs;
 };
 
+// Most keys of the spatial sort for a live-particle bound n: four per
+// particle (at least 2^16, at most 2^31), so that a compaction's work is
+// O(particles) whatever the grid's cell count.
+uint64_t sort_key_bound(uint64_t n) { return std::min<uint64_t>(std::max<uint64_t>(4 * n, 1ull << 16), 1ull << 31); }
+
 Layout layout(const fte_params *p, const fte_grid_desc *g, uint64_t n_max, size_t n_base, size_t n_child) {
     Layout L{};
     L.pcells = (g->bx[0] + 2) * (g->bx[1] + 2) * (g->bx[2] + 2);
     L.rs = needs_kperp(p) ? kRSKperp : kRSPlain;
-    L.grid = (size_t)slots_of(g) * g->n_leaves * L.pcells * L.rs * rec_elem(p);
+    const size_t n_blk = g->n_pool > 0 ? (size_t)g->n_pool : (size_t)g->n_leaves;
+    L.grid = (size_t)slots_of(g) * n_blk * L.pcells * L.rs * rec_elem(p);
     L.off_child = align256(n_base * 4);
     L.off_info = L.off_child + align256(std::max<size_t>(n_child, 8) * 4);
-    L.index = L.off_info + align256((size_t)g->n_leaves * 16);
+    L.off_map = L.off_info + align256((size_t)g->n_leaves * 16);
+    L.index = L.off_map + (g->n_pool > 0 ? align256((size_t)slots_of(g) * g->n_leaves * 4) : 0);
     L.state = state_bytes(n_max);
     const size_t nbins = (size_t)p->n_obs * p->n_e * p->n_t;          // smoothed (box observers)
     const size_t nbr = (size_t)obs_bins(p) * p->n_e * p->n_t * runs_eff(p);
@@ -291,7 +313,10 @@ Layout layout(const fte_params *p, const fte_grid_desc *g, uint64_t n_max, size_
     L.off_s = L.off_j + align256(std::max<size_t>(nbr, 1) * 8);
     L.off_cart = L.off_s + align256(std::max<size_t>(nbr, 1) * 8);
     L.off_keys = L.off_cart + align256((size_t)g->n_leaves * L.pcells * 6 * 8);
-    L.n_keys = (uint32_t)((size_t)g->n_leaves * g->bx[0] * g->bx[1] * g->bx[2]);   // finest sort key
+    // sort keys: the finest key space (one per leaf cell), bounded by the
+    // particle capacity (see sort_key_bound)
+    L.n_keys = (uint32_t)std::min<uint64_t>((uint64_t)g->n_leaves * g->bx[0] * g->bx[1] * g->bx[2],
+                                            sort_key_bound(n_max));
     L.off_counts = L.off_keys + align256(n_max * 4);
     L.off_tsum = L.off_counts + align256(((size_t)L.n_keys + 1) * 4);
     L.off_sm = L.off_tsum + align256(((size_t)L.n_keys / 4096 + 2) * 4);
@@ -304,7 +329,9 @@ Layout layout(const fte_params *p, const fte_grid_desc *g, uint64_t n_max, size_
     L.off_fin_sm = L.off_sm + align256(L.sm_n * 8);
     L.off_dl = L.off_fin_sm + align256(p->sigma_x > 0.0 ? 4 * nbins * 8 : 0);
     L.off_out4 = L.off_dl + align256(p->sigma_x > 0.0 ? nbins * 8 : 0);
-    L.work = L.off_out4 + 256;
+    L.off_lists = L.off_out4 + 256;
+    L.off_occ = L.off_lists + (g->n_pool > 0 ? align256((size_t)3 * g->n_leaves * 4) : 0);
+    L.work = L.off_occ + (g->n_pool > 0 ? align256((n_base + 1) * 4) : 0);
     L.tangent = p->grad ? tangent_bytes(n_max) : 0;
     return L;
 }
@@ -370,6 +397,18 @@ void make_devparams(const fte_params *p, DevParams *d) {
         d->obs_omega[o] = ob.omega;
         d->obs_off[o] = d->n_obs_bins;
         d->n_obs_bins += d->obs_nphi[o];
+    }
+    // the smallest radial x colatitude box holding every observer box (a
+    // particle outside it is in none)
+    d->obs_u[0] = d->obs_u[2] = d->obs_u[4] = HUGE_VAL;
+    d->obs_u[1] = d->obs_u[3] = d->obs_u[5] = -HUGE_VAL;
+    for (int o = 0; o < p->n_obs; ++o) {
+        d->obs_u[0] = std::min(d->obs_u[0], d->obs[o][0]);
+        d->obs_u[1] = std::max(d->obs_u[1], d->obs[o][1]);
+        d->obs_u[2] = std::min(d->obs_u[2], d->obs_rsq[o][0]);
+        d->obs_u[3] = std::max(d->obs_u[3], d->obs_rsq[o][1]);
+        d->obs_u[4] = std::min(d->obs_u[4], d->obs[o][2]);
+        d->obs_u[5] = std::max(d->obs_u[5], d->obs[o][3]);
     }
     d->seed = p->seed;
     d->dmm_model = p->dmm_model;
@@ -453,6 +492,35 @@ DevState state_view(void *base, uint64_t n) {
 
 }  // namespace fte
 
+// Scratch of fte_bin_observers_static: the finalize kernel's output (j, then
+// sigma) staged on the device before the copy to the caller's host arrays,
+// in a file-scope array instead of the caller's work buffer.  Every GPU the
+// library runs on holds its own copy until the process ends; its address on
+// each device is looked up once, with that device current, and kept.
+static __device__ __align__(256) double scratch[2 * FTE_STATIC_BINS];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double *> g_scratch_of;   // by device id (nullptr: not looked up yet)
+
+// The current device's address of `scratch` (looked up on first use).
+hipError_t scratch_address(double **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_of.size() <= dev) g_scratch_of.resize(dev + 1, nullptr);
+    if (!g_scratch_of[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_of[dev] = (double *)ptr;
+    }
+    *out = g_scratch_of[dev];
+    return hipSuccess;
+}
+}  // namespace
+
 extern "C" {
 
 fte_status fte_create(fte_ctx **out, const fte_params *p) {
@@ -475,6 +543,12 @@ fte_status fte_create(fte_ctx **out, const fte_params *p) {
         return FTE_EDEVICE;
     }
     if (hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(c->pinned);
+        delete c;
+        return FTE_EDEVICE;
+    }
+    if (scratch_address(&c->scratch) != hipSuccess) {
+        (void)hipEventDestroy(c->ev);
         (void)hipHostFree(c->pinned);
         delete c;
         return FTE_EDEVICE;
@@ -521,6 +595,8 @@ fte_status fte_bind_buffers(fte_ctx *c, const fte_grid_desc *g, uint64_t n_max, 
     if (c->p.grad && (!b->tangent_a || !b->tangent_b || ((uintptr_t)b->tangent_a & 255) ||
                       ((uintptr_t)b->tangent_b & 255)))
         return fail(c, FTE_EINVAL, "gradient mode needs 256-byte aligned tangent buffers");
+    if (g->n_pool > 0 && (c->p.sigma_x > 0.0 || c->p.n_runs > 0 || (c->p.absorb_layer > 0.0 && c->p.absorb_rate > 0.0)))
+        return fail(c, FTE_EINVAL, "a streamed subset (n_pool) is not combined with smoothing, ensembles or absorbing layers");
     const Layout L = layout(&c->p, g, n_max, base.size(), child.size());
     c->g = *g;
     c->leaves.assign(g->leaves, g->leaves + 4 * (size_t)g->n_leaves);
@@ -575,6 +651,7 @@ fte_status fte_bind_buffers(fte_ctx *c, const fte_grid_desc *g, uint64_t n_max, 
         d.bx[a] = g->bx[a];
         d.px[a] = g->bx[a] + 2;
         d.nb1[a] = g->n1[a] / g->bx[a];
+        d.bx_mag[a] = (uint32_t)((0x100000000ull + g->bx[a] - 1) / g->bx[a]);
     }
     d.n_levels = g->n_levels;
     d.n_leaves = g->n_leaves;
@@ -591,6 +668,11 @@ fte_status fte_bind_buffers(fte_ctx *c, const fte_grid_desc *g, uint64_t n_max, 
     d.rec = b->grid;
     d.rs = L.rs;
     d.nf = L.rs == kRSKperp ? kNF : 10;
+    d.n_blk = g->n_pool > 0 ? g->n_pool : g->n_leaves;
+    d.pool_map = g->n_pool > 0 ? (const int32_t *)(ix + L.off_map) : nullptr;
+    c->plans.assign(g->n_pool > 0 ? d.n_slots : 0, fte_ctx::SlotPlan{});
+    c->d_lists = g->n_pool > 0 ? (int32_t *)(w + L.off_lists) : nullptr;
+    c->d_occ = g->n_pool > 0 ? (uint32_t *)(w + L.off_occ) : nullptr;
     c->bound = true;
     c->loaded = false;
     c->index_ready = false;
@@ -612,6 +694,13 @@ static fte_status setup_grid(fte_ctx *c, hipStream_t s) {
     if (!c->child.empty())
         HIPCHK(c, hipMemcpyAsync((void *)d.child, c->child.data(), c->child.size() * 4, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync((void *)d.leaf_info, c->info.data(), c->info.size() * 4, hipMemcpyHostToDevice, s));
+    if (d.pool_map) {
+        // no leaf held in any slot until its snapshot is loaded
+        c->plans.assign(d.n_slots, fte_ctx::SlotPlan{});
+        std::vector<int32_t> none((size_t)d.n_slots * d.n_leaves, -1);
+        HIPCHK(c, hipMemcpyAsync((void *)d.pool_map, none.data(), none.size() * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
     HIPCHK(c, launch_zero_counters(c->cnt, s));
     if (c->hist_n) HIPCHK(c, launch_zero((double *)c->b.hist, c->hist_n, s));
     if (c->sm_n) HIPCHK(c, launch_zero(c->sm, c->sm_n, s));
@@ -639,12 +728,13 @@ static fte_status setup_grid(fte_ctx *c, hipStream_t s) {
 }
 
 // Ghost fill, derived fields and record ghost fill of snapshot w.k into its slot.
-static fte_status derive_snapshot(fte_ctx *c, const RawWin &w, hipStream_t s) {
+static fte_status derive_snapshot(fte_ctx *c, const RawWin &w, hipStream_t s, LeafList held = LeafList{nullptr, 0},
+                                  LeafList gath = LeafList{nullptr, 0}) {
     const DevGrid &d = c->dg;
     const int fp32 = c->p.precision == FTE_MIXED;
-    HIPCHK(c, launch_raw_ghost(d, w, c->cart, c->cnt, s));
-    HIPCHK(c, launch_derive(d, w, c->cart, c->b.grid, fp32, s));
-    HIPCHK(c, launch_record_ghost(d, w.k % d.n_slots, c->b.grid, fp32, c->cnt, s));
+    HIPCHK(c, launch_raw_ghost(d, w, c->cart, c->cnt, held, s));
+    HIPCHK(c, launch_derive(d, w, c->cart, c->b.grid, fp32, held, s));
+    HIPCHK(c, launch_record_ghost(d, w.k % d.n_slots, c->b.grid, fp32, c->cnt, gath, s));
     return FTE_OK;
 }
 
@@ -653,12 +743,13 @@ static fte_status input_flags(fte_ctx *c, hipStream_t s) {
     unsigned int flags = 0;
     HIPCHK(c, hipMemcpyAsync(&flags, &c->cnt->flags, sizeof(flags), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
-    if (flags & (kFlagBadInput | kFlagAmrDepth)) {
+    if (flags & (kFlagBadInput | kFlagAmrDepth | kFlagNotResident)) {
         HIPCHK(c, launch_zero_counters(c->cnt, s));
         HIPCHK(c, hipStreamSynchronize(s));
         c->loaded = false;
         c->index_ready = false;
         if (flags & kFlagBadInput) return fail(c, FTE_EINVAL, "wind data hold non-finite values or |B| = 0");
+        if (flags & kFlagNotResident) return fail(c, FTE_EINVAL, "the ghost rule read a leaf the pool does not hold");
         return fail(c, FTE_EINVAL, "block-boundary rule needed more than one coarser level");
     }
     return FTE_OK;
@@ -702,6 +793,216 @@ fte_status fte_load_grid(fte_ctx *c, const double *vb, void *stream) {
     return FTE_OK;
 }
 
+namespace {
+
+// Cartesian bounding sphere of level-1 block (I, J, K): centre and radius
+// from a 5 x 5 x 5 sample of the (xi, theta, phi) box, with 2% margin.
+void block_sphere(const fte_grid_desc &g, int I, int J, int K, double c[3], double *rad) {
+    double pts[125][3];
+    int n = 0;
+    for (int a = 0; a < 5; ++a)
+        for (int b = 0; b < 5; ++b)
+            for (int e = 0; e < 5; ++e) {
+                const double xi = (I + a / 4.0) * g.bx[0] * g.dxi;
+                const double r = g.xi_map ? g.r_lo * exp(xi) : g.r_lo + xi;
+                const double th = g.th_lo + (J + b / 4.0) * g.bx[1] * g.dth;
+                const double ph = g.ph_lo + (K + e / 4.0) * g.bx[2] * g.dph;
+                pts[n][0] = r * sin(th) * cos(ph);
+                pts[n][1] = r * sin(th) * sin(ph);
+                pts[n][2] = r * cos(th);
+                ++n;
+            }
+    c[0] = c[1] = c[2] = 0.0;
+    for (int q = 0; q < n; ++q)
+        for (int a = 0; a < 3; ++a) c[a] += pts[q][a] / n;
+    double m = 0.0;
+    for (int q = 0; q < n; ++q) {
+        const double dx = pts[q][0] - c[0], dy = pts[q][1] - c[1], dz = pts[q][2] - c[2];
+        m = std::max(m, sqrt(dx * dx + dy * dy + dz * dz));
+    }
+    *rad = 1.02 * m;
+}
+
+bool ranges_overlap(double a0, double a1, double b0, double b1) { return a0 <= b1 && a1 >= b0; }
+
+}  // namespace
+
+extern "C" {
+
+fte_status fte_plan_snapshot(fte_ctx *c, int k, const fte_injection *sources, int n_sources, double wind_speed_max,
+                             int32_t *leaves_out, uint64_t cap, uint64_t counts[3], void *stream) {
+    if (!c) return FTE_EINVAL;
+    if (!c->bound) return fail(c, FTE_ESTATE, "bind buffers before planning snapshots");
+    const DevGrid &d = c->dg;
+    if (!d.pool_map) return fail(c, FTE_EINVAL, "the grid holds every leaf (n_pool = 0): nothing to plan");
+    if (k < 0 || k >= d.n_snap) return fail(c, FTE_EINVAL, "snapshot index out of range");
+    if (n_sources < 0 || (n_sources > 0 && !sources)) return fail(c, FTE_EINVAL, "bad source list");
+    if (!(wind_speed_max >= 0.0) || !isfinite(wind_speed_max)) return fail(c, FTE_EINVAL, "wind_speed_max must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    if (!c->index_ready) {
+        fte_status r = setup_grid(c, s);
+        if (r != FTE_OK) return r;
+    }
+    const fte_grid_desc &g = c->g;
+    const int nb[3] = {d.nb1[0], d.nb1[1], d.nb1[2]};
+    const int n_base = nb[0] * nb[1] * nb[2];
+    // level-1 blocks holding a held particle, and the fastest of them
+    std::vector<uint32_t> occ((size_t)n_base + 1, 0u);
+    HIPCHK(c, hipMemcpyAsync(c->d_occ, occ.data(), occ.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, launch_occupancy(d, c->st[c->cur], c->cnt, c->cur, c->n_upper, c->d_occ, c->d_occ + n_base, s));
+    HIPCHK(c, hipMemcpyAsync(occ.data(), c->d_occ, occ.size() * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    double P_max = 0.0;
+    if (occ[n_base]) {
+        float pos;
+        memcpy(&pos, &occ[n_base], 4);
+        P_max = exp((double)pos - 80.0);
+    }
+    const double mc2 = c->p.mass * kC * kC;
+    for (int q = 0; q < n_sources; ++q) {
+        const double eps = sources[q].e_hi / mc2;
+        if (eps > 0.0) P_max = std::max(P_max, sqrt(eps * (eps + 2.0)));
+    }
+    const double v_max = kC * P_max / sqrt(1.0 + P_max * P_max);
+    // snapshot k serves the steps from snapshot k-1 to k+1
+    const double t_end = d.t_s0 + std::min(k + 1, d.n_snap - 1) * d.dt_s;
+    const double t_now = c->p.t0 + (double)c->global_step * c->p.dt;
+    const double horizon = std::max(t_end - t_now, 0.0) + c->p.dt;
+    const double reach = (std::min(1.5 * v_max, kC) + wind_speed_max) * horizon;
+    // seeds: occupied blocks and blocks overlapping a source region
+    std::vector<double> cen((size_t)n_base * 3), rad(n_base);
+    std::vector<char> seed(n_base, 0);
+    for (int K = 0; K < nb[2]; ++K)
+        for (int J = 0; J < nb[1]; ++J)
+            for (int I = 0; I < nb[0]; ++I) {
+                const int b = I + nb[0] * (J + nb[1] * K);
+                block_sphere(g, I, J, K, &cen[3 * (size_t)b], &rad[b]);
+                if (occ[b]) seed[b] = 1;
+                const double xi0 = I * g.bx[0] * g.dxi, xi1 = (I + 1) * g.bx[0] * g.dxi;
+                const double r0 = g.xi_map ? g.r_lo * exp(xi0) : g.r_lo + xi0;
+                const double r1 = g.xi_map ? g.r_lo * exp(xi1) : g.r_lo + xi1;
+                const double t0 = g.th_lo + J * g.bx[1] * g.dth, t1 = t0 + g.bx[1] * g.dth;
+                const double p0 = g.ph_lo + K * g.bx[2] * g.dph, p1 = p0 + g.bx[2] * g.dph;
+                for (int q = 0; q < n_sources && !seed[b]; ++q) {
+                    const fte_injection &src = sources[q];
+                    const double ra = src.r, rb = src.region ? std::max(src.r_hi, src.r) : src.r;
+                    if (!ranges_overlap(ra, rb, r0, r1) || !ranges_overlap(src.th_lo, src.th_hi, t0, t1)) continue;
+                    bool ph_ok = src.ph_hi - src.ph_lo >= 2 * kPi;
+                    for (double sh : {-2 * kPi, 0.0, 2 * kPi}) ph_ok |= ranges_overlap(src.ph_lo + sh, src.ph_hi + sh, p0, p1);
+                    if (ph_ok) seed[b] = 1;
+                }
+            }
+    std::vector<int> seeds;
+    for (int b = 0; b < n_base; ++b)
+        if (seed[b]) seeds.push_back(b);
+    // blocks within reach of a seed (3: the gather set)
+    std::vector<char> lvl(n_base, 0);
+    for (int b = 0; b < n_base; ++b) {
+        if (seed[b]) {
+            lvl[b] = 3;
+            continue;
+        }
+        for (int q : seeds) {
+            const double dx = cen[3 * (size_t)b] - cen[3 * (size_t)q], dy = cen[3 * (size_t)b + 1] - cen[3 * (size_t)q + 1],
+                         dz = cen[3 * (size_t)b + 2] - cen[3 * (size_t)q + 2];
+            if (sqrt(dx * dx + dy * dy + dz * dz) <= reach + rad[b] + rad[q]) {
+                lvl[b] = 3;
+                break;
+            }
+        }
+    }
+    // Leaves: the gather set holds the leaves under the level-1 blocks in
+    // reach.  The ghost layer of a level-L leaf reads virtual values at its
+    // ghost cell centres, which at a coarser neighbour interpolate level-(L-1)
+    // values up to 2.5 level-L cells outside the leaf: every leaf within 3
+    // level-(L-1) cells (one level-1 cell for L = 1) must be held, and the
+    // input of each held leaf's own ghost fill reads as far again.
+    const int F = g.n_levels;
+    const int nper = d.periodic ? d.n1[2] << (F - 1) : 0;   // finest phi cells of a periodic grid
+    auto leaf_range = [&](int l, long lo[3], long hi[3], long *e) {
+        const int32_t *q = &c->info[4 * (size_t)l];
+        const int L = q[0];
+        for (int a2 = 0; a2 < 3; ++a2) {
+            const long w = (long)g.bx[a2] << (F - L);
+            lo[a2] = (long)q[1 + a2] * w;
+            hi[a2] = lo[a2] + w;
+        }
+        *e = L >= 2 ? 3L << (F - L + 1) : 1L << (F - 1);
+    };
+    auto near = [&](int la, int lb) {   // lb within la's reach
+        long lo[3], hi[3], lo2[3], hi2[3], e, e2;
+        leaf_range(la, lo, hi, &e);
+        leaf_range(lb, lo2, hi2, &e2);
+        for (int a2 = 0; a2 < 2; ++a2)
+            if (!(lo[a2] - e < hi2[a2] && hi[a2] + e > lo2[a2])) return false;
+        bool ok = lo[2] - e < hi2[2] && hi[2] + e > lo2[2];
+        if (nper) ok = ok || (lo[2] - e < hi2[2] + nper && hi[2] + e > lo2[2] + nper) ||
+                       (lo[2] - e < hi2[2] - nper && hi[2] + e > lo2[2] - nper);
+        return ok;
+    };
+    std::vector<std::vector<int>> in_block(n_base);
+    std::vector<int> anc(d.n_leaves);
+    for (int l = 0; l < d.n_leaves; ++l) {
+        const int32_t *e = &c->info[4 * (size_t)l];
+        const int sh = e[0] - 1;
+        anc[l] = (e[1] >> sh) + nb[0] * ((e[2] >> sh) + nb[1] * (e[3] >> sh));
+        in_block[anc[l]].push_back(l);
+    }
+    // the leaves within reach of any leaf of `from`: candidates in the 27
+    // level-1 blocks around each
+    auto grow = [&](const std::vector<char> &from) {
+        std::vector<char> out = from;
+        for (int la = 0; la < d.n_leaves; ++la) {
+            if (!from[la]) continue;
+            const int b = anc[la];
+            const int I = b % nb[0], J = (b / nb[0]) % nb[1], K = b / (nb[0] * nb[1]);
+            for (int dk = -1; dk <= 1; ++dk)
+                for (int dj = -1; dj <= 1; ++dj)
+                    for (int di = -1; di <= 1; ++di) {
+                        int i2 = I + di, j2 = J + dj, k2 = K + dk;
+                        if (i2 < 0 || i2 >= nb[0] || j2 < 0 || j2 >= nb[1]) continue;
+                        if (k2 < 0 || k2 >= nb[2]) {
+                            if (!d.periodic) continue;
+                            k2 = (k2 + nb[2]) % nb[2];
+                        }
+                        for (int lb : in_block[i2 + nb[0] * (j2 + nb[1] * k2)])
+                            if (!out[lb] && near(la, lb)) out[lb] = 1;
+                    }
+        }
+        return out;
+    };
+    std::vector<char> in_c(d.n_leaves, 0);
+    for (int l = 0; l < d.n_leaves; ++l) in_c[l] = lvl[anc[l]] == 3;
+    const std::vector<char> in_h = grow(in_c);
+    const std::vector<char> in_i = grow(in_h);
+    fte_ctx::SlotPlan pl;
+    pl.snap = k;
+    pl.map.assign(d.n_leaves, -1);
+    for (int l = 0; l < d.n_leaves; ++l) {
+        if (in_i[l]) pl.input.push_back(l);
+        if (in_h[l]) {
+            const int blk = (int)pl.held.size();
+            pl.held.push_back(l);
+            pl.map[l] = in_c[l] ? blk : -2 - blk;
+            if (in_c[l]) pl.gather.push_back(l);
+        }
+    }
+    if ((int)pl.held.size() > c->g.n_pool)
+        return fail(c, FTE_ENOMEM, "the particles can reach " + std::to_string(pl.held.size()) +
+                                       " leaves, more than n_pool = " + std::to_string(c->g.n_pool));
+    if (leaves_out && cap < pl.input.size()) return fail(c, FTE_ENOMEM, "leaves_out holds fewer than the input leaves");
+    if (counts) {
+        counts[0] = pl.gather.size();
+        counts[1] = pl.held.size();
+        counts[2] = pl.input.size();
+    }
+    if (leaves_out) memcpy(leaves_out, pl.input.data(), pl.input.size() * 4);
+    c->plans[k % d.n_slots] = std::move(pl);
+    return FTE_OK;
+}
+
+}  // extern "C"
+
 fte_status fte_load_snapshot(fte_ctx *c, int k, const double *const raw[5], void *stream) {
     if (!c) return FTE_EINVAL;
     if (!c->bound) return fail(c, FTE_ESTATE, "bind buffers before loading snapshots");
@@ -721,8 +1022,24 @@ fte_status fte_load_snapshot(fte_ctx *c, int k, const double *const raw[5], void
         fte_status r = setup_grid(c, s);
         if (r != FTE_OK) return r;
     }
-    HIPCHK(c, launch_check_raw(d, raw[2], 1, c->cnt, s));
-    fte_status r = derive_snapshot(c, w, s);
+    fte_status r;
+    if (d.pool_map) {
+        // a streamed subset: the slot holds the leaves its plan chose
+        fte_ctx::SlotPlan &pl = c->plans[k % d.n_slots];
+        if (pl.snap != k) return fail(c, FTE_ESTATE, "plan snapshot k (fte_plan_snapshot) before loading it");
+        const int nh = (int)pl.held.size(), ng = (int)pl.gather.size(), ni = (int)pl.input.size();
+        HIPCHK(c, hipMemcpyAsync((void *)(d.pool_map + (size_t)(k % d.n_slots) * d.n_leaves), pl.map.data(),
+                                 pl.map.size() * 4, hipMemcpyHostToDevice, s));
+        if (nh) HIPCHK(c, hipMemcpyAsync(c->d_lists, pl.held.data(), (size_t)nh * 4, hipMemcpyHostToDevice, s));
+        if (ng) HIPCHK(c, hipMemcpyAsync(c->d_lists + nh, pl.gather.data(), (size_t)ng * 4, hipMemcpyHostToDevice, s));
+        if (ni)
+            HIPCHK(c, hipMemcpyAsync(c->d_lists + nh + ng, pl.input.data(), (size_t)ni * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(c, launch_check_raw_leaves(d, raw[2], c->cnt, LeafList{c->d_lists + nh + ng, ni}, s));
+        r = derive_snapshot(c, w, s, LeafList{c->d_lists, nh}, LeafList{c->d_lists + nh, ng});
+    } else {
+        HIPCHK(c, launch_check_raw(d, raw[2], 1, c->cnt, s));
+        r = derive_snapshot(c, w, s);
+    }
     if (r != FTE_OK) return r;
     r = input_flags(c, s);
     if (r != FTE_OK) return r;
@@ -863,8 +1180,9 @@ fte_status fte_step_n(fte_ctx *c, uint32_t n_steps, void *stream) {
         if (c->compact_every > 0 && c->since_compact >= (uint64_t)c->compact_every) {
             const int to = 1 - c->cur;
             if (c->sort) {
-                HIPCHK(c, launch_compact_sorted(c->dg, c->sort, c->st[c->cur], c->st[to], c->tn[c->cur], c->tn[to],
-                                                c->cnt, c->cur, c->n_upper, c->keys, c->counts, c->tsum, s));
+                const SortShape K = sort_shape_for(c->dg, c->sort, std::min<uint64_t>(c->n_keys, sort_key_bound(c->n_upper)));
+                HIPCHK(c, launch_compact_sorted(c->dg, K, c->st[c->cur], c->st[to], c->tn[c->cur], c->tn[to], c->cnt,
+                                                c->cur, c->n_upper, c->keys, c->counts, c->tsum, s));
             } else {
                 HIPCHK(c, launch_zero_live(c->cnt, to, s));
                 HIPCHK(c, launch_compact(c->st[c->cur], c->st[to], c->tn[c->cur], c->tn[to], c->cnt, c->cur,
@@ -891,6 +1209,24 @@ fte_status fte_bin_observers(fte_ctx *c, double *j, double *sigma, int reset, vo
         HIPCHK(c, launch_finalize(c->dp, (const double *)c->b.hist, c->cnt, c->fin_j, c->fin_s, s));
         if (j) HIPCHK(c, hipMemcpyAsync(j, c->fin_j, nb * 8, hipMemcpyDeviceToHost, s));
         if (sigma) HIPCHK(c, hipMemcpyAsync(sigma, c->fin_s, nb * 8, hipMemcpyDeviceToHost, s));
+        if (reset) HIPCHK(c, launch_zero((double *)c->b.hist, c->hist_n, s));
+    }
+    HIPCHK(c, hipStreamSynchronize(s));
+    return FTE_OK;
+}
+
+fte_status fte_bin_observers_static(fte_ctx *c, double *j, double *sigma, int reset, void *stream) {
+    if (!c) return FTE_EINVAL;
+    if (!c->loaded) return fail(c, FTE_ESTATE, "nothing to bin before the grid is loaded");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = (size_t)obs_bins(&c->p) * c->p.n_e * c->p.n_t * runs_eff(&c->p);
+    if (nb > FTE_STATIC_BINS)
+        return fail(c, FTE_EINVAL, std::to_string(nb) + " bins exceed the static scratch of " +
+                                       std::to_string(FTE_STATIC_BINS) + "; use fte_bin_observers");
+    if (nb > 0) {
+        HIPCHK(c, launch_finalize(c->dp, (const double *)c->b.hist, c->cnt, c->scratch, c->scratch + FTE_STATIC_BINS, s));
+        if (j) HIPCHK(c, hipMemcpyAsync(j, c->scratch, nb * 8, hipMemcpyDeviceToHost, s));
+        if (sigma) HIPCHK(c, hipMemcpyAsync(sigma, c->scratch + FTE_STATIC_BINS, nb * 8, hipMemcpyDeviceToHost, s));
         if (reset) HIPCHK(c, launch_zero((double *)c->b.hist, c->hist_n, s));
     }
     HIPCHK(c, hipStreamSynchronize(s));

@@ -97,6 +97,14 @@ struct M<float> {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int ncell(const DevGrid &G, int L, int a) { return G.n1[a] << (L - 1); }
 
+// c / bx[a] for 0 <= c: the high word of c ceil(2^32 / bx).  With
+// e = ceil(2^32 / bx) - 2^32 / bx in [0, 1) the product exceeds c / bx by
+// c e / 2^32 < 1 / bx as long as c bx < 2^32 (cell indices below 2^26, blocks
+// of at most 64 cells), so the floor is exact.
+__device__ __forceinline__ int div_bx(const DevGrid &G, int c, int a) {
+    return (int)__umulhi((uint32_t)c, G.bx_mag[a]);
+}
+
 // Bring a level-L index into the domain: clamp xi and theta, wrap a periodic phi.
 __device__ __forceinline__ void fold(const DevGrid &G, int L, int c[3]) {
 #pragma unroll
@@ -119,7 +127,7 @@ __device__ __forceinline__ int find_leaf_cell(const DevGrid &G, int L, const int
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         cc[a] = c[a] >> (L - 1);
-        B[a] = cc[a] / G.bx[a];
+        B[a] = div_bx(G, cc[a], a);
     }
     int node = G.base[B[0] + G.nb1[0] * (B[1] + G.nb1[1] * B[2])];
     int m = 1;
@@ -131,7 +139,7 @@ __device__ __forceinline__ int find_leaf_cell(const DevGrid &G, int L, const int
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             cc[a] = (m <= L) ? (c[a] >> (L - m)) : (c[a] << (m - L));
-            const int Bn = cc[a] / G.bx[a];
+            const int Bn = div_bx(G, cc[a], a);
             slot |= (Bn & 1) << a;
         }
         node = G.child[grp * 8 + slot];

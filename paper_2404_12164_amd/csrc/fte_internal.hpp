@@ -41,6 +41,7 @@ struct DevParams {
     double obs_omega[FTE_MAX_OBS];   // rotation of each observer's pattern
     double obs_rsq[FTE_MAX_OBS][2];  // squared radial edges r1^2, r2^2
     int obs_nphi[FTE_MAX_OBS];       // longitude bins per observer
+    double obs_u[6];                 // union of the observer boxes: r1, r2, r1^2, r2^2, th1, th2
     int obs_off[FTE_MAX_OBS];        // its first observer bin
     int n_obs_bins;
     // kernel-smoothed intensities (smooth != 0)
@@ -76,6 +77,7 @@ struct DevGrid {
     double t_s0, inv_dt_s, dt_s;
     int xi_map, periodic;
     int n1[3], bx[3], px[3];     // level-1 cells, block cells, padded block cells
+    uint32_t bx_mag[3];          // ceil(2^32 / bx): c / bx as the high word of c * bx_mag
     int nb1[3];                  // level-1 blocks per dimension
     int n_levels, n_leaves, n_snap, n_base, n_child;
     int n_slots;                 // snapshot record slots held (snapshot k in slot k mod n_slots)
@@ -84,9 +86,24 @@ struct DevGrid {
     const int32_t *base;         // [nb1 product] node codes (>=0 leaf, <0 -(group+1))
     const int32_t *child;        // [n_groups][8] node codes
     const int32_t *leaf_info;    // [n_leaves][4] level, I, J, K
-    const void *rec;             // records [snap][leaf][pcell][rs]
+    const void *rec;             // records [slot][block][pcell][rs]
     int rs, nf;                  // record stride and stored fields (10/10 or 14/13)
+    // Record blocks per slot: n_leaves (block = leaf id) or, when a subset of
+    // leaves is streamed, the pool size n_pool with pool_map[slot][leaf] =
+    // the leaf's block in that slot's pool (>= 0: resident and valid for the
+    // gather; -2 - block: held only as a neighbour for the ghost fill; -1:
+    // not held).  pool_map is NULL when every leaf is held.
+    int n_blk;
+    const int32_t *pool_map;
 };
+
+// Pool block of a leaf in a slot (any held block, also a neighbour-only one),
+// or -1.
+__host__ __device__ inline int pool_block(const DevGrid &g, int slot, int leaf) {
+    if (!g.pool_map) return leaf;
+    const int v = g.pool_map[(size_t)slot * g.n_leaves + leaf];
+    return v >= 0 ? v : (v <= -2 ? -2 - v : -1);
+}
 
 // Particle state (struct of arrays, capacity n_max).
 struct DevState {
@@ -154,7 +171,7 @@ struct DevCounters {
     double w_inj_dgamma;     // sum of w d ln w / d gamma_inj
 };
 
-enum : unsigned int { kFlagAmrDepth = 1u, kFlagBadInput = 2u, kFlagNoLeaf = 4u };
+enum : unsigned int { kFlagAmrDepth = 1u, kFlagBadInput = 2u, kFlagNoLeaf = 4u, kFlagNotResident = 8u };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -170,11 +187,23 @@ struct RawWin {
     const double *s[5];
     int k;
 };
-hipError_t launch_raw_ghost(const DevGrid &g, const RawWin &w, double *work_cart, DevCounters *cnt, hipStream_t s);
-hipError_t launch_derive(const DevGrid &g, const RawWin &w, const double *work_cart, void *rec, int fp32,
+// A list of leaves the load kernels work on (NULL: every leaf).
+struct LeafList {
+    const int32_t *ids;
+    int n;
+};
+hipError_t launch_raw_ghost(const DevGrid &g, const RawWin &w, double *work_cart, DevCounters *cnt, LeafList ll,
+                            hipStream_t s);
+hipError_t launch_derive(const DevGrid &g, const RawWin &w, const double *work_cart, void *rec, int fp32, LeafList ll,
                          hipStream_t s);
-hipError_t launch_record_ghost(const DevGrid &g, int snap, void *rec, int fp32, DevCounters *cnt, hipStream_t s);
+hipError_t launch_record_ghost(const DevGrid &g, int snap, void *rec, int fp32, DevCounters *cnt, LeafList ll,
+                               hipStream_t s);
 hipError_t launch_check_raw(const DevGrid &g, const double *raw, size_t n_snaps, DevCounters *cnt, hipStream_t s);
+hipError_t launch_check_raw_leaves(const DevGrid &g, const double *raw, DevCounters *cnt, LeafList ll, hipStream_t s);
+// Level-1 blocks that hold a live particle (occ[base block] = 1) and the
+// largest ln p among them (as the ordered bits of a float in *lnp_bits).
+hipError_t launch_occupancy(const DevGrid &g, DevState st, const DevCounters *cnt, int slot, uint64_t n_upper,
+                            uint32_t *occ, uint32_t *lnp_bits, hipStream_t s);
 hipError_t launch_inject(const DevParams &p, const DevGrid &g, int rec_fp32, const fte_injection &inj, DevState st,
                          DevTan tn, DevCounters *cnt, int slot, uint64_t n, uint64_t first_pid, hipStream_t s);
 hipError_t launch_add_live(DevCounters *cnt, int slot, uint64_t n, hipStream_t s);
@@ -184,10 +213,17 @@ hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevTan
 hipError_t launch_compact(DevState src, DevState dst, DevTan tsrc, DevTan tdst, DevCounters *cnt, int from,
                           uint64_t n_upper, int block, hipStream_t s);
 hipError_t launch_zero_live(DevCounters *cnt, int slot, hipStream_t s);
-uint32_t sort_keys_for(const DevGrid &g, int sort);
-hipError_t launch_compact_sorted(const DevGrid &g, int sort, DevState src, DevState dst, DevTan tsrc, DevTan tdst,
-                                 DevCounters *cnt, int from, uint64_t n_upper, uint32_t *keys, uint32_t *counts,
-                                 uint32_t *tsum, hipStream_t s);
+// Key space of the spatial sort: (leaf >> leaf_shift, cube of 2^cube_shift
+// cells per edge), n_keys keys, h[] cubes per block axis.
+struct SortShape {
+    int cube_shift, leaf_shift;
+    int h[3];
+    uint32_t n_sub, n_keys;
+};
+SortShape sort_shape_for(const DevGrid &g, int sort, uint64_t max_keys);
+hipError_t launch_compact_sorted(const DevGrid &g, const SortShape &K, DevState src, DevState dst, DevTan tsrc,
+                                 DevTan tdst, DevCounters *cnt, int from, uint64_t n_upper, uint32_t *keys,
+                                 uint32_t *counts, uint32_t *tsum, hipStream_t s);
 hipError_t launch_finalize(const DevParams &p, const double *hist, const DevCounters *cnt, double *j, double *sig,
                            hipStream_t s);
 hipError_t launch_finalize_steady(const DevParams &p, const double *hist, const DevCounters *cnt, double *j,

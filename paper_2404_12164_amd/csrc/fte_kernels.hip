@@ -43,17 +43,20 @@ struct RawSrc {
     }
 };
 
-// records: [snap][leaf][pcell][rs] of R, interior at padded offset +1
+// records: [slot][block][pcell][rs] of R, interior at padded offset +1; the
+// block of a leaf through the grid's pool map when a subset is held (a leaf
+// not held reads as NaN, which the caller flags)
 template <typename R>
 struct RecSrc {
     const R *p;
-    const int32_t *leaf_info;
-    int snap, n_leaves, pcells, px0, px1, bx0, bx1, bx2, rs, nf;
+    const DevGrid *g;
+    int snap, pcells, px0, px1, bx0, bx1, bx2, rs, nf;
     __device__ void mean_cube(int leaf, const int cm[3], int k, double out[kNF]) const {
-        const int4 li = reinterpret_cast<const int4 *>(leaf_info)[leaf];
+        const int4 li = reinterpret_cast<const int4 *>(g->leaf_info)[leaf];
         const int l0 = cm[0] - li.y * bx0, l1 = cm[1] - li.z * bx1, l2 = cm[2] - li.w * bx2;
+        const int blk = pool_block(*g, snap, leaf);
         for (int q = 0; q < kNF; ++q) out[q] = 0.0;
-        if (l0 < 0 || l1 < 0 || l2 < 0 || l0 + k > bx0 || l1 + k > bx1 || l2 + k > bx2) {
+        if (blk < 0 || l0 < 0 || l1 < 0 || l2 < 0 || l0 + k > bx0 || l1 + k > bx1 || l2 + k > bx2) {
             for (int q = 0; q < kNF; ++q) out[q] = __builtin_nan("");
             return;
         }
@@ -61,7 +64,7 @@ struct RecSrc {
             for (int c1 = 0; c1 < k; ++c1)
                 for (int c0 = 0; c0 < k; ++c0) {
                     const size_t pc = (l0 + c0 + 1) + (size_t)px0 * ((l1 + c1 + 1) + (size_t)px1 * (l2 + c2 + 1));
-                    const R *src = p + (((size_t)snap * n_leaves + leaf) * pcells + pc) * rs;
+                    const R *src = p + (((size_t)snap * g->n_blk + blk) * pcells + pc) * rs;
                     for (int q = 0; q < nf; ++q) out[q] += (double)src[q];
                 }
         const double inv = 1.0 / (double)(k * k * k);
@@ -114,10 +117,11 @@ __device__ __forceinline__ const double *raw_at(const RawWin &W, int j) { return
 // Padded Cartesian (V, b) of one snapshot: interior cells from the input,
 // ghost cells by the block-boundary rule, then rotated with the angles of the
 // (folded) cell centre.
-__global__ void k_raw_ghost(DevGrid G, RawWin W, double *cart, DevCounters *cnt) {
+__global__ void k_raw_ghost(DevGrid G, RawWin W, double *cart, DevCounters *cnt, LeafList ll) {
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (size_t)G.n_leaves * G.pcells) return;
-    const int leaf = (int)(gid / G.pcells), pc = (int)(gid % G.pcells);
+    const int nl = ll.ids ? ll.n : G.n_leaves;
+    if (gid >= (size_t)nl * G.pcells) return;
+    const int leaf = ll.ids ? ll.ids[gid / G.pcells] : (int)(gid / G.pcells), pc = (int)(gid % G.pcells);
     int L, c[3], loc[3];
     decode_pcell(G, leaf, pc, &L, c, loc);
     double v[6];
@@ -159,11 +163,12 @@ __device__ __forceinline__ void cart_v_input(const DevGrid &G, const double *sna
 // uniform (xi, theta, phi) spacing (one-sided at physical edges), chain rule
 // with the analytic Jacobian at the centre, explicit dV/dt across snapshots.
 template <typename R>
-__global__ void k_derive(DevGrid G, RawWin W, const double *cart, R *rec) {
+__global__ void k_derive(DevGrid G, RawWin W, const double *cart, R *rec, LeafList ll) {
     const int snap = W.k;
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (size_t)G.n_leaves * G.cells) return;
-    const int leaf = (int)(gid / G.cells);
+    const int nl = ll.ids ? ll.n : G.n_leaves;
+    if (gid >= (size_t)nl * G.cells) return;
+    const int leaf = ll.ids ? ll.ids[gid / G.cells] : (int)(gid / G.cells);
     const int idx = (int)(gid % G.cells);
     const int loc[3] = {idx % G.bx[0], (idx / G.bx[0]) % G.bx[1], idx / (G.bx[0] * G.bx[1])};
     const int4 li = reinterpret_cast<const int4 *>(G.leaf_info)[leaf];
@@ -248,7 +253,8 @@ __global__ void k_derive(DevGrid G, RawWin W, const double *cart, R *rec) {
 
     const double *s = raw_at(W, snap) + ((size_t)leaf * G.cells + idx) * 6;
     const double Bn = ::sqrt(s[3] * s[3] + s[4] * s[4] + s[5] * s[5]);
-    R *out = rec + (((size_t)(snap % G.n_slots) * G.n_leaves + leaf) * G.pcells + pc) * G.rs;
+    const int slot = snap % G.n_slots;
+    R *out = rec + (((size_t)slot * G.n_blk + pool_block(G, slot, leaf)) * G.pcells + pc) * G.rs;
     out[0] = (R)s[0];
     out[1] = (R)s[1];
     out[2] = (R)s[2];
@@ -266,22 +272,29 @@ __global__ void k_derive(DevGrid G, RawWin W, const double *cart, R *rec) {
 
 // Ghost layer of the records by the block-boundary rule.
 template <typename R>
-__global__ void k_record_ghost(DevGrid G, int slot, R *rec, DevCounters *cnt) {
+__global__ void k_record_ghost(DevGrid G, int slot, R *rec, DevCounters *cnt, LeafList ll) {
     const int snap = slot;    // records are addressed by slot
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (size_t)G.n_leaves * G.pcells) return;
-    const int leaf = (int)(gid / G.pcells), pc = (int)(gid % G.pcells);
+    const int nl = ll.ids ? ll.n : G.n_leaves;
+    if (gid >= (size_t)nl * G.pcells) return;
+    const int leaf = ll.ids ? ll.ids[gid / G.pcells] : (int)(gid / G.pcells), pc = (int)(gid % G.pcells);
     int L, c[3], loc[3];
     decode_pcell(G, leaf, pc, &L, c, loc);
     const bool interior = loc[0] >= 0 && loc[0] < G.bx[0] && loc[1] >= 0 && loc[1] < G.bx[1] && loc[2] >= 0 &&
                           loc[2] < G.bx[2];
     if (interior) return;
-    RecSrc<R> S{rec, G.leaf_info, snap, G.n_leaves, G.pcells, G.px[0], G.px[1], G.bx[0], G.bx[1], G.bx[2], G.rs, G.nf};
+    RecSrc<R> S{rec, &G, snap, G.pcells, G.px[0], G.px[1], G.bx[0], G.bx[1], G.bx[2], G.rs, G.nf};
     double v[kNF];
-    R *out = rec + (((size_t)snap * G.n_leaves + leaf) * G.pcells + pc) * G.rs;
+    R *out = rec + (((size_t)snap * G.n_blk + pool_block(G, snap, leaf)) * G.pcells + pc) * G.rs;
     if (!virtual_value<kNF>(G, S, L, c, v)) {
         atomicOr(&cnt->flags, kFlagAmrDepth);
         for (int q = 0; q < kNF; ++q) v[q] = __builtin_nan("");
+    }
+    if (G.pool_map) {
+        // a neighbour the ghost rule reads is not held in the pool
+        bool fin = true;
+        for (int q = 0; q < G.nf; ++q) fin &= isfinite(v[q]);
+        if (!fin) atomicOr(&cnt->flags, kFlagNotResident);
     }
     for (int q = 0; q < G.nf; ++q) out[q] = (R)v[q];
     for (int q = G.nf; q < G.rs; ++q) out[q] = (R)0;
@@ -296,31 +309,56 @@ hipError_t launch_check_raw(const DevGrid &g, const double *raw, size_t n_snaps,
     return hipGetLastError();
 }
 
-hipError_t launch_raw_ghost(const DevGrid &g, const RawWin &w, double *work_cart, DevCounters *cnt, hipStream_t s) {
-    const size_t n = (size_t)g.n_leaves * g.pcells;
-    hipLaunchKernelGGL(k_raw_ghost, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, w, work_cart, cnt);
+hipError_t launch_raw_ghost(const DevGrid &g, const RawWin &w, double *work_cart, DevCounters *cnt, LeafList ll,
+                            hipStream_t s) {
+    const size_t n = (size_t)(ll.ids ? ll.n : g.n_leaves) * g.pcells;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_raw_ghost, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, w, work_cart, cnt, ll);
     return hipGetLastError();
 }
 
-hipError_t launch_derive(const DevGrid &g, const RawWin &w, const double *work_cart, void *rec, int fp32,
+hipError_t launch_derive(const DevGrid &g, const RawWin &w, const double *work_cart, void *rec, int fp32, LeafList ll,
                          hipStream_t s) {
-    const size_t n = (size_t)g.n_leaves * g.cells;
+    const size_t n = (size_t)(ll.ids ? ll.n : g.n_leaves) * g.cells;
+    if (n == 0) return hipSuccess;
     if (fp32)
-        hipLaunchKernelGGL(k_derive<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, w, work_cart, (float *)rec);
+        hipLaunchKernelGGL(k_derive<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, w, work_cart, (float *)rec,
+                           ll);
     else
         hipLaunchKernelGGL(k_derive<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, w, work_cart,
-                           (double *)rec);
+                           (double *)rec, ll);
     return hipGetLastError();
 }
 
-hipError_t launch_record_ghost(const DevGrid &g, int snap, void *rec, int fp32, DevCounters *cnt, hipStream_t s) {
-    const size_t n = (size_t)g.n_leaves * g.pcells;
+hipError_t launch_record_ghost(const DevGrid &g, int snap, void *rec, int fp32, DevCounters *cnt, LeafList ll,
+                               hipStream_t s) {
+    const size_t n = (size_t)(ll.ids ? ll.n : g.n_leaves) * g.pcells;
+    if (n == 0) return hipSuccess;
     if (fp32)
         hipLaunchKernelGGL(k_record_ghost<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, snap, (float *)rec,
-                           cnt);
+                           cnt, ll);
     else
         hipLaunchKernelGGL(k_record_ghost<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, snap,
-                           (double *)rec, cnt);
+                           (double *)rec, cnt, ll);
+    return hipGetLastError();
+}
+
+// Non-finite values or |B| = 0 in the cells of the listed leaves of one
+// snapshot [leaf][cell][6].
+__global__ void k_check_raw_leaves(const double *raw, int cells, LeafList ll, DevCounters *cnt) {
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (size_t)ll.n * cells) return;
+    const double *v = raw + ((size_t)ll.ids[gid / cells] * cells + gid % cells) * 6;
+    bool bad = false;
+    for (int q = 0; q < 6; ++q) bad |= !isfinite(v[q]);
+    bad |= !(v[3] * v[3] + v[4] * v[4] + v[5] * v[5] > 0.0);
+    if (bad) atomicOr(&cnt->flags, kFlagBadInput);
+}
+
+hipError_t launch_check_raw_leaves(const DevGrid &g, const double *raw, DevCounters *cnt, LeafList ll, hipStream_t s) {
+    const size_t n = (size_t)ll.n * g.cells;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_raw_leaves, dim3(blocks_for(n, 256)), dim3(256), 0, s, raw, g.cells, ll, cnt);
     return hipGetLastError();
 }
 
@@ -362,7 +400,7 @@ __device__ __forceinline__ int descend(const DevGrid &G, const int32_t *base, co
     for (int a = 0; a < 3; ++a) {
         int c = (int)M<R>::floor_(s[a]);
         c = c > G.n1[a] - 1 ? G.n1[a] - 1 : c;
-        B[a] = c / G.bx[a];
+        B[a] = div_bx(G, c, a);
         S[a] = s[a];
     }
     int node = base[B[0] + G.nb1[0] * (B[1] + G.nb1[1] * B[2])];
@@ -378,7 +416,7 @@ __device__ __forceinline__ int descend(const DevGrid &G, const int32_t *base, co
             int c = (int)M<R>::floor_(S[a]);
             const int n = G.n1[a] << (L - 1);
             c = c > n - 1 ? n - 1 : c;
-            B[a] = c / G.bx[a];
+            B[a] = div_bx(G, c, a);
             slot |= (B[a] & 1) << a;
         }
         node = child[grp * 8 + slot];
@@ -406,12 +444,46 @@ __device__ __forceinline__ void fold_s(const DevGrid &G, R s[3]) {
     }
 }
 
+// Level-1 blocks holding a held particle and the largest ln p among them (for
+// planning which leaves a snapshot window needs).  Positive floats order like
+// their bit patterns, so the maximum is an integer atomic.
+__global__ void k_occupancy(DevGrid G, DevState st, const DevCounters *cnt, int slot, uint32_t *occ,
+                            uint32_t *lnp_bits) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt->n_live[slot] || st.status[i] != FTE_PS_ACTIVE) return;
+    const double x = st.x[i], y = st.y[i], z = st.z[i];
+    const double r = ::sqrt(x * x + y * y + z * z);
+    double ph = ::atan2(y, x);
+    if (ph < 0.0) ph += 2.0 * kPi;
+    double sc[3];
+    grid_coords<double>(G, r, ::acos(z / r), ph, sc);
+    fold_s<double>(G, sc);
+    int B[3];
+    for (int a = 0; a < 3; ++a) {
+        int c = (int)::floor(sc[a]);
+        c = c > G.n1[a] - 1 ? G.n1[a] - 1 : (c < 0 ? 0 : c);
+        B[a] = div_bx(G, c, a);
+    }
+    occ[B[0] + G.nb1[0] * (B[1] + G.nb1[1] * B[2])] = 1u;
+    const float lp = (float)st.lnp[i];
+    const float pos = lp > -80.f ? lp + 80.f : 0.f;     // shifted to stay positive
+    atomicMax(lnp_bits, __float_as_uint(pos));
+}
+
+hipError_t launch_occupancy(const DevGrid &g, DevState st, const DevCounters *cnt, int slot, uint64_t n_upper,
+                            uint32_t *occ, uint32_t *lnp_bits, hipStream_t s) {
+    if (n_upper == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_occupancy, dim3(blocks_for(n_upper, 256)), dim3(256), 0, s, g, st, cnt, slot, occ, lnp_bits);
+    return hipGetLastError();
+}
+
 // ===========================================================================
 // injection
 // ===========================================================================
 // Region test of the paper's injection law (section 2.3): the leaf cell
 // holding x has div V < divv_max at snapshot k (its own record value).
-__device__ bool in_region(const DevGrid &G, int rec_fp32, double x, double y, double z, int k, double divv_max) {
+__device__ bool in_region(const DevGrid &G, int rec_fp32, double x, double y, double z, int k, double divv_max,
+                          unsigned int *flags) {
     const double r = ::sqrt(x * x + y * y + z * z);
     const double th = ::acos(z / r);
     double ph = ::atan2(y, x);
@@ -431,7 +503,12 @@ __device__ bool in_region(const DevGrid &G, int rec_fp32, double x, double y, do
         loc[a] = c - B[a] * G.bx[a];
     }
     const size_t pc = (size_t)(loc[0] + 1) + (size_t)G.px[0] * ((loc[1] + 1) + (size_t)G.px[1] * (loc[2] + 1));
-    const size_t at = (((size_t)(k % G.n_slots) * G.n_leaves + leaf) * G.pcells + pc) * G.rs + 6;
+    const int blk = pool_block(G, k % G.n_slots, leaf);
+    if (blk < 0 || (G.pool_map && G.pool_map[(size_t)(k % G.n_slots) * G.n_leaves + leaf] < 0)) {
+        atomicOr(flags, kFlagNotResident);     // a streamed subset without this leaf
+        return false;
+    }
+    const size_t at = (((size_t)(k % G.n_slots) * G.n_blk + blk) * G.pcells + pc) * G.rs + 6;
     const double dv = rec_fp32 ? (double)reinterpret_cast<const float *>(G.rec)[at]
                                : reinterpret_cast<const double *>(G.rec)[at];
     return dv < divv_max;
@@ -494,7 +571,7 @@ __global__ void k_inject(DevParams P, DevGrid G, int rec_fp32, fte_injection inj
                 px = rr * stt * ::cos(ph);
                 py = rr * stt * ::sin(ph);
                 pz = rr * ct;
-                ok = in_region(G, rec_fp32, px, py, pz, snap, inj.divv_max);
+                ok = in_region(G, rec_fp32, px, py, pz, snap, inj.divv_max, &cnt->flags);
             }
             if (!ok) status = FTE_PS_NUMERIC;
         }
@@ -570,16 +647,18 @@ struct RecTile {
     int leaf, k0, layers, ks;
 };
 
-template <typename R, bool KPERP, bool TS2, bool TILE = false>
-__device__ __forceinline__ bool gather(const DevGrid &G, const int32_t *ibase, const int32_t *ichild, R s[3], int ks,
-                                       R alpha, R acc[kNF], const RecTile T = RecTile{nullptr, -1, 0, 0, -1}) {
+// Returns 0, or 1 when no leaf holds the point, 2 when (SUB: a streamed
+// subset of leaves) the leaf's records are not resident in both slots.
+template <typename R, bool KPERP, bool TS2, bool TILE = false, bool SUB = false>
+__device__ __forceinline__ int gather(const DevGrid &G, const int32_t *ibase, const int32_t *ichild, R s[3], int ks,
+                                      R alpha, R acc[kNF], const RecTile T = RecTile{nullptr, -1, 0, 0, -1}) {
     constexpr int NF = KPERP ? 13 : 10;
     constexpr int RS = KPERP ? kRSKperp : kRSPlain;
     fold_s<R>(G, s);
     int B[3];
     R S[3];
     const int leaf = descend<R>(G, ibase, ichild, s, S, B);
-    if (leaf < 0) return false;
+    if (leaf < 0) return 1;
     // local cell relative to the first centre of the block, padded index
     int i[3];
     R f[3];
@@ -615,12 +694,21 @@ __device__ __forceinline__ bool gather(const DevGrid &G, const int32_t *ibase, c
                     for (int q = 0; q < NF; ++q) acc[q] += w * p[q];
                 }
             }
-            return true;
+            return 0;
+        }
+    }
+    // the record block of the leaf in each live slot
+    int blk[2] = {leaf, leaf};
+    if constexpr (SUB) {
+#pragma unroll
+        for (int sn = 0; sn < 2; ++sn) {
+            blk[sn] = G.pool_map[(size_t)((ks + sn) % G.n_slots) * G.n_leaves + leaf];
+            if (blk[sn] < 0) return 2;
         }
     }
     // the 8 corners of snapshot slot ks + sn, weighted by ws
     auto corners = [&](int sn, R ws) {
-        const R *base = rec + (((size_t)((ks + sn) % G.n_slots) * G.n_leaves + leaf) * G.pcells + pc) * RS;
+        const R *base = rec + (((size_t)((ks + sn) % G.n_slots) * G.n_blk + blk[sn]) * G.pcells + pc) * RS;
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             const int e0 = d & 1, e1 = (d >> 1) & 1, e2 = (d >> 2) & 1;
@@ -637,7 +725,7 @@ __device__ __forceinline__ bool gather(const DevGrid &G, const int32_t *ibase, c
         const int nsn = G.n_snap >= 2 ? 2 : 1;
         for (int sn = 0; sn < nsn; ++sn) corners(sn, G.n_snap >= 2 ? (sn == 0 ? (R)1 - alpha : alpha) : (R)1);
     }
-    return true;
+    return 0;
 }
 
 // Directional derivatives of the gathered (spherical-component) fields along
@@ -716,7 +804,7 @@ __device__ __forceinline__ bool gather_d(const DevGrid &G, const int32_t *ibase,
     }
     for (int sn = 0; sn < nsn; ++sn) {
         const R ws = (G.n_snap >= 2) ? (sn == 0 ? (R)1 - alpha : alpha) : (R)1;
-        const R *base = rec + (((size_t)((ks + sn) % G.n_slots) * G.n_leaves + leaf) * G.pcells + pc) * RS;
+        const R *base = rec + (((size_t)((ks + sn) % G.n_slots) * G.n_blk + leaf) * G.pcells + pc) * RS;
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             const int e0 = d & 1, e1 = (d >> 1) & 1, e2 = (d >> 2) & 1;
@@ -868,7 +956,7 @@ constexpr int step_wpe_max() {
     return TS2 ? 2 : 8;
 }
 
-template <typename R, bool KPERP, int MODE, bool LIDX, bool LAYER, bool TS2, bool ENS>
+template <typename R, bool KPERP, int MODE, bool LIDX, bool LAYER, bool TS2, bool ENS, bool SUB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R, MODE>(), step_wpe_max<TS2>()))) void k_step(DevParams P, DevGrid G, DevState st, DevTan tn, DevCounters *cnt,
                                               int slot, double *hist, double *sm, uint64_t n0, uint32_t n_steps,
                                               StepLds LD) {
@@ -930,8 +1018,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                 const size_t layer = (size_t)G.px[0] * G.px[1] * kTileRS;
                 const size_t nfl = layer * TL;
                 const float *recf = reinterpret_cast<const float *>(G.rec);
+                // the anchor leaf's record block in each live slot (a
+                // streamed subset: no tile unless it is resident in both)
+                int ab[2] = {anchor[0], anchor[0]};
+                if constexpr (SUB) {
+                    for (int sn = 0; sn < 2; ++sn)
+                        ab[sn] = G.pool_map[(size_t)((ks0 + sn) % G.n_slots) * G.n_leaves + anchor[0]];
+                }
+                if (ab[0] >= 0 && ab[1] >= 0) {
                 for (int sn = 0; sn < 2; ++sn) {
-                    const float *src = recf + (((size_t)((ks0 + sn) % G.n_slots) * G.n_leaves + anchor[0]) * G.pcells) *
+                    const float *src = recf + (((size_t)((ks0 + sn) % G.n_slots) * G.n_blk + ab[sn]) * G.pcells) *
                                                   kTileRS + (size_t)k0 * layer;
                     if ((nfl & 3) == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
                         // 16-byte copies (the tile offset is 16-byte aligned)
@@ -943,6 +1039,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                     }
                 }
                 tile = RecTile{(lds_float *)t, anchor[0], k0, TL, ks0};
+                }
             }
             __syncthreads();
         }
@@ -1048,7 +1145,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                     break;
                 }
             } else {
-                if (!gather<R, KPERP, TS2, kTile>(G, ibase, ichild, s, ks, alpha, acc, tile)) {
+                const int gr = gather<R, KPERP, TS2, kTile, SUB>(G, ibase, ichild, s, ks, alpha, acc, tile);
+                if (gr != 0) {
+                    if (SUB && gr == 2) atomicOr(&cnt->flags, kFlagNotResident);
                     status = FTE_PS_NUMERIC;
                     break;
                 }
@@ -1344,7 +1443,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
             // radial and colatitude tests come first, then the longitude bin
             // of each observer (rotating with it), the energy bin only for a
             // particle inside one
-            if (P.n_obs > 0) {
+            const bool in_obs_box = kF64 ? ((double)r >= P.obs_u[0] && (double)r < P.obs_u[1])
+                                         : (r2 >= P.obs_u[2] && r2 < P.obs_u[3]);
+            if (P.n_obs > 0 && in_obs_box && th >= (R)P.obs_u[4] && th < (R)P.obs_u[5]) {
                 const double ut = (t + P.dt - P.t_ref) * P.inv_dT;
                 const double t1 = P.t0 + (double)(n + 1) * P.dt;
                 for (int o = 0; o < P.n_obs; ++o) {
@@ -1450,12 +1551,20 @@ static void launch_step_e(const DevParams &p, const DevGrid &g, DevState st, Dev
     // single run keeps them uniform, in scalar registers
     if constexpr (MODE == 0) {
         if (p.n_runs > 0) {
-            hipLaunchKernelGGL((k_step<R, KPERP, MODE, LIDX, LAYER, TS2, true>), grid, blk, shmem, s, p, g, st, tn,
-                               cnt, slot, hist, sm, n0, n_steps, ld);
+            hipLaunchKernelGGL((k_step<R, KPERP, MODE, LIDX, LAYER, TS2, true, false>), grid, blk, shmem, s, p, g, st,
+                               tn, cnt, slot, hist, sm, n0, n_steps, ld);
             return;
         }
+        // a streamed subset of leaves: records through the pool map
+        if constexpr (TS2 && !LIDX && !LAYER) {
+            if (g.pool_map) {
+                hipLaunchKernelGGL((k_step<R, KPERP, MODE, LIDX, LAYER, TS2, false, true>), grid, blk, shmem, s, p, g,
+                                   st, tn, cnt, slot, hist, sm, n0, n_steps, ld);
+                return;
+            }
+        }
     }
-    hipLaunchKernelGGL((k_step<R, KPERP, MODE, LIDX, LAYER, TS2, false>), grid, blk, shmem, s, p, g, st, tn, cnt,
+    hipLaunchKernelGGL((k_step<R, KPERP, MODE, LIDX, LAYER, TS2, false, false>), grid, blk, shmem, s, p, g, st, tn, cnt,
                        slot, hist, sm, n0, n_steps, ld);
 }
 
@@ -1621,11 +1730,15 @@ hipError_t launch_compact(DevState src, DevState dst, DevTan tsrc, DevTan tdst, 
 
 // ---------------------------------------------------------------------------
 // compaction with a spatial counting sort: live particles are regrouped by
-// (leaf, cube of 2^(sort-1) cells per edge) so that a wavefront gathers from
-// neighbouring records; order inside a key is arbitrary (results depend only
-// on pid, not on storage order).
+// (leaf, cube of cells) so that a wavefront gathers from neighbouring
+// records; order inside a key is arbitrary (results depend only on pid, not
+// on storage order).  The key space is bounded by the particle count, not by
+// the grid: the host picks the cube edge (and, on grids with more leaves than
+// that bound allows, groups of consecutive leaves) per compaction
+// (sort_shape_for), so zeroing and scanning the per-key counts costs
+// O(live particles) however many cells the grid has.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t cell_key(const DevGrid &G, int shift, double x, double y, double z) {
+__device__ __forceinline__ uint32_t cell_key(const DevGrid &G, const SortShape &K, double x, double y, double z) {
     const double r = ::sqrt(x * x + y * y + z * z);
     float ph = ::atan2f((float)y, (float)x);
     if (ph < 0.f) ph += (float)(2.0 * kPi);
@@ -1641,14 +1754,12 @@ __device__ __forceinline__ uint32_t cell_key(const DevGrid &G, int shift, double
     for (int a = 0; a < 3; ++a) {
         int l = (int)::floorf(S[a]) - B[a] * G.bx[a];
         l = l < 0 ? 0 : (l > G.bx[a] - 1 ? G.bx[a] - 1 : l);
-        sub[a] = l >> shift;
+        sub[a] = l >> K.cube_shift;
     }
-    const int h0 = G.bx[0] >> shift, h1 = G.bx[1] >> shift;
-    const uint32_t nsub = (uint32_t)h0 * h1 * (G.bx[2] >> shift);
-    return (uint32_t)leaf * nsub + (uint32_t)(sub[0] + h0 * (sub[1] + h1 * sub[2]));
+    return ((uint32_t)leaf >> K.leaf_shift) * K.n_sub + (uint32_t)(sub[0] + K.h[0] * (sub[1] + K.h[1] * sub[2]));
 }
 
-__global__ void k_sort_key(DevGrid G, int shift, DevState src, const DevCounters *cnt, int from, uint32_t *keys,
+__global__ void k_sort_key(DevGrid G, SortShape K, DevState src, const DevCounters *cnt, int from, uint32_t *keys,
                            uint32_t *counts) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cnt->n_live[from]) return;
@@ -1656,7 +1767,7 @@ __global__ void k_sort_key(DevGrid G, int shift, DevState src, const DevCounters
         keys[i] = 0xFFFFFFFFu;
         return;
     }
-    const uint32_t k = cell_key(G, shift, src.x[i], src.y[i], src.z[i]);
+    const uint32_t k = cell_key(G, K, src.x[i], src.y[i], src.z[i]);
     keys[i] = k;
     atomicAdd(&counts[k], 1u);
 }
@@ -1746,20 +1857,34 @@ __global__ void k_zero_u32(uint32_t *p, uint32_t n) {
     if (i < n) p[i] = 0u;
 }
 
-uint32_t sort_keys_for(const DevGrid &g, int sort) {
-    const int sh = sort - 1;
-    return (uint32_t)g.n_leaves * (uint32_t)((g.bx[0] >> sh) * (g.bx[1] >> sh) * (g.bx[2] >> sh));
+// Cubes of 2^(sort-1) cells or coarser, and groups of 2^leaf_shift
+// consecutive leaves, so that the key space fits max_keys.
+SortShape sort_shape_for(const DevGrid &g, int sort, uint64_t max_keys) {
+    SortShape K{};
+    const int bmax = g.bx[0] > g.bx[1] ? (g.bx[0] > g.bx[2] ? g.bx[0] : g.bx[2]) : (g.bx[1] > g.bx[2] ? g.bx[1] : g.bx[2]);
+    for (K.cube_shift = sort - 1;; ++K.cube_shift) {
+        const int e = 1 << K.cube_shift;
+        for (int a = 0; a < 3; ++a) K.h[a] = (g.bx[a] + e - 1) >> K.cube_shift;
+        K.n_sub = (uint32_t)(K.h[0] * K.h[1] * K.h[2]);
+        if ((uint64_t)g.n_leaves * K.n_sub <= max_keys || e >= bmax) break;
+    }
+    for (K.leaf_shift = 0;; ++K.leaf_shift) {
+        const uint64_t groups = ((uint64_t)g.n_leaves + (1ull << K.leaf_shift) - 1) >> K.leaf_shift;
+        K.n_keys = (uint32_t)(groups * K.n_sub);
+        if (groups * K.n_sub <= max_keys) break;
+    }
+    return K;
 }
 
-hipError_t launch_compact_sorted(const DevGrid &g, int sort, DevState src, DevState dst, DevTan tsrc, DevTan tdst,
-                                 DevCounters *cnt, int from, uint64_t n_upper, uint32_t *keys, uint32_t *counts,
-                                 uint32_t *tsum, hipStream_t s) {
-    const uint32_t nk = sort_keys_for(g, sort);
+hipError_t launch_compact_sorted(const DevGrid &g, const SortShape &K, DevState src, DevState dst, DevTan tsrc,
+                                 DevTan tdst, DevCounters *cnt, int from, uint64_t n_upper, uint32_t *keys,
+                                 uint32_t *counts, uint32_t *tsum, hipStream_t s) {
+    const uint32_t nk = K.n_keys;
     const uint32_t ntile = (nk + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_zero_u32, dim3(blocks_for(nk, 256)), dim3(256), 0, s, counts, nk);
     if (n_upper > 0)
-        hipLaunchKernelGGL(k_sort_key, dim3(blocks_for(n_upper, 256)), dim3(256), 0, s, g, sort - 1, src, cnt, from,
-                           keys, counts);
+        hipLaunchKernelGGL(k_sort_key, dim3(blocks_for(n_upper, 256)), dim3(256), 0, s, g, K, src, cnt, from, keys,
+                           counts);
     hipLaunchKernelGGL(k_scan_tiles, dim3(ntile), dim3(1024), 0, s, counts, nk, tsum);
     hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, tsum, ntile, cnt, 1 - from);
     hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(nk, 256)), dim3(256), 0, s, counts, nk, tsum);

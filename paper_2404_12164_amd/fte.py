@@ -30,7 +30,7 @@ SYMBOLS = ["fte_create", "fte_destroy", "fte_last_error", "fte_query_sizes", "ft
            "fte_inject", "fte_step_n", "fte_bin_observers", "fte_read_hist", "fte_get_stats", "fte_read_particles",
            "fte_set_launch", "fte_reset", "fte_set_timing", "fte_bin_smoothed", "fte_grad", "fte_read_tangents",
            "fte_state_size", "fte_save_state", "fte_load_state", "fte_autotune", "fte_bin_steady",
-           "fte_load_snapshot", "fte_set_record_tile"]
+           "fte_load_snapshot", "fte_set_record_tile", "fte_plan_snapshot", "fte_bin_observers_static"]
 TANGENT_COLS = 13         # d(x, y, z, mu, lnp)/d lambda_ref, the same for kperp_ratio, d ln w / d gamma_inj,
 #                           d ln w / d lambda_ref, d ln w / d kperp_ratio
 
@@ -65,7 +65,7 @@ class fte_grid_desc(C.Structure):
                 ("th_lo", C.c_double), ("dth", C.c_double), ("ph_lo", C.c_double), ("dph", C.c_double),
                 ("phi_periodic", C.c_int), ("n1", C.c_int * 3), ("bx", C.c_int * 3), ("n_levels", C.c_int),
                 ("n_leaves", C.c_int), ("leaves", C.POINTER(C.c_int32)), ("n_snap", C.c_int),
-                ("t_s0", C.c_double), ("dt_s", C.c_double), ("n_slots", C.c_int)]
+                ("t_s0", C.c_double), ("dt_s", C.c_double), ("n_slots", C.c_int), ("n_pool", C.c_int)]
 
 
 class fte_injection(C.Structure):
@@ -116,12 +116,15 @@ def lib():
         L.fte_inject.argtypes = [vp, C.POINTER(fte_injection), u64, u64, vp]
         L.fte_step_n.argtypes = [vp, u32, vp]
         L.fte_bin_observers.argtypes = [vp, dp, dp, C.c_int, vp]
+        L.fte_bin_observers_static.argtypes = [vp, dp, dp, C.c_int, vp]
         L.fte_read_hist.argtypes = [vp, dp, dp, vp]
         L.fte_get_stats.argtypes = [vp, C.POINTER(fte_stats), vp]
         L.fte_read_particles.argtypes = [vp, dp, dp, dp, dp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32),
                                          C.POINTER(C.c_int32), u64, C.POINTER(C.c_uint64), vp]
         L.fte_set_launch.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
         L.fte_set_record_tile.argtypes = [vp, C.c_int]
+        L.fte_plan_snapshot.argtypes = [vp, C.c_int, C.POINTER(fte_injection), C.c_int, C.c_double,
+                                        C.POINTER(C.c_int32), u64, C.POINTER(C.c_uint64), vp]
         L.fte_reset.argtypes = [vp, vp]
         L.fte_set_timing.argtypes = [vp, C.c_int]
         L.fte_bin_smoothed.argtypes = [vp, dp, dp, vp]
@@ -219,6 +222,7 @@ def make_grid_desc(g: dict):
     d.t_s0 = g.get("t_s0", 0.0)
     d.dt_s = g.get("dt_s", 1.0)
     d.n_slots = int(g.get("n_slots", 0))
+    d.n_pool = int(g.get("n_pool", 0))
     return d, leaves
 
 
@@ -292,6 +296,19 @@ def fte_load_snapshot(ctx, k: int, ptrs, stream: int):
     _check(ctx, lib().fte_load_snapshot(ctx, int(k), arr, C.c_void_p(stream)))
 
 
+def fte_plan_snapshot(ctx, k: int, sources, wind_speed_max: float, n_leaves: int, stream: int):
+    """Leaves snapshot k's slot holds (a streamed subset): returns the ids of
+    the leaves whose input the load reads and the counts (gather, held,
+    input)."""
+    arr = (fte_injection * max(len(sources), 1))(*[make_injection(q) for q in sources])
+    out = np.zeros(n_leaves, dtype=np.int32)
+    counts = (C.c_uint64 * 3)()
+    _check(ctx, lib().fte_plan_snapshot(ctx, int(k), arr, len(sources), float(wind_speed_max),
+                                        out.ctypes.data_as(C.POINTER(C.c_int32)), n_leaves, counts,
+                                        C.c_void_p(stream)))
+    return out[: counts[2]].copy(), (int(counts[0]), int(counts[1]), int(counts[2]))
+
+
 def fte_inject(ctx, inj: dict, n: int, first_pid: int, stream: int):
     io = make_injection(inj)
     _check(ctx, lib().fte_inject(ctx, C.byref(io), int(n), int(first_pid), C.c_void_p(stream)))
@@ -308,6 +325,18 @@ def fte_bin_observers(ctx, shape, reset: bool, stream: int):
     dp = C.POINTER(C.c_double)
     _check(ctx, lib().fte_bin_observers(ctx, j.ctypes.data_as(dp), s.ctypes.data_as(dp), int(bool(reset)),
                                         C.c_void_p(stream)))
+    return j[:n].reshape(shape), s[:n].reshape(shape)
+
+
+def fte_bin_observers_static(ctx, shape, reset: bool, stream: int):
+    """fte_bin_observers through the library's fixed device scratch (no
+    allocation)."""
+    n = int(np.prod(shape))
+    j = np.zeros(max(n, 1))
+    s = np.zeros(max(n, 1))
+    dp = C.POINTER(C.c_double)
+    _check(ctx, lib().fte_bin_observers_static(ctx, j.ctypes.data_as(dp), s.ctypes.data_as(dp), int(bool(reset)),
+                                               C.c_void_p(stream)))
     return j[:n].reshape(shape), s[:n].reshape(shape)
 
 
@@ -477,6 +506,11 @@ class Simulation:
             vb = vb_sph.to(device=self.device, dtype=t.float64).contiguous()
         fte_load_grid(self.ctx, vb.data_ptr(), self.stream)
         del vb
+
+    def plan_snapshot(self, k: int, sources, wind_speed_max: float):
+        """With a leaf pool (grid n_pool > 0): choose the leaves snapshot k's
+        slot holds; returns (input leaf ids, (gather, held, input) counts)."""
+        return fte_plan_snapshot(self.ctx, k, sources, wind_speed_max, len(self.grid["leaves"]), self.stream)
 
     def load_snapshot(self, k: int, vb_all):
         """Derive snapshot k of a streaming grid into its slot from vb_all, a

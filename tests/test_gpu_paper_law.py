@@ -145,3 +145,33 @@ def test_paper_workload_small_matches_oracle(F, torch_cuda, orc):
     assert np.all(np.abs(sums - h) <= 1e-9 * np.maximum(np.abs(h), 1e-6 * sc))
     Jo, _ = orc.finalize_steady(p, sums, w)
     assert np.allclose(Jg, Jo, rtol=1e-12, atol=0)
+
+
+def test_sort_key_space_bounded_on_fine_grid(F, torch_cuda):
+    """The paper's experiment on its 4-level grid (76,509 leaves) with 10^4
+    particles: the spatial sort's key space is capped at 2^16 keys, so keys
+    group pairs of consecutive leaves (more leaves than keys); trajectories
+    are bit-identical to the ballot compaction's (storage order never changes
+    a result)."""
+    torch = torch_cuda
+    c = W.paper_cir(n_levels=4, n_particles=10_000)
+    g = c["grid"]
+    assert len(g["leaves"]) > (1 << 16)
+    raw = W.make_raw(g, c["wind"], xp=torch, device=torch.device("cuda:0"))
+    outs = []
+    for sort in (1, 0):
+        sim = F.Simulation(c["params"], g, c["n_particles"])
+        sim.load_grid(raw)
+        sim.set_launch(256, 64, 64, sort)
+        sim.inject(c["injection"], c["n_particles"], 0)
+        sim.step(1280)
+        torch.cuda.synchronize()
+        outs.append((sim.particles(), sim.read_hist()[0], sim.stats()))
+        sim.close()
+    (a, sa, sta), (b, sb, stb) = outs
+    oa, ob = np.argsort(a["pid"]), np.argsort(b["pid"])
+    assert np.array_equal(a["pid"][oa], b["pid"][ob])
+    for k in ("x", "mu", "lnp", "w", "status"):
+        assert np.array_equal(a[k][oa], b[k][ob]), k
+    assert sta.particle_steps == stb.particle_steps and sta.device_flags == 0
+    assert np.allclose(sa, sb, rtol=1e-12, atol=1e-12 * max(np.abs(sa).max(), 1e-300))

@@ -80,3 +80,111 @@ def test_ring_of_slots_matches_full_grid(F, torch_cuda):
     sc = max(np.abs(sa).max(), 1e-300)
     assert (sa > 0).sum() > 20
     assert np.allclose(sa, sb, rtol=1e-12, atol=1e-14 * sc)
+
+
+def _pool_case(n=2000):
+    """The CIR grid (2,346 leaves) with 8 hourly snapshots and a source of
+    5-20 keV protons in a 10 x 10 degree patch at 0.3 au: within two hours
+    they reach a strict subset of the leaves."""
+    AU = W.AU
+    cfg = W.cir_time_dependent(n_particles=n, n_snap=8)
+    g = cfg["grid"]
+    inj = dict(cfg["injection"], r=0.3 * AU, th_lo=85 * DEG, th_hi=95 * DEG, ph_lo=0.0, ph_hi=10 * DEG,
+               e_lo=5 * W.KEV, e_hi=20 * W.KEV, n_total=n, n_inj_steps=0, k0=0, pid0=0)
+    return cfg, g, inj
+
+
+def _pool_run(F, torch, p, g, inj, vb, n, n_pool, n_int, per, wind=700e3):
+    gs = dict(g, n_slots=3, n_pool=n_pool)
+    b = F.Simulation(p, gs, n)
+    b.set_launch(256, 64, 64, 1)
+    counts = []
+    for k in (0, 1):
+        counts.append(b.plan_snapshot(k, [inj], wind)[1])
+        b.load_snapshot(k, vb)
+    b.inject(inj, n, 0)
+    for k in range(n_int):
+        if k > 0:
+            counts.append(b.plan_snapshot(k + 1, [inj], wind)[1])
+            b.load_snapshot(k + 1, vb)
+        b.step(per)
+    torch.cuda.synchronize()
+    out = b.particles()
+    sums, w = b.read_hist()
+    st = b.stats()
+    b.close()
+    return out, sums, w, st, counts
+
+
+def test_leaf_pool_matches_full_grid(F, torch_cuda):
+    """A ring of three slots that each hold only the leaves the particles can
+    reach (planned from their positions and the source) gives the
+    trajectories and sums of the fully loaded grid, bit for bit, on the
+    mixed path with the benchmark's launch shape; the planned sets are a
+    strict subset of the leaves."""
+    torch = torch_cuda
+    n = 2000
+    cfg, g, inj = _pool_case(n)
+    p = dict(cfg["params"], precision="mixed")
+    vb = W.make_raw(g, cfg["wind"], xp=torch, device=torch.device("cuda:0"))
+    per = int(g["dt_s"] / p["dt"])
+    n_int = 5
+    a = F.Simulation(p, g, n)
+    a.load_grid(vb)
+    a.set_launch(256, 64, 64, 1)
+    a.inject(inj, n, 0)
+    a.step(n_int * per)
+    torch.cuda.synchronize()
+    A = a.particles()
+    sa, wa = a.read_hist()
+    a.close()
+    nl = len(g["leaves"])
+    B, sb, wb, st, counts = _pool_run(F, torch, p, g, inj, vb, n, nl, n_int, per)
+    print("pool (gather, held, input) leaves per snapshot:", counts, "of", nl)
+    assert st.device_flags == 0
+    assert counts[0][0] < nl // 2 and max(c[1] for c in counts) < nl
+    # the steps come in other chunks, so compaction drops retired particles
+    # at other global steps: compare those still active
+    ma, mb = A["status"] == 0, B["status"] == 0
+    oa, ob = np.argsort(A["pid"][ma]), np.argsort(B["pid"][mb])
+    assert ma.sum() > n // 2
+    for key in ("pid", "x", "mu", "lnp", "w"):
+        assert np.array_equal(A[key][ma][oa], B[key][mb][ob]), key
+    assert wa == pytest.approx(wb, rel=1e-14)
+    sc = max(np.abs(sa).max(), 1e-300)
+    assert np.allclose(sa, sb, rtol=1e-12, atol=1e-14 * sc)
+    # a pool too small for the reachable leaves is refused at planning time
+    gs = dict(g, n_slots=3, n_pool=max(c[1] for c in counts) // 2)
+    c = F.Simulation(p, gs, n)
+    with pytest.raises(F.FteError):
+        c.plan_snapshot(0, [inj], 700e3)
+    c.close()
+
+
+def test_leaf_pool_fp64_matches_oracle(F, torch_cuda, orc):
+    """The FP64 path on a leaf pool against the oracle, which reads the whole
+    raw grid: every trajectory within 1e-10."""
+    torch = torch_cuda
+    n = 600
+    cfg, g, inj = _pool_case(n)
+    p = dict(cfg["params"], precision="fp64")
+    vb = W.make_raw(g, cfg["wind"], xp=torch, device=torch.device("cuda:0"))
+    per = int(g["dt_s"] / p["dt"])
+    n_int = 4
+    nl = len(g["leaves"])
+    B, sb, wb, st, counts = _pool_run(F, torch, p, g, inj, vb, n, nl, n_int, per)
+    assert st.device_flags == 0
+    assert max(c[1] for c in counts) < nl
+    G = orc.Grid(g, vb[: n_int + 2].cpu().numpy())
+    ref = orc.inject(p, inj, n, 0)
+    h = np.zeros(orc.hist_size(p))
+    orc.run(p, G, ref, 0, n_int * per, h)
+    alive = ref.status == 0
+    ob = np.argsort(B["pid"])
+    mb = B["status"][ob] == 0
+    assert np.array_equal(B["pid"][ob][mb], ref.pid[alive])
+    dx = np.abs(B["x"][ob][mb] - ref.x[alive]).max() / W.AU
+    dmu = np.abs(B["mu"][ob][mb] - ref.mu[alive]).max()
+    assert dx < 1e-10 and dmu < 1e-10, (dx, dmu)
+    sc = max(np.abs(h).max(), 1e-300)
+    assert np.allclose(sb, h, rtol=1e-9, atol=1e-12 * sc)

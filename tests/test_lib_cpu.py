@@ -202,3 +202,21 @@ def test_shocked_cir_jump_conditions():
     V1 = W.cir_shocked_wind(r, th, ph - shift, 0.0, width_if=0.1 * deg)[:, 0]
     assert (V1[1] - U) / (V1[2] - U) == pytest.approx(3.0, rel=2e-3)
     assert (V1[5] - U) / (V1[4] - U) == pytest.approx(3.0, rel=2e-3)
+
+
+def test_sort_workspace_bounded_by_particles(F):
+    """The spatial sort's key space is bounded by the particle capacity, not
+    by the grid: on the paper's 4-level grid (76,509 leaves, 2.35 x 10^8 leaf
+    cells) the work buffer grows with capacity by O(bytes per particle) and
+    holds no per-cell counter array beyond the load-time workspace."""
+    cfg = W.paper_cir(n_levels=4, n_particles=1000)
+    g = cfg["grid"]
+    nl = len(g["leaves"])
+    cells = nl * int(np.prod(g["bx"]))
+    pc = int(np.prod(np.asarray(g["bx"]) + 2))
+    cart = nl * pc * 6 * 8                       # load-time Cartesian (V, b) of one snapshot
+    small = F.fte_query_sizes(cfg["params"], g, 10_000).work_bytes
+    big = F.fte_query_sizes(cfg["params"], g, 1_000_000).work_bytes
+    assert cells * 4 > 9e8                      # a per-cell count array would be ~1 GB
+    assert small < cart + 4e6                   # keys + counts of at most 2^16 keys + the rest
+    assert big - small < 1_000_000 * 4 * 5      # keys (4 B) + counts (4 per particle x 4 B) per particle
