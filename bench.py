@@ -62,7 +62,7 @@ def read_counters(name, kernel):
 class Run:
     """One context on the workload plus its lazy continuous-injection plan."""
 
-    def __init__(self, F, cfg, raw, precision, block, spl, compact, sort=1, load=True):
+    def __init__(self, F, cfg, raw, precision, block, spl, compact, sort=1, load=True, tile=None):
         import torch
         self.torch = torch
         self.cfg = cfg
@@ -77,6 +77,8 @@ class Run:
             self.sim.load_grid(raw)
         self.load_s = time.time() - t
         self.sim.set_launch(block, spl, compact, sort)
+        if tile is not None:
+            self.sim.set_record_tile(tile)
         self.sim.set_timing(True)
         self.injected = 0
         self.n0 = 0
@@ -483,6 +485,8 @@ def paper_leg(F, W, args, levels=(1, 2, 3)):
         sim.load_grid(raw)
         del raw
         sim.set_launch(args.block, args.spl, args.compact, args.sort)
+        if args.tile_bytes is not None:
+            sim.set_record_tile(args.tile_bytes)
         sim.inject(c["injection"], c["n_particles"], 0)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -663,6 +667,7 @@ def main():
     ap.add_argument("--spl", type=int, default=64)
     ap.add_argument("--compact", type=int, default=64)
     ap.add_argument("--sort", type=int, default=1)
+    ap.add_argument("--tile-bytes", type=int, default=None, help="LDS record tile budget (default: the library's)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")
@@ -715,7 +720,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    run = Run(F, cfg, raw, args.precision, args.block, args.spl, args.compact, args.sort)
+    run = Run(F, cfg, raw, args.precision, args.block, args.spl, args.compact, args.sort, tile=args.tile_bytes)
     log(f"grid loaded in {run.load_s:.2f} s")
     if args.warmup > 0:
         timed(run, args.warmup, chunk, total=total_steps)
@@ -736,8 +741,8 @@ def main():
     F_fields = 13 if (cfg["params"].get("kperp_ratio", 0) > 0 or cfg["params"].get("lambda_perp", 0) > 0) else 10
     T_s = 2 if g["n_snap"] >= 2 else 1
     s_f = 4 if args.precision == "mixed" else 8
-    kern = ("k_step<float,false,0,false,false,true,false>" if args.precision == "mixed"
-            else "k_step<double,false,0,false,false,true,false>")
+    kern = ("k_step<float,false,0,false,false,true,false,false>" if args.precision == "mixed"
+            else "k_step<double,false,0,false,false,true,false,false>")
     nl = max(res["launches"], 1)
     launch_s = res["kernel_ms"] / 1e3 / nl
     ps_launch = res["particle_steps"] / nl
@@ -807,7 +812,7 @@ def main():
         del r64
         extra["fp64_value"] = res64["particle_steps"] / (res64["ms"] / 1e3)
         extra["mixed_over_fp64"] = round(value / extra["fp64_value"], 3)
-        kern64 = "k_step<double,false,0,false,false,true,false>"
+        kern64 = "k_step<double,false,0,false,false,true,false,false>"
         c64 = read_counters("k_step_cir_fp64_counters.txt", kern64)
         if c64 is not None:
             nl64 = max(res64["launches"], 1)

@@ -677,14 +677,16 @@ __device__ __forceinline__ int gather(const DevGrid &G, const int32_t *ibase, co
     if constexpr (TILE) {
         // both corner layers i[2] + 1 and i[2] + 2 in the tile: the same
         // values, weights and summation order as the global path below
-        const bool in = leaf == T.leaf && ks == T.ks && i[2] + 1 >= T.k0 && i[2] + 2 < T.k0 + T.layers && i[0] >= -1 &&
-            i[0] + 2 < G.px[0] && i[1] >= -1 && i[1] + 2 < G.px[1];
+        // (TS2: both live snapshots; otherwise a steady grid, one snapshot)
+        constexpr int NS = TS2 ? 2 : 1;
+        const bool in = (TS2 || G.n_snap < 2) && leaf == T.leaf && ks == T.ks && i[2] + 1 >= T.k0 &&
+            i[2] + 2 < T.k0 + T.layers && i[0] >= -1 && i[0] + 2 < G.px[0] && i[1] >= -1 && i[1] + 2 < G.px[1];
         if (in) {
             const size_t tsnap = (size_t)T.layers * sz * RS;
             lds_float *tb = T.lds + ((size_t)(i[2] + 1 - T.k0) * sz + (size_t)(i[1] + 1) * sy + (size_t)(i[0] + 1)) * RS;
 #pragma unroll
-            for (int sn = 0; sn < 2; ++sn) {
-                const R ws = sn == 0 ? (R)1 - alpha : alpha;
+            for (int sn = 0; sn < NS; ++sn) {
+                const R ws = TS2 ? (sn == 0 ? (R)1 - alpha : alpha) : (R)1;
 #pragma unroll
                 for (int d = 0; d < 8; ++d) {
                     const int e0 = d & 1, e1 = (d >> 1) & 1, e2 = (d >> 2) & 1;
@@ -951,9 +953,12 @@ constexpr int step_wpe() {
 // Most waves per SIMD the allocator plans for: 2 for the unrolled
 // two-snapshot gather, so that the scheduler keeps its 40 loads in flight
 // instead of trading them for a third wave.
+#ifndef FTE_STEP_WPE_MAX_TS2
+#define FTE_STEP_WPE_MAX_TS2 2
+#endif
 template <bool TS2>
 constexpr int step_wpe_max() {
-    return TS2 ? 2 : 8;
+    return TS2 ? FTE_STEP_WPE_MAX_TS2 : 8;
 }
 
 template <typename R, bool KPERP, int MODE, bool LIDX, bool LAYER, bool TS2, bool ENS, bool SUB>
@@ -980,7 +985,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
     // record tile (float kernels, time-dependent grid): anchored at the leaf
     // and k-layer of the workgroup's middle particle, for the snapshot pair of
     // the launch's first step
-    constexpr bool kTile = std::is_same<R, float>::value && (TS2 || MODE == 2) && !LAYER && !LIDX;
+    constexpr bool kTile = std::is_same<R, float>::value && !LAYER && !LIDX;
     constexpr int kTileRS = KPERP ? kRSKperp : kRSPlain;
     RecTile tile{nullptr, -1, 0, 0, -1};
     if constexpr (kTile) {
@@ -1010,10 +1015,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                 int k0 = anchor[1] - (TL - 2) / 2;
                 k0 = k0 > pz - TL ? pz - TL : k0;
                 k0 = k0 < 0 ? 0 : k0;
-                const double tau = (P.t0 + (double)n0 * P.dt - G.t_s0) * G.inv_dt_s;
-                double kf = ::floor(tau);
-                kf = kf < 0.0 ? 0.0 : (kf > (double)(G.n_snap - 2) ? (double)(G.n_snap - 2) : kf);
-                const int ks0 = (int)kf;
+                // the snapshot pair of the launch's first step (one snapshot
+                // on a steady grid)
+                const int nst = G.n_snap >= 2 ? 2 : 1;
+                int ks0 = 0;
+                if (nst == 2) {
+                    const double tau = (P.t0 + (double)n0 * P.dt - G.t_s0) * G.inv_dt_s;
+                    double kf = ::floor(tau);
+                    kf = kf < 0.0 ? 0.0 : (kf > (double)(G.n_snap - 2) ? (double)(G.n_snap - 2) : kf);
+                    ks0 = (int)kf;
+                }
                 float *t = reinterpret_cast<float *>(k_step_lds + LD.tile_off);
                 const size_t layer = (size_t)G.px[0] * G.px[1] * kTileRS;
                 const size_t nfl = layer * TL;
@@ -1026,7 +1037,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                         ab[sn] = G.pool_map[(size_t)((ks0 + sn) % G.n_slots) * G.n_leaves + anchor[0]];
                 }
                 if (ab[0] >= 0 && ab[1] >= 0) {
-                for (int sn = 0; sn < 2; ++sn) {
+                for (int sn = 0; sn < nst; ++sn) {
                     const float *src = recf + (((size_t)((ks0 + sn) % G.n_slots) * G.n_blk + ab[sn]) * G.pcells) *
                                                   kTileRS + (size_t)k0 * layer;
                     if ((nfl & 3) == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
@@ -1654,15 +1665,24 @@ hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevTan
     size_t shmem = 0;
     bool lidx = false;
     StepLds ld = plan_step_lds(p, g, n0, n_steps, &shmem, &lidx);
-    if (fp32 && !lidx && g.n_snap >= 2 && !(p.layer_k0dt > 0.0) && tile_bytes > 0) {
-        // as many whole padded k-layers of both snapshots as fit, at least two
+    if (fp32 && !lidx && (g.n_snap >= 2 || !p.grad) && !(p.layer_k0dt > 0.0) && tile_bytes > 0) {
+        // as many whole padded k-layers of the live snapshots (two, or the
+        // one of a steady grid) as fit, at least two
+        const size_t nst = g.n_snap >= 2 ? 2 : 1;
         const size_t layer_bytes = (size_t)g.px[0] * g.px[1] * (kp ? kRSKperp : kRSPlain) * sizeof(float);
-        size_t tl = tile_bytes / (2 * layer_bytes);
+        // the steady-grid kernel runs 3 waves per SIMD: keep three
+        // workgroups' LDS within the CU's 160 KB
+        size_t budget = tile_bytes;
+        if (nst == 1) {
+            const size_t third = (size_t)160 * 1024 / 3;
+            budget = budget < third - shmem - 64 ? budget : (third > shmem + 64 ? third - shmem - 64 : 0);
+        }
+        size_t tl = budget / (nst * layer_bytes);
         if (tl > (size_t)g.px[2]) tl = (size_t)g.px[2];
         if (tl >= 2) {
             ld.tile_off = (int)((shmem + 15) & ~(size_t)15);
             ld.tile_layers = (int)tl;
-            shmem = (size_t)ld.tile_off + 2 * tl * layer_bytes;
+            shmem = (size_t)ld.tile_off + nst * tl * layer_bytes;
         }
     }
     if (fp32) {

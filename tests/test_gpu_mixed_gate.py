@@ -224,3 +224,28 @@ def test_record_tile_bit_identical_largest(F, torch_cuda, largest):
     a = gpu_subset_run(F, torch_cuda, pm, g, raw, inj, blocks, 1152)
     b = gpu_subset_run(F, torch_cuda, pm, g, raw, inj, blocks, 1152, tile=0)
     assert_same_run(a, b)
+
+
+def test_record_tile_bit_identical_steady(F, torch_cuda):
+    """A steady grid (the paper's experiment in the corotating frame, 2 AMR
+    levels, one snapshot): the one-snapshot tile (six k-layers) and no tile
+    give identical trajectories and sums, 10^5 particles, 1,280 steps."""
+    torch = torch_cuda
+    c = W.paper_cir(n_levels=2, n_particles=100_000)
+    g = c["grid"]
+    raw = W.make_raw(g, c["wind"], xp=torch, device=torch.device("cuda:0"))
+    runs = []
+    for tile in (None, 0):
+        sim = F.Simulation(c["params"], g, c["n_particles"])
+        sim.load_grid(raw)
+        sim.set_launch(*LAUNCH)
+        if tile is not None:
+            sim.set_record_tile(tile)
+        sim.inject(c["injection"], c["n_particles"], 0)
+        sim.step(1280)
+        torch.cuda.synchronize()
+        sums, w = sim.read_hist()
+        runs.append((sim.particles(), sums, w, sim.stats()))
+        sim.close()
+    assert runs[0][3].device_flags == 0
+    assert_same_run(runs[0], runs[1])
