@@ -154,18 +154,6 @@ typedef struct {
      * single run with the fields above.  Not combined with sigma_x > 0.      */
     int n_runs;           /* 0..FTE_MAX_RUNS                                       */
     const fte_run *runs;  /* host, n_runs entries; copied by fte_create            */
-    /* Absorbing layers (on when both are > 0; not in the paper, an option of
-     * this library): at distance d < absorb_layer inside r_in and inside
-     * r_out, the weight decays at the rate absorb_rate (1 - d/absorb_layer)^2,
-     * taken at the post-step radius: w *= exp(-rate dt) after the boundary and
-     * colatitude tests of each step.  The absorbing spheres stay behind the
-     * layers.  The weight removed counts in fte_stats.w_retired of its
-     * boundary.  The rate is C1 in position, so each trajectory's weight,
-     * unlike a hard absorption, is differentiable in the parameters that move
-     * it: with grad = 1 the tangents also carry d ln w / d(lambda_ref,
-     * kperp_ratio) and dJ includes them.  0 / 0: hard absorption only.      */
-    double absorb_layer;  /* m                                                     */
-    double absorb_rate;   /* 1/s                                                   */
     /* Gradient mode with FTE_DMM_EQ5: |mu| in Eq. 5 gives dD/dmu a jump of
      * 2A at mu = 0, which the derivative of each sampled step does not see
      * (a.e. d2D/dmu2 has no Dirac term).  kink_sigma > 0 adds to the
@@ -267,9 +255,7 @@ typedef struct {
     uint64_t particle_steps;  /* steps taken by active particles                */
     uint64_t n_retired[6];    /* by FTE_PS_* (index 0 unused)                   */
     double w_injected;
-    double w_retired[6];      /* weight of retired particles by FTE_PS_*, plus
-                                 the weight the absorbing layers removed at
-                                 r_in (index 1) and r_out (index 2)             */
+    double w_retired[6];      /* weight of retired particles by FTE_PS_*        */
     uint64_t global_step;     /* next global step index                         */
     uint32_t device_flags;    /* nonzero: a kernel met an unsupported case (bit
                                  8: a step reached a leaf a streamed subset
@@ -356,7 +342,7 @@ fte_status fte_load_snapshot(fte_ctx *ctx, int k, const double *const raw[5], vo
  * read).  FTE_ENOMEM when more than n_pool leaves must be held; FTE_EINVAL
  * without a pool.  A step that still reaches a leaf outside C retires the
  * particle as FTE_PS_NUMERIC and raises bit 8 of fte_stats.device_flags.
- * Not combined with smoothing, ensembles or absorbing layers.
+ * Not combined with smoothing or ensembles.
  * Synchronises. */
 fte_status fte_plan_snapshot(fte_ctx *ctx, int k, const fte_injection *sources, int n_sources, double wind_speed_max,
                              int32_t *leaves_out, uint64_t cap, uint64_t counts[3], void *stream);
@@ -418,7 +404,7 @@ fte_status fte_read_particles(fte_ctx *ctx, double *x3, double *mu, double *lnp,
  * [3][n_obs*n_e*n_t]) with respect to (lambda_ref, kperp_ratio, gamma_inj),
  * the last including the change of W_inj.  The derivatives are pathwise:
  * a hard absorption and the 6-width cut of the kernels are treated as fixed
- * events (the absorbing layers of fte_params make absorption smooth).
+ * events.
  * The kperp_ratio derivative is 0 unless kperp_ratio > 0.  Either array may
  * be NULL.  Synchronises. */
 fte_status fte_bin_smoothed(fte_ctx *ctx, double *J, double *dJ, void *stream);
@@ -430,10 +416,9 @@ fte_status fte_bin_smoothed(fte_ctx *ctx, double *J, double *dJ, void *stream);
 fte_status fte_grad(fte_ctx *ctx, const double *dL_dJ, double grad[3], void *stream);
 
 /* Tangents of the held particles (gradient mode), storage order as
- * fte_read_particles: HOST array [n_live][13] = dx, dy, dz, dmu, dlnp with
- * respect to lambda_ref, the same five with respect to kperp_ratio,
- * d ln w / d gamma_inj, d ln w / d lambda_ref and d ln w / d kperp_ratio
- * (the last two from the absorbing layers).  cap is the row capacity of tan (FTE_ENOMEM if
+ * fte_read_particles: HOST array [n_live][11] = dx, dy, dz, dmu, dlnp with
+ * respect to lambda_ref, the same five with respect to kperp_ratio, and
+ * d ln w / d gamma_inj.  cap is the row capacity of tan (FTE_ENOMEM if
  * below n_live); *n_out receives n_live.  Synchronises. */
 fte_status fte_read_tangents(fte_ctx *ctx, double *tan, uint64_t cap, uint64_t *n_out, void *stream);
 

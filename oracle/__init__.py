@@ -74,7 +74,6 @@ class OrParams(C.Structure):
         ("t_ref", C.c_double), ("dT", C.c_double), ("n_t", C.c_int), ("n_batch", C.c_int),
         ("bg_kind", C.c_int), ("bg", C.c_double * 16),
         ("smooth", C.c_int), ("sig_x", C.c_double), ("sig_lne", C.c_double), ("sig_t", C.c_double),
-        ("absorb_layer", C.c_double), ("absorb_rate", C.c_double),
     ]
 
 
@@ -205,8 +204,6 @@ def make_params(p: dict) -> OrParams:
     if sm:
         o.smooth = 1
         o.sig_x, o.sig_lne, o.sig_t = sm["sigma_x"], sm["sigma_lne"], sm["sigma_t"]
-    o.absorb_layer = p.get("absorb_layer", 0.0)
-    o.absorb_rate = p.get("absorb_rate", 0.0)
     return o
 
 

@@ -67,8 +67,6 @@ typedef struct {
     double bg[16];        /* analytic background parameters                      */
     int    smooth;        /* accumulate the kernel-smoothed intensity sums       */
     double sig_x, sig_lne, sig_t;  /* Gaussian widths: space (m), ln E, time (s) */
-    double absorb_layer;  /* width h of the absorbing layers inside r_in, r_out, m */
-    double absorb_rate;   /* their peak weight-decay rate k0, 1/s (both > 0: on)  */
 } or_params;
 
 /* Observer bins: observer o covers obs_nphi[o] consecutive longitude bins. */
@@ -743,21 +741,6 @@ typedef struct {
 
 static int or_finite3(const double *x) { return isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]); }
 
-/* Weight-decay rate of the absorbing layers at radius r: inside each radial
- * boundary, at distance d < h from it, k0 (1 - d/h)^2; zero elsewhere.  A
- * layer of finite width in front of the absorbing sphere (not in the paper:
- * an option of this implementation) removes weight continuously, so that
- * the weight of every trajectory, unlike a hard absorption, changes smoothly
- * with the parameters that move it. */
-static double or_layer_rate(const or_params *pp, double r)
-{
-    double h = pp->absorb_layer, k = 0.0;
-    double u_in = 1.0 - (r - pp->r_in) / h, u_out = 1.0 - (pp->r_out - r) / h;
-    if (u_in > 0.0) k += u_in * u_in;
-    if (u_out > 0.0) k += u_out * u_out;
-    return pp->absorb_rate * k;
-}
-
 /* Speed for P = p/(m c). */
 static double or_speed(double P) { return OR_C * P / sqrt(1.0 + P * P); }
 
@@ -856,8 +839,6 @@ static void or_step(const or_params *pp, const void *g, or_particle *pt, uint64_
             double th_hi = gg->d.th_lo + gg->d.n1[1] * gg->d.dth;
             if (th < gg->d.th_lo || th > th_hi) { pt->status = OR_OUT_DOMAIN; return; }
         }
-        /* survival through the layers over this step, at the post-step radius */
-        if (pp->absorb_layer > 0.0 && pp->absorb_rate > 0.0) pt->w *= exp(-or_layer_rate(pp, r) * pp->dt);
     }
 
     if (sm && pp->smooth && pp->n_obs > 0)

@@ -164,9 +164,6 @@ std::string check_params(const fte_params *p) {
         }
     }
     if (!(p->sigma_x >= 0.0) || !isfinite(p->sigma_x)) return "sigma_x must be >= 0";
-    if (!(p->absorb_layer >= 0.0) || !isfinite(p->absorb_layer) || !(p->absorb_rate >= 0.0) ||
-        !isfinite(p->absorb_rate))
-        return "absorb_layer and absorb_rate must be finite and >= 0";
     if (!isfinite(p->kink_sigma)) return "kink_sigma must be finite";
     if (p->grad != 0 && p->grad != 1) return "grad must be 0 or 1";
     if (p->grad && !(p->sigma_x > 0.0)) return "the gradient needs the smoothed intensities (sigma_x > 0)";
@@ -425,10 +422,6 @@ void make_devparams(const fte_params *p, DevParams *d) {
         d->kink_inv_2s2 = 1.0 / (2.0 * p->kink_sigma * p->kink_sigma);
     }
     if (p->grad && p->dmm_model == FTE_DMM_EQ5 && p->kink_sigma < 0.0) d->kink_bridge = 1;
-    if (p->absorb_layer > 0.0 && p->absorb_rate > 0.0) {
-        d->layer_k0dt = p->absorb_rate * p->dt;
-        d->layer_inv_h = 1.0 / p->absorb_layer;
-    }
     // kernel-smoothed intensities
     if (p->sigma_x > 0.0) {
         d->smooth = 1;
@@ -595,8 +588,8 @@ fte_status fte_bind_buffers(fte_ctx *c, const fte_grid_desc *g, uint64_t n_max, 
     if (c->p.grad && (!b->tangent_a || !b->tangent_b || ((uintptr_t)b->tangent_a & 255) ||
                       ((uintptr_t)b->tangent_b & 255)))
         return fail(c, FTE_EINVAL, "gradient mode needs 256-byte aligned tangent buffers");
-    if (g->n_pool > 0 && (c->p.sigma_x > 0.0 || c->p.n_runs > 0 || (c->p.absorb_layer > 0.0 && c->p.absorb_rate > 0.0)))
-        return fail(c, FTE_EINVAL, "a streamed subset (n_pool) is not combined with smoothing, ensembles or absorbing layers");
+    if (g->n_pool > 0 && (c->p.sigma_x > 0.0 || c->p.n_runs > 0))
+        return fail(c, FTE_EINVAL, "a streamed subset (n_pool) is not combined with smoothing or ensembles");
     const Layout L = layout(&c->p, g, n_max, base.size(), child.size());
     c->g = *g;
     c->leaves.assign(g->leaves, g->leaves + 4 * (size_t)g->n_leaves);
@@ -1488,7 +1481,7 @@ uint64_t state_fingerprint(const fte_ctx *c) {
     h = fnv_val(h, p.e_min); h = fnv_val(h, p.dlne); h = fnv_val(h, p.n_e); h = fnv_val(h, p.t_ref);
     h = fnv_val(h, p.dT); h = fnv_val(h, p.n_t); h = fnv_val(h, p.n_batch);
     h = fnv_val(h, p.sigma_x); h = fnv_val(h, p.sigma_lne); h = fnv_val(h, p.sigma_t); h = fnv_val(h, p.grad);
-    h = fnv_val(h, p.n_runs); h = fnv_val(h, p.absorb_layer); h = fnv_val(h, p.absorb_rate);
+    h = fnv_val(h, p.n_runs);
     h = fnv_val(h, p.kink_sigma);
     for (int r = 0; r < p.n_runs; ++r) {
         h = fnv_val(h, c->runs[r].lambda_ref);

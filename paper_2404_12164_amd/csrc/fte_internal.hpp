@@ -58,8 +58,6 @@ struct DevParams {
     int n_runs;              // 0: single run
     int n_runs_eff;          // max(n_runs, 1): leading dimension of the sums
     int kperp_any;           // some run has kappa_perp: 13-field records, KPERP kernels
-    double layer_k0dt;       // absorbing layers: peak decay per step k0 dt (0: off)
-    double layer_inv_h;      // 1 / layer width
     double kink_norm, kink_inv_2s2;   // tangents: 2 / (sqrt(2 pi) s), 1 / (2 s^2) (0: off)
     int kink_bridge;                  // tangents: the bridge occupation at mu = 0 instead
     uint64_t seed;
@@ -114,16 +112,15 @@ struct DevState {
     uint16_t *run;
 };
 
-// Tangent state of the gradient mode (struct of arrays, capacity n_max): 13
+// Tangent state of the gradient mode (struct of arrays, capacity n_max): 11
 // double arrays of `stride` entries from `base`: d(x, y, z, mu, lnp)/d lambda_ref,
-// the same with respect to kperp_ratio, d ln w / d gamma_inj, and d ln w /
-// d(lambda_ref, kperp_ratio) (nonzero only with absorbing layers).
+// the same with respect to kperp_ratio, and d ln w / d gamma_inj.
 struct DevTan {
     double *base;
     uint64_t stride;
     __host__ __device__ double *col(int q) const { return base + (uint64_t)q * stride; }
 };
-enum : int { kTanLnw = 10, kTanLnwP = 11, kTanCols = 13 };
+enum : int { kTanLnw = 10, kTanCols = 11 };
 
 // LDS plan of a step launch: observer time bins [it_lo, it_lo + n_tb) are
 // accumulated in LDS (n_tb = 0: straight to the global histogram).  The block

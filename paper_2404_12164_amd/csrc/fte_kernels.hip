@@ -961,7 +961,7 @@ constexpr int step_wpe_max() {
     return TS2 ? FTE_STEP_WPE_MAX_TS2 : 8;
 }
 
-template <typename R, bool KPERP, int MODE, bool LIDX, bool LAYER, bool TS2, bool ENS, bool SUB>
+template <typename R, bool KPERP, int MODE, bool LIDX, bool TS2, bool ENS, bool SUB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R, MODE>(), step_wpe_max<TS2>()))) void k_step(DevParams P, DevGrid G, DevState st, DevTan tn, DevCounters *cnt,
                                               int slot, double *hist, double *sm, uint64_t n0, uint32_t n_steps,
                                               StepLds LD) {
@@ -985,7 +985,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
     // record tile (float kernels, time-dependent grid): anchored at the leaf
     // and k-layer of the workgroup's middle particle, for the snapshot pair of
     // the launch's first step
-    constexpr bool kTile = std::is_same<R, float>::value && !LAYER && !LIDX;
+    constexpr bool kTile = std::is_same<R, float>::value && !LIDX;
     constexpr int kTileRS = KPERP ? kRSKperp : kRSPlain;
     RecTile tile{nullptr, -1, 0, 0, -1};
     if constexpr (kTile) {
@@ -1059,10 +1059,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
         double x = st.x[i], y = st.y[i], z = st.z[i];
         R mu = (R)st.mu[i], lnp = (R)st.lnp[i];
         const double w = st.w[i];
-        // absorbing layers: the survival factor of this launch's steps so far
-        // (the weight is w wf) and the rates (u_in^2, u_out^2) summed over them
-        R wf = (R)1, L_in = (R)0, L_out = (R)0;
-        auto w_now = [&]() -> double { return w * (double)wf; };
         const uint64_t pid = st.pid[i];
         const uint32_t kinj = st.kinj[i];
         int status = FTE_PS_ACTIVE;
@@ -1081,7 +1077,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
             run_id = rr.run_id;
         }
         // tangents (MODE 2)
-        R TX[ND][3], TM[ND], TL[ND], DW[ND];
+        R TX[ND][3], TM[ND], TL[ND];
         R dlnw = (R)0;
         if constexpr (MODE == 2) {
 #pragma unroll
@@ -1091,7 +1087,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                 TX[k][2] = (R)tn.col(5 * k + 2)[i];
                 TM[k] = (R)tn.col(5 * k + 3)[i];
                 TL[k] = (R)tn.col(5 * k + 4)[i];
-                DW[k] = (R)tn.col(kTanLnwP + k)[i];
             }
             dlnw = (R)tn.col(kTanLnw)[i];
         }
@@ -1381,27 +1376,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                 status = FTE_PS_OUT_OF_DOMAIN;
                 break;
             }
-            // ---- absorbing layers: survival over this step at the post-step
-            // radius, a factor exp(-k0 dt (u_in^2 + u_out^2)) with u = 1 - d / h
-            // where the distance d to a boundary is below h
-            if constexpr (LAYER) {
-                double u_in = 1.0 - ((double)r - P.r_in) * P.layer_inv_h;
-                double u_out = 1.0 - (P.r_out - (double)r) * P.layer_inv_h;
-                u_in = u_in > 0.0 ? u_in : 0.0;
-                u_out = u_out > 0.0 ? u_out : 0.0;
-                if (u_in > 0.0 || u_out > 0.0) {
-                    L_in += (R)(u_in * u_in);
-                    L_out += (R)(u_out * u_out);
-                    wf *= M<R>::exp_((R)(-P.layer_k0dt * (u_in * u_in + u_out * u_out)));
-                    if constexpr (MODE == 2) {
-                        // d ln w = -k0 dt (2 / h)(u_out - u_in) dr, dr = x . dx / r
-                        const double g = -P.layer_k0dt * 2.0 * P.layer_inv_h * (u_out - u_in) / (double)r;
-#pragma unroll
-                        for (int k = 0; k < ND; ++k)
-                            DW[k] += (R)(g * (x * (double)TX[k][0] + y * (double)TX[k][1] + z * (double)TX[k][2]));
-                    }
-                }
-            }
             // ---- kernel-smoothed sums of the post-step state, per global step
             // (the time kernel is applied when they are read out)
             if constexpr (MODE >= 1) {
@@ -1409,7 +1383,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                 if (m >= 0 && m < P.n_win) {
                     const R lnE = M<R>::log_((R)P.mass_c2 * M<R>::div_(Pcur * Pcur, gcur + (R)1));
                     const R iE = M<R>::exp_(-lnE);
-                    const R base_w = (R)w_now() * vcur * dt;
+                    const R base_w = (R)w * vcur * dt;
                     const R dlE = M<R>::div_(gcur + (R)1, gcur);        // d ln E / d ln p
                     const R G2n = M<R>::div_((R)1, gcur * gcur);       // d ln v / d ln p
                     for (int o = 0; o < P.n_obs; ++o) {
@@ -1443,7 +1417,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                                 const R fe = (-ue * (R)P.inv_sl2 - (R)1) * dlE;
 #pragma unroll
                                 for (int k = 0; k < ND; ++k)
-                                    atomicAdd(cell + 1 + k, (double)(c * (gx[k] + fe * TL[k] + DW[k])));
+                                    atomicAdd(cell + 1 + k, (double)(c * (gx[k] + fe * TL[k])));
                                 atomicAdd(cell + 3, (double)(c * dlnw));
                             }
                         }
@@ -1475,7 +1449,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                         const int ie = (int)M<R>::floor_(ue);
                         const int it = (int)::floor(ut);
                         const int ib = (int)(pid % (uint64_t)P.n_batch);
-                        const double add = w_now() * (double)vcur * P.dt;
+                        const double add = w * (double)vcur * P.dt;
                         const int lt = it - LD.it_lo;
                         const size_t rob = (size_t)run_r * P.n_obs_bins + obin;
                         if (lt >= 0 && lt < LD.n_tb) {
@@ -1500,23 +1474,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                 tn.col(5 * k + 2)[i] = (double)TX[k][2];
                 tn.col(5 * k + 3)[i] = (double)TM[k];
                 tn.col(5 * k + 4)[i] = (double)TL[k];
-                tn.col(kTanLnwP + k)[i] = (double)DW[k];
             }
-        }
-        const double w_end = w_now();
-        if (LAYER && w_end != w) {
-            // the removed weight, split between the layers in proportion to
-            // their accumulated rates
-            st.w[i] = w_end;
-            const double lost = w - w_end, f_in = (double)L_in / ((double)L_in + (double)L_out);
-            if (L_in > (R)0) atomicAdd(&cnt->w_retired[FTE_PS_ABSORBED_IN], lost * f_in);
-            if (L_out > (R)0) atomicAdd(&cnt->w_retired[FTE_PS_ABSORBED_OUT], lost - lost * f_in);
         }
         if (status == FTE_PS_ACTIVE && n_win >= step_end) status = FTE_PS_DONE;
         if (status != FTE_PS_ACTIVE) {
             st.status[i] = status;
             atomicAdd(&cnt->retired[status], 1ull);
-            atomicAdd(&cnt->w_retired[status], w_end);
+            atomicAdd(&cnt->w_retired[status], w);
         }
     }
     // block total of particle-steps, one atomic per block
@@ -1545,16 +1509,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
 }
 
 // Instances: the LDS block index only when the build allows it (it is off by
-// default), the absorbing layers only when the context has them, so that the
-// kernels of a plain run carry no code of either; the unrolled two-snapshot
-// gather (TS2) on time-dependent grids, where the register peak it adds (2
-// waves per SIMD instead of 3 on the float path) pays for itself: +15% on the
-// CIR workload, +10% on the kappa_perp ensemble, even on the largest workload,
-// +2% on the double path (already at 2 waves).  The tangent kernels gather
-// through their own path.  Per-particle run parameters (ENS) only for
-// ensembles: a single run's stay uniform, which frees vector registers (+6%
-// on the double path).
-template <typename R, bool KPERP, int MODE, bool LIDX, bool LAYER, bool TS2>
+// default), so that the kernels of a plain run carry none of its code; the
+// unrolled two-snapshot gather (TS2) on time-dependent grids, where the
+// register peak it adds (2 waves per SIMD instead of 3 on the float path)
+// pays for itself: +15% on the CIR workload, +10% on the kappa_perp
+// ensemble, even on the largest workload, +2% on the double path (already at
+// 2 waves).  The tangent kernels gather through their own path.
+// Per-particle run parameters (ENS) only for ensembles: a single run's stay
+// uniform, which frees vector registers (+6% on the double path).  Records
+// through a leaf pool's map (SUB) only for streamed subsets.
+template <typename R, bool KPERP, int MODE, bool LIDX, bool TS2>
 static void launch_step_e(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
                           double *hist, double *sm, uint64_t n0, uint32_t n_steps, dim3 grid, dim3 blk, StepLds ld,
                           size_t shmem, hipStream_t s) {
@@ -1562,36 +1526,36 @@ static void launch_step_e(const DevParams &p, const DevGrid &g, DevState st, Dev
     // single run keeps them uniform, in scalar registers
     if constexpr (MODE == 0) {
         if (p.n_runs > 0) {
-            hipLaunchKernelGGL((k_step<R, KPERP, MODE, LIDX, LAYER, TS2, true, false>), grid, blk, shmem, s, p, g, st,
-                               tn, cnt, slot, hist, sm, n0, n_steps, ld);
+            hipLaunchKernelGGL((k_step<R, KPERP, MODE, LIDX, TS2, true, false>), grid, blk, shmem, s, p, g, st, tn,
+                               cnt, slot, hist, sm, n0, n_steps, ld);
             return;
         }
         // a streamed subset of leaves: records through the pool map
-        if constexpr (TS2 && !LIDX && !LAYER) {
+        if constexpr (TS2 && !LIDX) {
             if (g.pool_map) {
-                hipLaunchKernelGGL((k_step<R, KPERP, MODE, LIDX, LAYER, TS2, false, true>), grid, blk, shmem, s, p, g,
-                                   st, tn, cnt, slot, hist, sm, n0, n_steps, ld);
+                hipLaunchKernelGGL((k_step<R, KPERP, MODE, LIDX, TS2, false, true>), grid, blk, shmem, s, p, g, st,
+                                   tn, cnt, slot, hist, sm, n0, n_steps, ld);
                 return;
             }
         }
     }
-    hipLaunchKernelGGL((k_step<R, KPERP, MODE, LIDX, LAYER, TS2, false, false>), grid, blk, shmem, s, p, g, st, tn, cnt,
+    hipLaunchKernelGGL((k_step<R, KPERP, MODE, LIDX, TS2, false, false>), grid, blk, shmem, s, p, g, st, tn, cnt,
                        slot, hist, sm, n0, n_steps, ld);
 }
 
-template <typename R, bool KPERP, int MODE, bool LIDX, bool LAYER>
+template <typename R, bool KPERP, int MODE, bool LIDX>
 static void launch_step_ts(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
                            double *hist, double *sm, uint64_t n0, uint32_t n_steps, dim3 grid, dim3 blk, StepLds ld,
                            size_t shmem, hipStream_t s) {
     if constexpr (MODE < 2) {
         if (g.n_snap >= 2) {
-            launch_step_e<R, KPERP, MODE, LIDX, LAYER, true>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid,
-                                                             blk, ld, shmem, s);
+            launch_step_e<R, KPERP, MODE, LIDX, true>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld,
+                                                      shmem, s);
             return;
         }
     }
-    launch_step_e<R, KPERP, MODE, LIDX, LAYER, false>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld,
-                                                      shmem, s);
+    launch_step_e<R, KPERP, MODE, LIDX, false>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld, shmem,
+                                               s);
 }
 
 template <typename R, bool KPERP, int MODE>
@@ -1600,21 +1564,12 @@ static void launch_step_m(const DevParams &p, const DevGrid &g, DevState st, Dev
                           size_t shmem, bool lidx, hipStream_t s) {
     if constexpr (kLdsIndexBytes > 0) {
         if (lidx) {
-            if (p.layer_k0dt > 0.0)
-                launch_step_ts<R, KPERP, MODE, true, true>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk,
-                                                           ld, shmem, s);
-            else
-                launch_step_ts<R, KPERP, MODE, true, false>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk,
-                                                            ld, shmem, s);
+            launch_step_ts<R, KPERP, MODE, true>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld, shmem,
+                                                 s);
             return;
         }
     }
-    if (p.layer_k0dt > 0.0)
-        launch_step_ts<R, KPERP, MODE, false, true>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld,
-                                                    shmem, s);
-    else
-        launch_step_ts<R, KPERP, MODE, false, false>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld,
-                                                     shmem, s);
+    launch_step_ts<R, KPERP, MODE, false>(p, g, st, tn, cnt, slot, hist, sm, n0, n_steps, grid, blk, ld, shmem, s);
 }
 
 template <typename R, bool KPERP>
@@ -1665,7 +1620,7 @@ hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevTan
     size_t shmem = 0;
     bool lidx = false;
     StepLds ld = plan_step_lds(p, g, n0, n_steps, &shmem, &lidx);
-    if (fp32 && !lidx && (g.n_snap >= 2 || !p.grad) && !(p.layer_k0dt > 0.0) && tile_bytes > 0) {
+    if (fp32 && !lidx && (g.n_snap >= 2 || !p.grad) && tile_bytes > 0) {
         // as many whole padded k-layers of the live snapshots (two, or the
         // one of a steady grid) as fit, at least two
         const size_t nst = g.n_snap >= 2 ? 2 : 1;

@@ -31,8 +31,7 @@ SYMBOLS = ["fte_create", "fte_destroy", "fte_last_error", "fte_query_sizes", "ft
            "fte_set_launch", "fte_reset", "fte_set_timing", "fte_bin_smoothed", "fte_grad", "fte_read_tangents",
            "fte_state_size", "fte_save_state", "fte_load_state", "fte_autotune", "fte_bin_steady",
            "fte_load_snapshot", "fte_set_record_tile", "fte_plan_snapshot", "fte_bin_observers_static"]
-TANGENT_COLS = 13         # d(x, y, z, mu, lnp)/d lambda_ref, the same for kperp_ratio, d ln w / d gamma_inj,
-#                           d ln w / d lambda_ref, d ln w / d kperp_ratio
+TANGENT_COLS = 11         # d(x, y, z, mu, lnp)/d lambda_ref, the same for kperp_ratio, d ln w / d gamma_inj
 
 
 class fte_observer(C.Structure):
@@ -57,7 +56,7 @@ class fte_params(C.Structure):
                 ("t_ref", C.c_double), ("dT", C.c_double), ("n_t", C.c_int), ("n_batch", C.c_int),
                 ("sigma_x", C.c_double), ("sigma_lne", C.c_double), ("sigma_t", C.c_double), ("grad", C.c_int),
                 ("n_runs", C.c_int), ("runs", C.POINTER(fte_run)),
-                ("absorb_layer", C.c_double), ("absorb_rate", C.c_double), ("kink_sigma", C.c_double)]
+                ("kink_sigma", C.c_double)]
 
 
 class fte_grid_desc(C.Structure):
@@ -198,8 +197,6 @@ def make_params(p: dict) -> fte_params:
             arr[i] = fte_run(float(r["lambda_ref"]), float(r.get("kperp_ratio", 0.0)), int(r["n_steps"]))
         o.runs = C.cast(arr, C.POINTER(fte_run))
         o._runs_keep = arr          # the C call reads the table; keep it alive with the struct
-    o.absorb_layer = p.get("absorb_layer", 0.0)
-    o.absorb_rate = p.get("absorb_rate", 0.0)
     o.kink_sigma = p.get("kink_sigma", 0.0)
     return o
 

@@ -122,8 +122,7 @@ def test_rejects_bad_params(F):
     cfg = W.tiny_parker()
     for over in (dict(dt=0.0), dict(mass=-1.0), dict(n_batch=0), dict(n_batch=65), dict(dmm_model=7),
                  dict(q=2.5), dict(r_out=0.0), dict(run_id=70000), dict(precision=3),
-                 dict(kink_sigma=float("nan")), dict(kink_sigma=float("-inf")), dict(absorb_layer=-1.0),
-                 dict(absorb_rate=float("inf"))):
+                 dict(kink_sigma=float("nan")), dict(kink_sigma=float("-inf"))):
         with pytest.raises(F.FteError):
             F.fte_query_sizes(dict(cfg["params"], **over), cfg["grid"], 10)
 
