@@ -741,8 +741,8 @@ def main():
     F_fields = 13 if (cfg["params"].get("kperp_ratio", 0) > 0 or cfg["params"].get("lambda_perp", 0) > 0) else 10
     T_s = 2 if g["n_snap"] >= 2 else 1
     s_f = 4 if args.precision == "mixed" else 8
-    kern = ("k_step<float,false,0,false,false,true,false,false>" if args.precision == "mixed"
-            else "k_step<double,false,0,false,false,true,false,false>")
+    kern = ("k_step<float,false,0,false,true,false,false>" if args.precision == "mixed"
+            else "k_step<double,false,0,false,true,false,false>")
     nl = max(res["launches"], 1)
     launch_s = res["kernel_ms"] / 1e3 / nl
     ps_launch = res["particle_steps"] / nl
@@ -812,7 +812,7 @@ def main():
         del r64
         extra["fp64_value"] = res64["particle_steps"] / (res64["ms"] / 1e3)
         extra["mixed_over_fp64"] = round(value / extra["fp64_value"], 3)
-        kern64 = "k_step<double,false,0,false,false,true,false,false>"
+        kern64 = "k_step<double,false,0,false,true,false,false>"
         c64 = read_counters("k_step_cir_fp64_counters.txt", kern64)
         if c64 is not None:
             nl64 = max(res64["launches"], 1)

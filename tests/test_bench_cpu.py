@@ -34,11 +34,11 @@ def test_counters_apply_only_to_their_kernel(tmp_path, monkeypatch, same_source,
     number of bench steps) and only to the kernel source and instance they
     were taken on."""
     sha = "1234567890abcdef"
-    k = "k_step<float,false,0,false,false,true,false,false>"
+    k = "k_step<float,false,0,false,true,false,false>"
     _profile(tmp_path, sha, k)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: sha if same_source else "ffffffffffffffff")
-    got = bench.read_counters("p.txt", k if same_kernel else "k_step<double,false,0,false,false,true,false,false>")
+    got = bench.read_counters("p.txt", k if same_kernel else "k_step<double,false,0,false,true,false,false>")
     if same_source and same_kernel:
         assert got["hbm_bytes_per_particle_step"] == 250.5 and got["valu_insts_per_particle_step"] == 21.0
     else:
