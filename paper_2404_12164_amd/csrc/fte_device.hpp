@@ -33,6 +33,10 @@ __device__ __forceinline__ U4 philox10(U4 ctr, uint32_t k0, uint32_t k1) {
         ctr = nx;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
+        // the round keys are uniform: bump them in scalar registers each
+        // round rather than let the compiler hoist all twenty out of the
+        // step loop, where they spill to vector lanes and cost a read each
+        asm volatile("" : "+s"(k0), "+s"(k1));
     }
     return ctr;
 }
@@ -63,6 +67,7 @@ struct M<double> {
     static __device__ __forceinline__ double acos_(double x) { return ::acos(x); }
     static __device__ __forceinline__ double atan2_(double y, double x) { return ::atan2(y, x); }
     static __device__ __forceinline__ double floor_(double x) { return ::floor(x); }
+    static __device__ __forceinline__ double fma_(double a, double b, double c) { return ::fma(a, b, c); }
     static __device__ __forceinline__ double fmod_(double x, double y) { return ::fmod(x, y); }
     // quotients in the double path stay correctly rounded
     static __device__ __forceinline__ double div_(double a, double b) { return a / b; }
@@ -73,13 +78,24 @@ struct M<double> {
 
 template <>
 struct M<float> {
-    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+    // hardware square root (1 ulp) instead of the correctly rounded sequence
+    // (a scaled estimate corrected by two fused multiply-adds).  The empty asm
+    // hides the result's origin from the optimizer: it would otherwise fold
+    // some reciprocals of it into reciprocal square roots and not others, so
+    // that the same quantity computed at two places (at launch start and in
+    // the step loop) could round differently.
+    static __device__ __forceinline__ float sqrt_(float x) {
+        float r = __builtin_amdgcn_sqrtf(x);
+        asm("" : "+v"(r));
+        return r;
+    }
     static __device__ __forceinline__ float log_(float x) { return __logf(x); }
     static __device__ __forceinline__ float exp_(float x) { return __expf(x); }
     static __device__ __forceinline__ float pow_(float x, float y) { return __expf(y * __logf(x)); }
     static __device__ __forceinline__ float acos_(float x) { return ::acosf(x); }
     static __device__ __forceinline__ float atan2_(float y, float x) { return ::atan2f(y, x); }
     static __device__ __forceinline__ float floor_(float x) { return ::floorf(x); }
+    static __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
     static __device__ __forceinline__ float fmod_(float x, float y) { return ::fmodf(x, y); }
     // quotients in the float path: hardware reciprocal (1 ulp) times numerator
     static __device__ __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }

@@ -647,9 +647,23 @@ struct RecTile {
     int leaf, k0, layers, ks;
 };
 
+// Float kernels with the record tile whose gather loads each lane's corners
+// from its own source (tile or global) and interpolates once: the plain
+// forward kernels with 10-field records, two snapshots (bit 1) or a steady
+// grid (bit 2).  The 13-field records (cross-field diffusion) hold too many
+// values for it; the ensemble and leaf-pool instances would spill.
+#ifndef FTE_TILE_UNIFIED
+#define FTE_TILE_UNIFIED 1
+#endif
+template <typename R, bool KPERP, int MODE, bool TS2, bool ENS, bool SUB>
+constexpr bool unified_gather() {
+    return std::is_same<R, float>::value && !KPERP && MODE == 0 && !ENS && !SUB &&
+           (FTE_TILE_UNIFIED & (TS2 ? 1 : 2)) != 0;
+}
+
 // Returns 0, or 1 when no leaf holds the point, 2 when (SUB: a streamed
 // subset of leaves) the leaf's records are not resident in both slots.
-template <typename R, bool KPERP, bool TS2, bool TILE = false, bool SUB = false>
+template <typename R, bool KPERP, bool TS2, bool TILE = false, bool SUB = false, bool UNI = false>
 __device__ __forceinline__ int gather(const DevGrid &G, const int32_t *ibase, const int32_t *ichild, R s[3], int ks,
                                       R alpha, R acc[kNF], const RecTile T = RecTile{nullptr, -1, 0, 0, -1}) {
     constexpr int NF = KPERP ? 13 : 10;
@@ -681,6 +695,54 @@ __device__ __forceinline__ int gather(const DevGrid &G, const int32_t *ibase, co
         constexpr int NS = TS2 ? 2 : 1;
         const bool in = (TS2 || G.n_snap < 2) && leaf == T.leaf && ks == T.ks && i[2] + 1 >= T.k0 &&
             i[2] + 2 < T.k0 + T.layers && i[0] >= -1 && i[0] + 2 < G.px[0] && i[1] >= -1 && i[1] + 2 < G.px[1];
+        if constexpr (UNI) {
+            // a wavefront whose particles are partly in the tile loads each
+            // lane's corners from its own source into registers and
+            // interpolates once (with a branch per source around the
+            // interpolation too, such a wavefront would run it twice)
+            if (TS2 || G.n_snap < 2) {
+                static_assert(!SUB, "the leaf-pool kernels gather through the branches below");
+                R v[NS][8][NF];
+                if (in) {
+                    const size_t tsnap = (size_t)T.layers * sz * RS;
+                    lds_float *tb =
+                        T.lds + ((size_t)(i[2] + 1 - T.k0) * sz + (size_t)(i[1] + 1) * sy + (size_t)(i[0] + 1)) * RS;
+#pragma unroll
+                    for (int sn = 0; sn < NS; ++sn)
+#pragma unroll
+                        for (int d = 0; d < 8; ++d) {
+                            lds_float *p = tb + sn * tsnap + ((d & 1) * sx + ((d >> 1) & 1) * sy + (d >> 2) * sz) * RS;
+#pragma unroll
+                            for (int q = 0; q < NF; ++q) v[sn][d][q] = p[q];
+                        }
+                } else {
+#pragma unroll
+                    for (int sn = 0; sn < NS; ++sn) {
+                        const R *base =
+                            rec + (((size_t)((ks + sn) % G.n_slots) * G.n_blk + leaf) * G.pcells + pc) * RS;
+#pragma unroll
+                        for (int d = 0; d < 8; ++d) {
+                            const R *p = base + ((d & 1) * sx + ((d >> 1) & 1) * sy + (d >> 2) * sz) * RS;
+#pragma unroll
+                            for (int q = 0; q < NF; ++q) v[sn][d][q] = p[q];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int sn = 0; sn < NS; ++sn) {
+                    const R ws = TS2 ? (sn == 0 ? (R)1 - alpha : alpha) : (R)1;
+#pragma unroll
+                    for (int d = 0; d < 8; ++d) {
+                        const int e0 = d & 1, e1 = (d >> 1) & 1, e2 = (d >> 2) & 1;
+                        const R w =
+                            ws * (e0 ? f[0] : (R)1 - f[0]) * (e1 ? f[1] : (R)1 - f[1]) * (e2 ? f[2] : (R)1 - f[2]);
+#pragma unroll
+                        for (int q = 0; q < NF; ++q) acc[q] += w * v[sn][d][q];
+                    }
+                }
+                return 0;
+            }
+        }
         if (in) {
             const size_t tsnap = (size_t)T.layers * sz * RS;
             lds_float *tb = T.lds + ((size_t)(i[2] + 1 - T.k0) * sz + (size_t)(i[1] + 1) * sy + (size_t)(i[0] + 1)) * RS;
@@ -728,6 +790,17 @@ __device__ __forceinline__ int gather(const DevGrid &G, const int32_t *ibase, co
         for (int sn = 0; sn < nsn; ++sn) corners(sn, G.n_snap >= 2 ? (sn == 0 ? (R)1 - alpha : alpha) : (R)1);
     }
     return 0;
+}
+
+// Weight derivative of one corner along a tangent direction dS: every
+// product and fused multiply-add written out, so that the tile and global
+// paths (two copies of this code in one kernel) round identically whatever
+// the compiler would contract on its own.
+template <typename R>
+__device__ __forceinline__ R corner_dw(R ws, R w0, R w1, R w2, R g0, R g1, R g2, const R dS[3]) {
+#pragma clang fp contract(off)
+    const R a0 = g0 * w1 * w2, a1 = w0 * g1 * w2, a2 = w0 * w1 * g2;
+    return ws * M<R>::fma_(a2, dS[2], M<R>::fma_(a1, dS[1], a0 * dS[0]));
 }
 
 // Directional derivatives of the gathered (spherical-component) fields along
@@ -789,15 +862,14 @@ __device__ __forceinline__ bool gather_d(const DevGrid &G, const int32_t *ibase,
                     const R w = ws * w0 * w1 * w2;
                     R dw[ND];
 #pragma unroll
-                    for (int k = 0; k < ND; ++k)
-                        dw[k] = ws * (g0 * w1 * w2 * dS[k][0] + w0 * g1 * w2 * dS[k][1] + w0 * w1 * g2 * dS[k][2]);
+                    for (int k = 0; k < ND; ++k) dw[k] = corner_dw<R>(ws, w0, w1, w2, g0, g1, g2, dS[k]);
                     lds_float *p = tb + sn * tsnap + (e0 * sx + e1 * sy + e2 * sz) * RS;
 #pragma unroll
                     for (int q = 0; q < NF; ++q) {
                         const R v = p[q];
-                        acc[q] += w * v;
+                        acc[q] = M<R>::fma_(w, v, acc[q]);
 #pragma unroll
-                        for (int k = 0; k < ND; ++k) dacc[k][q] += dw[k] * v;
+                        for (int k = 0; k < ND; ++k) dacc[k][q] = M<R>::fma_(dw[k], v, dacc[k][q]);
                     }
                 }
             }
@@ -815,15 +887,14 @@ __device__ __forceinline__ bool gather_d(const DevGrid &G, const int32_t *ibase,
             const R w = ws * w0 * w1 * w2;
             R dw[ND];
 #pragma unroll
-            for (int k = 0; k < ND; ++k)
-                dw[k] = ws * (g0 * w1 * w2 * dS[k][0] + w0 * g1 * w2 * dS[k][1] + w0 * w1 * g2 * dS[k][2]);
+            for (int k = 0; k < ND; ++k) dw[k] = corner_dw<R>(ws, w0, w1, w2, g0, g1, g2, dS[k]);
             const R *p = base + (e0 * sx + e1 * sy + e2 * sz) * RS;
 #pragma unroll
             for (int q = 0; q < NF; ++q) {
                 const R v = p[q];
-                acc[q] += w * v;
+                acc[q] = M<R>::fma_(w, v, acc[q]);
 #pragma unroll
-                for (int k = 0; k < ND; ++k) dacc[k][q] += dw[k] * v;
+                for (int k = 0; k < ND; ++k) dacc[k][q] = M<R>::fma_(dw[k], v, dacc[k][q]);
             }
         }
     }
@@ -946,8 +1017,11 @@ extern __shared__ __align__(16) unsigned char k_step_lds[];
 #ifndef FTE_STEP_WPE_F64
 #define FTE_STEP_WPE_F64 2
 #endif
-template <typename R, int MODE>
+template <typename R, bool KPERP, int MODE, bool TS2, bool ENS, bool SUB>
 constexpr int step_wpe() {
+    // the register-resident gather would otherwise take the allocator past
+    // 256 registers (one wave per SIMD)
+    if (unified_gather<R, KPERP, MODE, TS2, ENS, SUB>()) return 2;
     return MODE == 2 ? 1 : (std::is_same<R, float>::value ? FTE_STEP_WPE_F32 : FTE_STEP_WPE_F64);
 }
 // Most waves per SIMD the allocator plans for: 2 for the unrolled
@@ -962,7 +1036,7 @@ constexpr int step_wpe_max() {
 }
 
 template <typename R, bool KPERP, int MODE, bool LIDX, bool TS2, bool ENS, bool SUB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R, MODE>(), step_wpe_max<TS2>()))) void k_step(DevParams P, DevGrid G, DevState st, DevTan tn, DevCounters *cnt,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R, KPERP, MODE, TS2, ENS, SUB>(), step_wpe_max<TS2>()))) void k_step(DevParams P, DevGrid G, DevState st, DevTan tn, DevCounters *cnt,
                                               int slot, double *hist, double *sm, uint64_t n0, uint32_t n_steps,
                                               StepLds LD) {
     constexpr int ND = MODE == 2 ? 2 : 1;
@@ -1105,10 +1179,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
         uint64_t nstart = n0 > kinj ? n0 : kinj;
         for (uint64_t n = nstart; n < n_end; ++n) {
             // ---- clock and snapshot pair (identical for every particle)
-            const double t = P.t0 + (double)n * P.dt;
             int ks = 0;
             R alpha = (R)0;
             if (G.n_snap >= 2) {
+                const double t = P.t0 + (double)n * P.dt;
                 const double tau = (t - G.t_s0) * G.inv_dt_s;
                 double kf = ::floor(tau);
                 kf = kf < 0.0 ? 0.0 : (kf > (double)(G.n_snap - 2) ? (double)(G.n_snap - 2) : kf);
@@ -1151,7 +1225,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                     break;
                 }
             } else {
-                const int gr = gather<R, KPERP, TS2, kTile, SUB>(G, ibase, ichild, s, ks, alpha, acc, tile);
+                const int gr = gather<R, KPERP, TS2, kTile, SUB, unified_gather<R, KPERP, MODE, TS2, ENS, SUB>()>(G, ibase, ichild, s, ks, alpha, acc, tile);
                 if (gr != 0) {
                     if (SUB && gr == 2) atomicOr(&cnt->flags, kFlagNotResident);
                     status = FTE_PS_NUMERIC;
@@ -1431,6 +1505,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
             const bool in_obs_box = kF64 ? ((double)r >= P.obs_u[0] && (double)r < P.obs_u[1])
                                          : (r2 >= P.obs_u[2] && r2 < P.obs_u[3]);
             if (P.n_obs > 0 && in_obs_box && th >= (R)P.obs_u[4] && th < (R)P.obs_u[5]) {
+                const double t = P.t0 + (double)n * P.dt;
                 const double ut = (t + P.dt - P.t_ref) * P.inv_dT;
                 const double t1 = P.t0 + (double)(n + 1) * P.dt;
                 for (int o = 0; o < P.n_obs; ++o) {
