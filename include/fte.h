@@ -458,8 +458,10 @@ fte_status fte_set_launch(fte_ctx *ctx, int block, int steps_per_launch, int com
  * live snapshots in LDS, as many as tile_bytes holds (at least two layers,
  * else no tile), and reads the corners that lie in it from LDS instead of
  * through the cache.  Values, weights and summation order are those of the
- * global gather, so trajectories do not depend on it.  0 turns it off;
- * default 61440, at most FTE_MAX_TILE_BYTES.  FTE_EINVAL outside 0..max. */
+ * global gather, so trajectories do not depend on it.  tile_bytes caps the
+ * tile; the kernel also keeps it within the LDS that leaves two workgroups
+ * per compute unit (three on a steady grid).  0 turns it off; default and
+ * largest FTE_MAX_TILE_BYTES.  FTE_EINVAL outside 0..max. */
 #define FTE_MAX_TILE_BYTES 131072
 fte_status fte_set_record_tile(fte_ctx *ctx, int tile_bytes);
 

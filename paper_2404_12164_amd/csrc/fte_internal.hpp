@@ -122,34 +122,39 @@ struct DevTan {
 };
 enum : int { kTanLnw = 10, kTanCols = 11 };
 
-// LDS plan of a step launch: observer time bins [it_lo, it_lo + n_tb) are
-// accumulated in LDS (n_tb = 0: straight to the global histogram).  The block
-// index can be staged in LDS too (tables up to FTE_LDS_INDEX_BYTES); on the
-// CIR workload its 10 KB stay resident in L1/L2 and staging cost 0.5%, so it
-// is off unless the limit is raised at build time.
+// LDS plan of a step launch: observer time bins [it_lo, it_lo + n_tb) can be
+// accumulated in LDS (histograms up to FTE_LDS_HIST_BYTES; n_tb = 0: straight
+// to the global histogram).  Off by default: observer hits are rare enough
+// that the global atomics cost nothing measurable, and the record tile makes
+// better use of the LDS (a fourth k-layer on the CIR workload, +3.5%).  The
+// block index can be staged in LDS too (tables up to FTE_LDS_INDEX_BYTES); on
+// the CIR workload its 10 KB stay resident in L1/L2 and staging cost 0.5%, so
+// it is off unless the limit is raised at build time.
 //
 // Record tile: the float step kernels (histogram, smoothed and tangent
 // modes, single runs and ensembles, with or without cross-field records) on
-// time-dependent grids stage, per workgroup, whole padded k-layers of one leaf for both
-// live snapshots in LDS (as many as FTE_LDS_TILE_BYTES holds, at least two;
-// 0 turns it off; fte_set_record_tile sets it at run time), anchored at the
-// workgroup's middle particle; corners that
-// lie in it are read from LDS, the others through the L1.  After the spatial
-// sort a workgroup's particles sit in few k-layers of one leaf, and LDS serves
-// such divergent reads several times faster than the L1.
+// time-dependent grids stage, per workgroup, whole padded k-layers of one leaf
+// for both live snapshots in LDS (as many as fit the budget, at least two;
+// the budget is the LDS that leaves two workgroups per CU, three for the
+// steady-grid kernels, capped by FTE_LDS_TILE_BYTES; 0 turns it off;
+// fte_set_record_tile sets the cap at run time), anchored at the workgroup's
+// middle particle; corners that lie in it are read from LDS, the others
+// through the L1.  After the spatial sort a workgroup's particles sit in few
+// k-layers of one leaf, and LDS serves such divergent reads several times
+// faster than the L1.
 struct StepLds {
     int it_lo, n_tb;
     int tile_layers;  // padded k-layers in the tile (0: no tile)
     int tile_off;     // byte offset of the tile in the dynamic LDS
 };
 #ifndef FTE_LDS_HIST_BYTES
-#define FTE_LDS_HIST_BYTES 16384
+#define FTE_LDS_HIST_BYTES 0
 #endif
 #ifndef FTE_LDS_INDEX_BYTES
 #define FTE_LDS_INDEX_BYTES 0
 #endif
 #ifndef FTE_LDS_TILE_BYTES
-#define FTE_LDS_TILE_BYTES 61440
+#define FTE_LDS_TILE_BYTES 131072
 #endif
 constexpr size_t kLdsHistBytes = FTE_LDS_HIST_BYTES;
 constexpr size_t kLdsTileBytes = FTE_LDS_TILE_BYTES;

@@ -1700,13 +1700,13 @@ hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevTan
         // one of a steady grid) as fit, at least two
         const size_t nst = g.n_snap >= 2 ? 2 : 1;
         const size_t layer_bytes = (size_t)g.px[0] * g.px[1] * (kp ? kRSKperp : kRSPlain) * sizeof(float);
-        // the steady-grid kernel runs 3 waves per SIMD: keep three
-        // workgroups' LDS within the CU's 160 KB
-        size_t budget = tile_bytes;
-        if (nst == 1) {
-            const size_t third = (size_t)160 * 1024 / 3;
-            budget = budget < third - shmem - 64 ? budget : (third > shmem + 64 ? third - shmem - 64 : 0);
-        }
+        // LDS of two workgroups per CU within its 160 KB (the two-snapshot
+        // kernels run 2 waves per SIMD), of three for the steady-grid kernel
+        // (3 waves per SIMD); 1 KB of each share is left to the kernel's
+        // static LDS and the allocation granule
+        const size_t share = (size_t)160 * 1024 / (nst == 1 ? 3 : 2);
+        const size_t fit = share > shmem + 1024 ? share - shmem - 1024 : 0;
+        const size_t budget = tile_bytes < fit ? tile_bytes : fit;
         size_t tl = budget / (nst * layer_bytes);
         if (tl > (size_t)g.px[2]) tl = (size_t)g.px[2];
         if (tl >= 2) {
