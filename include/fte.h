@@ -268,14 +268,14 @@ typedef struct {
  * record(snap, leaf, pcell) at element ((snap * n_leaves + leaf) * pcells +
  * pcell) * stride, elements of double (FTE_FP64) or float (FTE_MIXED); the
  * stride is FTE_RECORD_STRIDE (10: fields 0-9) when kappa_perp is off and
- * FTE_RECORD_STRIDE_KPERP (14: fields 0-12 and one pad) when it is on.
+ * FTE_RECORD_STRIDE_KPERP (13: fields 0-12) when it is on.
  * pcell = (i+1) + (bx+2) ((j+1) + (by+2)(k+1)) for local cell (i, j, k) in
  * [-1, bx] x [-1, by] x [-1, bz]: a one-cell ghost layer.
  * Record fields: 0-2 V (r, theta, phi components), 3-5 b = B/|B| (same),
  * 6 div V, 7 bb:grad V, 8 div b, 9 b . (dV/dt + (V . grad)V), 10-12
  * (b . grad) b (spherical components). */
 #define FTE_RECORD_STRIDE 10
-#define FTE_RECORD_STRIDE_KPERP 14
+#define FTE_RECORD_STRIDE_KPERP 13
 #define FTE_RECORD_FIELDS 13
 
 /* Particle state buffer layout for capacity n_max: arrays of n_max entries

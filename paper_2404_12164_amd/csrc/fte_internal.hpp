@@ -11,7 +11,7 @@ constexpr double kC = 299792458.0;
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kNF = FTE_RECORD_FIELDS;
 constexpr int kRSPlain = FTE_RECORD_STRIDE;       // fields 0-9
-constexpr int kRSKperp = FTE_RECORD_STRIDE_KPERP; // fields 0-12 + pad
+constexpr int kRSKperp = FTE_RECORD_STRIDE_KPERP; // fields 0-12
 // Smoothing kernels are dropped beyond this many widths, where a Gaussian has
 // fallen to 1.5e-8 of its peak: the jump at the cut then adds no visible
 // boundary term to the derivatives taken along trajectories.

@@ -22,7 +22,7 @@ FTE_FP64, FTE_MIXED = 0, 1
 DMM = {"iso": 0, "eq5": 1, "power_q": 2}
 MAX_OBS = 8
 RECORD_STRIDE = 10        # fields 0-9 (no kappa_perp)
-RECORD_STRIDE_KPERP = 14  # fields 0-12 and one pad
+RECORD_STRIDE_KPERP = 13  # fields 0-12
 RECORD_FIELDS = 13
 STATUS = {"active": 0, "absorbed_in": 1, "absorbed_out": 2, "out_of_domain": 3, "numeric": 4, "done": 5}
 MAX_RUNS = 64

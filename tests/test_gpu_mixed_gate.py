@@ -7,7 +7,7 @@ grids they run on.
   a per-cell sort every 64 steps) and its float kernel with the unrolled
   two-snapshot gather and the LDS record tile; 2,800 steps.
 - Largest workload: the 3-level shocked-CIR grid (2,880 leaves, 96
-  snapshots) with cross-field records (the tile's 14-float instance).
+  snapshots) with cross-field records (the tile's 13-float instance).
 
 Particles: 40 blocks of consecutive pids spread over those that start during
 the 2,800 steps, with the workload's own stratified continuous injection, so
@@ -215,7 +215,7 @@ def test_mixed_gate_largest(F, torch_cuda, orc, largest):
 
 
 def test_record_tile_bit_identical_largest(F, torch_cuda, largest):
-    """Cross-field records (14 floats): tile on and off give identical
+    """Cross-field records (13 floats): tile on and off give identical
     trajectories on the 3-level grid, 10^6 particles, 1,152 steps."""
     cfg, raw = largest
     g, inj = cfg["grid"], cfg["injection"]

@@ -148,7 +148,7 @@ def test_records_match_oracle(F, torch_cuda, orc):
     rng = np.random.default_rng(0)
     bx = g["bx"]
     px = [b + 2 for b in bx]
-    nf = 13 if rec.shape[-1] == 14 else 10
+    nf = 13 if rec.shape[-1] == 13 else 10
     scale = np.abs(rec[..., :nf]).reshape(-1, nf).max(axis=0)
     n = 0
     for leaf in rng.choice(len(g["leaves"]), size=40, replace=False):

@@ -58,7 +58,7 @@ def test_query_sizes_amr_cir(F):
     nl = len(cfg["grid"]["leaves"])
     assert s.grid_bytes == 3 * nl * 18 * 14 * 18 * 10 * 4
     kp = dict(cfg["params"], kperp_ratio=0.01)
-    assert F.fte_query_sizes(kp, cfg["grid"], 1000).grid_bytes == 3 * nl * 18 * 14 * 18 * 14 * 4
+    assert F.fte_query_sizes(kp, cfg["grid"], 1000).grid_bytes == 3 * nl * 18 * 14 * 18 * 13 * 4
 
 
 def _tiny_grid(**over):
@@ -134,7 +134,7 @@ def test_ensemble_sizes_and_rejections(F):
     one = F.fte_query_sizes(p, cfg["grid"], 100)
     two = F.fte_query_sizes(dict(p, runs=runs), cfg["grid"], 100)
     assert two.hist_bytes == 2 * one.hist_bytes              # sums per run
-    assert two.grid_bytes == one.grid_bytes // 10 * 14       # a run with kappa_perp: 13-field records
+    assert two.grid_bytes == one.grid_bytes // 10 * 13       # a run with kappa_perp: 13-field records
     bad = [[dict(lambda_ref=-1.0, n_steps=5)], [dict(lambda_ref=1e10, n_steps=0)],
            [dict(lambda_ref=1e10, kperp_ratio=-0.1, n_steps=5)], [dict(lambda_ref=1e10, n_steps=5)] * 65]
     for r in bad:
@@ -162,13 +162,13 @@ def test_streaming_grid_sizes(F):
 def test_largest_workload_sizes(F):
     """The largest workload (shocked CIR, 3 levels, 96 snapshots, kappa_perp,
     10^8 particles) validates, and its buffers fit one GPU's 288 GB: records
-    of 14 floats per padded cell for every snapshot, the particle state twice
+    of 13 floats per padded cell for every snapshot, the particle state twice
     (compaction ping-pong), the 5 x 20 x 288 x 32 observer sums."""
     cfg = W.cir_largest()
     g, p = cfg["grid"], cfg["params"]
     s = F.fte_query_sizes(p, g, cfg["n_particles"])
     nl = len(g["leaves"])
-    assert s.grid_bytes == 96 * nl * 18 * 10 * 18 * 14 * 4
+    assert s.grid_bytes == 96 * nl * 18 * 10 * 18 * 13 * 4
     assert s.hist_bytes >= 5 * 20 * 288 * 32 * 8
     total = s.grid_bytes + s.index_bytes + 2 * s.state_bytes + s.hist_bytes + s.work_bytes
     print("largest workload: grid", s.grid_bytes / 1e9, "GB, state", s.state_bytes / 1e9, "GB, total",
