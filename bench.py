@@ -134,6 +134,41 @@ def timed(run, K, chunk, total=None):
                 global_steps=done)
 
 
+def graph_leg(run, K, chunk, total, j_direct):
+    """The same run recorded as one launch graph (fte_capture_begin/end) and
+    replayed from a reset: its time next to the direct calls', and the
+    largest difference of the binned intensities."""
+    torch = run.torch
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        run.reset()
+        t = time.time()
+        run.sim.capture_begin()
+        done = 0
+        for k in range(K):
+            n = max(0, min(chunk, total - done))
+            if n > 0:
+                run.chunk(n)
+            done += n
+        graph = run.sim.capture_end()
+        build_s = time.time() - t
+        run.reset()
+        st0 = run.sim.stats()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run.sim.graph_launch(graph)
+        e1.record()
+        side.synchronize()
+        ms = e0.elapsed_time(e1)
+        st1 = run.sim.stats()
+        js, _ = run.sim.bin_observers()
+        graph.close()
+    steps = int(st1.particle_steps - st0.particle_steps)
+    return dict(ms=round(ms, 1), particle_steps=steps, value=steps / (ms / 1e3), record_and_instantiate_s=round(build_s, 2),
+                max_abs_diff_j_vs_direct=float(np.abs(js - j_direct).max()))
+
+
 def gradient_leg(F, W, raw, args):
     """Differentiation workload (10^6 protons, 8,000 steps, smoothed
     intensities at the three 1-au observers): time of the plain forward pass,
@@ -316,6 +351,55 @@ def ensemble_leg(F, W, args):
                autotune_s=round(t_tune, 2))
     ms0, steps0, _, _ = ensemble(False)
     out.update(ensemble_untuned_ms=round(ms0, 1))
+    if best and not args.no_graph:
+        # the whole ensemble at the tuned launch shape, its calls made
+        # directly without a synchronisation between chunks, then recorded
+        # as one launch graph and replayed from a reset
+        def calls(sim):
+            injected = [0] * len(cfg["injections"])
+            n0 = 0
+            while n0 < cfg["n_steps"]:
+                n1 = min(n0 + chunk, cfg["n_steps"])
+                for r, inj in enumerate(cfg["injections"]):
+                    S, Nr = inj["n_inj_steps"], inj["n_total"]
+                    j_max = min(Nr, int(math.ceil(n1 * Nr / S)) + 1)
+                    if j_max > injected[r]:
+                        sim.inject(inj, j_max - injected[r], inj["pid0"] + injected[r])
+                        injected[r] = j_max
+                sim.step(n1 - n0)
+                n0 = n1
+        side = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            sim = F.Simulation(p, g, N)
+            sim.load_grid(raw)
+            sim.set_launch(best[0], best[1], best[2], args.sort)
+            side.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            calls(sim)
+            e1.record()
+            side.synchronize()
+            direct_ms = e0.elapsed_time(e1)
+            direct_steps = int(sim.stats().particle_steps)
+            sim.reset()
+            t = time.time()
+            sim.capture_begin()
+            calls(sim)
+            gr = sim.capture_end()
+            build_s = time.time() - t
+            sim.reset()
+            e0.record()
+            sim.graph_launch(gr)
+            e1.record()
+            side.synchronize()
+            graph_ms = e0.elapsed_time(e1)
+            graph_steps = int(sim.stats().particle_steps)
+            gr.close()
+            sim.close()
+        out["graph"] = dict(direct_ms=round(direct_ms, 1), graph_ms=round(graph_ms, 1),
+                            vs_direct=round(direct_ms / graph_ms, 4), record_and_instantiate_s=round(build_s, 2),
+                            particle_steps_equal=direct_steps == graph_steps)
     # the same runs one context at a time (each loads the grid; not timed)
     seq_ms = 0.0
     seq_steps = 0
@@ -679,6 +763,7 @@ def main():
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's CIR experiment at 1-3 AMR levels")
     ap.add_argument("--no-stream", action="store_true", help="skip the snapshot-streaming run of the CIR workload")
     ap.add_argument("--no-pool", action="store_true", help="skip the leaf-pool streaming run of the largest workload")
+    ap.add_argument("--no-graph", action="store_true", help="skip the launch-graph replays (main run, ensemble)")
     ap.add_argument("--cpu-pids", type=int, default=4000)
     ap.add_argument("--cpu-pids-1", type=int, default=250, help="pids of the single-thread oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=2800)
@@ -732,6 +817,11 @@ def main():
     js, _ = run.sim.bin_observers()
     st = res["stats"]
     grid_load_s = run.load_s
+    graph = None
+    if not args.no_graph:
+        log("the same run recorded as one launch graph and replayed")
+        graph = graph_leg(run, K, chunk, total_steps, js)
+        graph["vs_direct"] = round(graph["value"] / value, 4)
     run.close()
     del run
     log(f"  {value:.4g} particle-steps/s over {res['global_steps']} global steps")
@@ -877,6 +967,7 @@ def main():
         "grid_load_s": round(grid_load_s, 2),
         "observer_counts_nonzero": int((js > 0).sum()),
         "retired": [int(v) for v in st.n_retired],
+        "graph": graph,
     }
     out.update(extra)
     print(json.dumps(out))

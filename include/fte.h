@@ -465,6 +465,38 @@ fte_status fte_set_launch(fte_ctx *ctx, int block, int steps_per_launch, int com
 #define FTE_MAX_TILE_BYTES 131072
 fte_status fte_set_record_tile(fte_ctx *ctx, int tile_bytes);
 
+/* Launch graphs for ensembles and repeated runs (a launch mechanism, not an
+ * operation of the method): record what a sequence of fte_inject and
+ * fte_step_n calls
+ * enqueues on one stream as one HIP graph, then run it with a single launch
+ * instead of one launch per kernel.
+ *
+ * fte_capture_begin starts a stream capture on `stream` (it first settles
+ * the live count of the last compaction, which the recording cannot read
+ * back).  Until fte_capture_end only fte_inject and fte_step_n may be called
+ * on the context (the others return FTE_ESTATE); they validate their
+ * arguments as usual and record their kernels without running them, with
+ * launches sized by the particles injected so far (the recording skips the
+ * live-count read-back and the per-launch timing events).  fte_capture_end
+ * ends the capture on the same stream, instantiates the graph, returns it in
+ * *out (owned by the caller, freed by fte_graph_destroy) and puts the
+ * context back in the state it had at fte_capture_begin: nothing has run.
+ * FTE_EDEVICE if HIP rejects the capture or the instantiation.
+ *
+ * fte_graph_launch runs the graph on `stream`.  The context must be at the
+ * global step, particle buffer and compaction phase the recording began at
+ * (checked, FTE_ESTATE otherwise), and its device state must be the one the
+ * recording began from (not checked: e.g. record after fte_reset and launch
+ * after another fte_reset).  The grid, launch shape and record tile are
+ * those of the recording.  Afterwards the context is where the recorded
+ * calls leave it.  Trajectories and sums are those of the same calls made
+ * directly (the kernels are the same; only the launch sizes differ). */
+typedef struct fte_graph fte_graph;
+fte_status fte_capture_begin(fte_ctx *ctx, void *stream);
+fte_status fte_capture_end(fte_ctx *ctx, void *stream, fte_graph **out);
+fte_status fte_graph_launch(fte_ctx *ctx, fte_graph *graph, void *stream);
+void fte_graph_destroy(fte_graph *graph);
+
 /* Self-tuning of the launch shape: from the current state, run trial_steps
  * global steps under each candidate (block size x compaction interval, steps
  * per launch fixed), timing the step and compaction kernels with HIP events,

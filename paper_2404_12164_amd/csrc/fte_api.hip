@@ -18,6 +18,12 @@
 
 using namespace fte;
 
+// Host-side stepping state that a recorded graph starts from and leaves.
+struct HostClock {
+    uint64_t global_step, since_compact, n_upper, injected_since;
+    int cur;
+};
+
 struct fte_ctx {
     fte_params p{};
     std::vector<fte_run> runs;     // copy of the ensemble table
@@ -64,7 +70,18 @@ struct fte_ctx {
     size_t tev_used = 0;
     double timed_ms = 0.0;
     uint32_t timed_launches = 0;
+    // launch-graph recording (fte_capture_begin .. fte_capture_end)
+    bool capturing = false;
+    hipStream_t cap_stream = nullptr;
+    HostClock graph_start{};
     std::string err;
+};
+
+struct fte_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    fte_ctx *ctx = nullptr;
+    HostClock start{}, end{};
 };
 
 namespace {
@@ -73,6 +90,14 @@ fte_status fail(fte_ctx *c, fte_status s, const std::string &msg) {
     if (c) c->err = msg;
     return s;
 }
+
+// Entry points that synchronise or read back refuse to run while a launch
+// graph is being recorded (only fte_inject and fte_step_n are recorded).
+#define NO_CAPTURE(ctx)                                                                            \
+    do {                                                                                           \
+        if ((ctx)->capturing)                                                                      \
+            return fail(ctx, FTE_ESTATE, "only fte_inject and fte_step_n may run while recording a graph"); \
+    } while (0)
 
 #define HIPCHK(ctx, expr)                                                                          \
     do {                                                                                           \
@@ -552,6 +577,11 @@ fte_status fte_create(fte_ctx **out, const fte_params *p) {
 
 void fte_destroy(fte_ctx *c) {
     if (!c) return;
+    if (c->capturing) {
+        // an unfinished recording: end it so that its stream is usable again
+        hipGraph_t g = nullptr;
+        if (hipStreamEndCapture(c->cap_stream, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+    }
     if (c->ev) (void)hipEventDestroy(c->ev);
     for (auto e : c->tev) (void)hipEventDestroy(e);
     if (c->pinned) (void)hipHostFree(c->pinned);
@@ -577,6 +607,7 @@ fte_status fte_query_sizes(const fte_params *p, const fte_grid_desc *g, uint64_t
 
 fte_status fte_bind_buffers(fte_ctx *c, const fte_grid_desc *g, uint64_t n_max, const fte_buffers *b) {
     if (!c) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (!b) return fail(c, FTE_EINVAL, "buffers is NULL");
     std::vector<int32_t> base, child, info;
     const std::string e = build_index(g, base, child, info);
@@ -760,6 +791,7 @@ static bool window_needs(int ns, int k, int j) {
 
 fte_status fte_load_grid(fte_ctx *c, const double *vb, void *stream) {
     if (!c) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (!c->bound) return fail(c, FTE_ESTATE, "bind buffers before loading the grid");
     if (!vb) return fail(c, FTE_EINVAL, "wind data is NULL");
     const DevGrid &d = c->dg;
@@ -825,6 +857,7 @@ extern "C" {
 fte_status fte_plan_snapshot(fte_ctx *c, int k, const fte_injection *sources, int n_sources, double wind_speed_max,
                              int32_t *leaves_out, uint64_t cap, uint64_t counts[3], void *stream) {
     if (!c) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (!c->bound) return fail(c, FTE_ESTATE, "bind buffers before planning snapshots");
     const DevGrid &d = c->dg;
     if (!d.pool_map) return fail(c, FTE_EINVAL, "the grid holds every leaf (n_pool = 0): nothing to plan");
@@ -998,6 +1031,7 @@ fte_status fte_plan_snapshot(fte_ctx *c, int k, const fte_injection *sources, in
 
 fte_status fte_load_snapshot(fte_ctx *c, int k, const double *const raw[5], void *stream) {
     if (!c) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (!c->bound) return fail(c, FTE_ESTATE, "bind buffers before loading snapshots");
     if (!raw) return fail(c, FTE_EINVAL, "raw is NULL");
     const DevGrid &d = c->dg;
@@ -1119,6 +1153,8 @@ fte_status fte_inject(fte_ctx *c, const fte_injection *inj, uint64_t n, uint64_t
     if (n == 0) return FTE_OK;
     hipStream_t s = (hipStream_t)stream;
     if (c->n_upper + n > c->n_max) {
+        if (c->capturing) return fail(c, FTE_ENOMEM, "particle capacity exceeded (while recording, retired "
+                                                     "particles are not subtracted)");
         fte_status r = refresh_exact(c, s);
         if (r != FTE_OK) return r;
         if (c->n_upper + n > c->n_max) return fail(c, FTE_ENOMEM, "particle capacity exceeded");
@@ -1154,7 +1190,10 @@ fte_status fte_step_n(fte_ctx *c, uint32_t n_steps, void *stream) {
             c->pending = false;
         }
         const uint32_t chunk = left < (uint32_t)c->spl ? left : (uint32_t)c->spl;
-        if (c->timing) {
+        // (a recorded graph carries no timing events and no read-back of
+        // the live count: its launches are sized by the injected total)
+        const bool timed = c->timing && !c->capturing;
+        if (timed) {
             if (c->tev_used + 2 > c->tev.size()) {
                 fte_status r = drain_timing(c, s);
                 if (r != FTE_OK) return r;
@@ -1163,7 +1202,7 @@ fte_status fte_step_n(fte_ctx *c, uint32_t n_steps, void *stream) {
         }
         HIPCHK(c, launch_step(c->dp, c->dg, c->st[c->cur], c->tn[c->cur], c->cnt, c->cur, (double *)c->b.hist, c->sm,
                               c->global_step, chunk, c->n_upper, c->block, c->p.precision == FTE_MIXED, c->tile_bytes, s));
-        if (c->timing) {
+        if (timed) {
             HIPCHK(c, hipEventRecord(c->tev[c->tev_used + 1], s));
             c->tev_used += 2;
         }
@@ -1183,11 +1222,13 @@ fte_status fte_step_n(fte_ctx *c, uint32_t n_steps, void *stream) {
             }
             c->cur = to;
             c->since_compact = 0;
-            HIPCHK(c, hipMemcpyAsync(c->pinned, &c->cnt->n_live[to], sizeof(unsigned long long),
-                                     hipMemcpyDeviceToHost, s));
-            HIPCHK(c, hipEventRecord(c->ev, s));
-            c->pending = true;
-            c->injected_since = 0;
+            if (!c->capturing) {
+                HIPCHK(c, hipMemcpyAsync(c->pinned, &c->cnt->n_live[to], sizeof(unsigned long long),
+                                         hipMemcpyDeviceToHost, s));
+                HIPCHK(c, hipEventRecord(c->ev, s));
+                c->pending = true;
+                c->injected_since = 0;
+            }
         }
     }
     return FTE_OK;
@@ -1195,6 +1236,7 @@ fte_status fte_step_n(fte_ctx *c, uint32_t n_steps, void *stream) {
 
 fte_status fte_bin_observers(fte_ctx *c, double *j, double *sigma, int reset, void *stream) {
     if (!c) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (!c->loaded) return fail(c, FTE_ESTATE, "nothing to bin before the grid is loaded");
     hipStream_t s = (hipStream_t)stream;
     const size_t nb = (size_t)obs_bins(&c->p) * c->p.n_e * c->p.n_t * runs_eff(&c->p);
@@ -1210,6 +1252,7 @@ fte_status fte_bin_observers(fte_ctx *c, double *j, double *sigma, int reset, vo
 
 fte_status fte_bin_observers_static(fte_ctx *c, double *j, double *sigma, int reset, void *stream) {
     if (!c) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (!c->loaded) return fail(c, FTE_ESTATE, "nothing to bin before the grid is loaded");
     hipStream_t s = (hipStream_t)stream;
     const size_t nb = (size_t)obs_bins(&c->p) * c->p.n_e * c->p.n_t * runs_eff(&c->p);
@@ -1228,6 +1271,7 @@ fte_status fte_bin_observers_static(fte_ctx *c, double *j, double *sigma, int re
 
 fte_status fte_bin_steady(fte_ctx *c, double *J, double *sigma, void *stream) {
     if (!c) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (!c->loaded) return fail(c, FTE_ESTATE, "nothing to bin before the grid is loaded");
     hipStream_t s = (hipStream_t)stream;
     const size_t nb = (size_t)obs_bins(&c->p) * c->p.n_e * runs_eff(&c->p);
@@ -1242,6 +1286,7 @@ fte_status fte_bin_steady(fte_ctx *c, double *J, double *sigma, void *stream) {
 
 fte_status fte_read_hist(fte_ctx *c, double *sums, double *w_injected, void *stream) {
     if (!c) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
     hipStream_t s = (hipStream_t)stream;
     if (sums && c->hist_n) HIPCHK(c, hipMemcpyAsync(sums, c->b.hist, c->hist_n * 8, hipMemcpyDeviceToHost, s));
@@ -1259,6 +1304,7 @@ fte_status fte_read_hist(fte_ctx *c, double *sums, double *w_injected, void *str
 
 fte_status fte_get_stats(fte_ctx *c, fte_stats *out, void *stream) {
     if (!c || !out) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
     hipStream_t s = (hipStream_t)stream;
     if (c->timing) {
@@ -1288,6 +1334,7 @@ fte_status fte_get_stats(fte_ctx *c, fte_stats *out, void *stream) {
 
 fte_status fte_reset(fte_ctx *c, void *stream) {
     if (!c) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(c, hipStreamSynchronize(s));
@@ -1309,6 +1356,7 @@ fte_status fte_reset(fte_ctx *c, void *stream) {
 
 fte_status fte_set_timing(fte_ctx *c, int enable) {
     if (!c) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (c->tev_used) return fail(c, FTE_ESTATE, "read the stats before switching timing");
     c->timing = enable != 0;
     if (c->timing && c->tev.empty()) {
@@ -1321,6 +1369,7 @@ fte_status fte_set_timing(fte_ctx *c, int enable) {
 fte_status fte_read_particles(fte_ctx *c, double *x3, double *mu, double *lnp, double *w, uint64_t *pid,
                               uint32_t *kinj, int32_t *status, uint64_t cap, uint64_t *n_out, void *stream) {
     if (!c) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
     hipStream_t s = (hipStream_t)stream;
     unsigned long long n = 0;
@@ -1368,6 +1417,7 @@ static fte_status smoothed_sums(fte_ctx *c, hipStream_t s, double *W, double *dW
 
 fte_status fte_bin_smoothed(fte_ctx *c, double *J, double *dJ, void *stream) {
     if (!c) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
     if (!(c->p.sigma_x > 0.0)) return fail(c, FTE_ESTATE, "smoothed intensities are off (sigma_x = 0)");
     if (dJ && !c->p.grad) return fail(c, FTE_ESTATE, "derivatives need gradient mode");
@@ -1396,6 +1446,7 @@ fte_status fte_bin_smoothed(fte_ctx *c, double *J, double *dJ, void *stream) {
 
 fte_status fte_grad(fte_ctx *c, const double *dL_dJ, double grad[3], void *stream) {
     if (!c) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
     if (!c->p.grad) return fail(c, FTE_ESTATE, "gradient mode is off");
     if (!dL_dJ || !grad) return fail(c, FTE_EINVAL, "dL_dJ and grad must be non-NULL");
@@ -1419,6 +1470,7 @@ fte_status fte_grad(fte_ctx *c, const double *dL_dJ, double grad[3], void *strea
 
 fte_status fte_read_tangents(fte_ctx *c, double *tan, uint64_t cap, uint64_t *n_out, void *stream) {
     if (!c) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
     if (!c->p.grad) return fail(c, FTE_ESTATE, "gradient mode is off");
     hipStream_t s = (hipStream_t)stream;
@@ -1524,6 +1576,7 @@ fte_status fte_state_size(fte_ctx *c, uint64_t *bytes, void *stream) {
 
 fte_status fte_save_state(fte_ctx *c, void *blob, uint64_t bytes, void *stream) {
     if (!c || !blob) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
     hipStream_t s = (hipStream_t)stream;
     DevCounters h;
@@ -1571,6 +1624,7 @@ fte_status fte_save_state(fte_ctx *c, void *blob, uint64_t bytes, void *stream) 
 
 fte_status fte_load_state(fte_ctx *c, const void *blob, uint64_t bytes, void *stream) {
     if (!c || !blob) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (!c->loaded) return fail(c, FTE_ESTATE, "load the grid before restoring a state");
     if (bytes < sizeof(StateHeader)) return fail(c, FTE_EINVAL, "state blob too short");
     StateHeader hd;
@@ -1623,6 +1677,7 @@ fte_status fte_load_state(fte_ctx *c, const void *blob, uint64_t bytes, void *st
 
 fte_status fte_autotune(fte_ctx *c, uint32_t trial_steps, int best[3], void *stream) {
     if (!c || !best) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (!c->loaded) return fail(c, FTE_ESTATE, "grid not loaded");
     if (trial_steps < 1) return fail(c, FTE_EINVAL, "trial_steps must be >= 1");
     hipStream_t s = (hipStream_t)stream;
@@ -1687,6 +1742,7 @@ fte_status fte_autotune(fte_ctx *c, uint32_t trial_steps, int best[3], void *str
 
 fte_status fte_set_launch(fte_ctx *c, int block, int steps_per_launch, int compact_every, int spatial_sort) {
     if (!c) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (block < 64 || block > 256 || (block & 63)) return fail(c, FTE_EINVAL, "block must be 64..256, multiple of 64");
     if (steps_per_launch < 1) return fail(c, FTE_EINVAL, "steps_per_launch must be >= 1");
     if (compact_every < 0 || (compact_every && compact_every % steps_per_launch))
@@ -1704,6 +1760,7 @@ fte_status fte_set_launch(fte_ctx *c, int block, int steps_per_launch, int compa
 
 fte_status fte_set_record_tile(fte_ctx *c, int tile_bytes) {
     if (!c) return FTE_EINVAL;
+    NO_CAPTURE(c);
     if (tile_bytes < 0 || tile_bytes > FTE_MAX_TILE_BYTES)
         return fail(c, FTE_EINVAL, "tile_bytes must be 0.." + std::to_string(FTE_MAX_TILE_BYTES));
     c->tile_bytes = (size_t)tile_bytes;
@@ -1711,3 +1768,94 @@ fte_status fte_set_record_tile(fte_ctx *c, int tile_bytes) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// launch graphs
+// ---------------------------------------------------------------------------
+namespace {
+HostClock clock_of(const fte_ctx *c) {
+    return HostClock{c->global_step, c->since_compact, c->n_upper, c->injected_since, c->cur};
+}
+void set_clock(fte_ctx *c, const HostClock &k) {
+    c->global_step = k.global_step;
+    c->since_compact = k.since_compact;
+    c->n_upper = k.n_upper;
+    c->injected_since = k.injected_since;
+    c->cur = k.cur;
+}
+}  // namespace
+
+fte_status fte_capture_begin(fte_ctx *c, void *stream) {
+    if (!c) return FTE_EINVAL;
+    NO_CAPTURE(c);
+    if (!c->loaded) return fail(c, FTE_ESTATE, "load the grid before recording");
+    hipStream_t s = (hipStream_t)stream;
+    // settle the live count of the last compaction first: the recording
+    // cannot read it back
+    if (c->pending) {
+        HIPCHK(c, hipEventSynchronize(c->ev));
+        c->n_upper = *c->pinned + c->injected_since;
+        c->pending = false;
+    }
+    HIPCHK(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    c->capturing = true;
+    c->cap_stream = s;
+    c->graph_start = clock_of(c);
+    return FTE_OK;
+}
+
+fte_status fte_capture_end(fte_ctx *c, void *stream, fte_graph **out) {
+    if (!c || !out) return FTE_EINVAL;
+    *out = nullptr;
+    if (!c->capturing) return fail(c, FTE_ESTATE, "no recording in progress");
+    hipStream_t s = (hipStream_t)stream;
+    if (s != c->cap_stream) return fail(c, FTE_EINVAL, "end the recording on the stream it began on");
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &graph);
+    c->capturing = false;
+    const HostClock end = clock_of(c);
+    set_clock(c, c->graph_start);      // nothing ran: back to where the recording began
+    if (e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(c, FTE_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(c, FTE_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    fte_graph *g = new fte_graph;
+    g->graph = graph;
+    g->exec = exec;
+    g->ctx = c;
+    g->start = c->graph_start;
+    g->end = end;
+    *out = g;
+    return FTE_OK;
+}
+
+fte_status fte_graph_launch(fte_ctx *c, fte_graph *g, void *stream) {
+    if (!c || !g) return FTE_EINVAL;
+    NO_CAPTURE(c);
+    if (g->ctx != c) return fail(c, FTE_EINVAL, "the graph was recorded on another context");
+    const HostClock k = clock_of(c);
+    if (k.global_step != g->start.global_step || k.cur != g->start.cur || k.since_compact != g->start.since_compact)
+        return fail(c, FTE_ESTATE, "the context is not at the global step, particle buffer and compaction phase "
+                                   "the recording began at");
+    hipStream_t s = (hipStream_t)stream;
+    if (c->pending) {
+        HIPCHK(c, hipEventSynchronize(c->ev));
+        c->pending = false;
+    }
+    HIPCHK(c, hipGraphLaunch(g->exec, s));
+    set_clock(c, g->end);
+    return FTE_OK;
+}
+
+void fte_graph_destroy(fte_graph *g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}

@@ -30,7 +30,8 @@ SYMBOLS = ["fte_create", "fte_destroy", "fte_last_error", "fte_query_sizes", "ft
            "fte_inject", "fte_step_n", "fte_bin_observers", "fte_read_hist", "fte_get_stats", "fte_read_particles",
            "fte_set_launch", "fte_reset", "fte_set_timing", "fte_bin_smoothed", "fte_grad", "fte_read_tangents",
            "fte_state_size", "fte_save_state", "fte_load_state", "fte_autotune", "fte_bin_steady",
-           "fte_load_snapshot", "fte_set_record_tile", "fte_plan_snapshot", "fte_bin_observers_static"]
+           "fte_load_snapshot", "fte_set_record_tile", "fte_plan_snapshot", "fte_bin_observers_static",
+           "fte_capture_begin", "fte_capture_end", "fte_graph_launch", "fte_graph_destroy"]
 TANGENT_COLS = 11         # d(x, y, z, mu, lnp)/d lambda_ref, the same for kperp_ratio, d ln w / d gamma_inj
 
 
@@ -135,11 +136,28 @@ def lib():
         L.fte_autotune.argtypes = [vp, u32, C.POINTER(C.c_int), vp]
         L.fte_bin_steady.argtypes = [vp, dp, dp, vp]
         L.fte_load_snapshot.argtypes = [vp, C.c_int, C.POINTER(vp), vp]
+        L.fte_capture_begin.argtypes = [vp, vp]
+        L.fte_capture_end.argtypes = [vp, vp, C.POINTER(vp)]
+        L.fte_graph_launch.argtypes = [vp, vp, vp]
+        L.fte_graph_destroy.argtypes = [vp]
+        L.fte_graph_destroy.restype = None
         for name in SYMBOLS:
-            if name not in ("fte_destroy", "fte_last_error"):
+            if name not in ("fte_destroy", "fte_last_error", "fte_graph_destroy"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
+
+
+class Graph:
+    """A recorded launch graph (fte_capture_end); free it with close()."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def close(self):
+        if self.handle:
+            fte_graph_destroy(self.handle)
+            self.handle = None
 
 
 class FteError(RuntimeError):
@@ -438,6 +456,24 @@ def fte_set_record_tile(ctx, tile_bytes: int):
     _check(ctx, lib().fte_set_record_tile(ctx, int(tile_bytes)))
 
 
+def fte_capture_begin(ctx, stream: int):
+    _check(ctx, lib().fte_capture_begin(ctx, C.c_void_p(stream)))
+
+
+def fte_capture_end(ctx, stream: int):
+    g = C.c_void_p()
+    _check(ctx, lib().fte_capture_end(ctx, C.c_void_p(stream), C.byref(g)))
+    return g
+
+
+def fte_graph_launch(ctx, graph, stream: int):
+    _check(ctx, lib().fte_graph_launch(ctx, graph, C.c_void_p(stream)))
+
+
+def fte_graph_destroy(graph):
+    lib().fte_graph_destroy(graph)
+
+
 def fte_reset(ctx, stream: int):
     _check(ctx, lib().fte_reset(ctx, C.c_void_p(stream)))
 
@@ -534,6 +570,17 @@ class Simulation:
 
     def set_timing(self, enable=True):
         fte_set_timing(self.ctx, enable)
+
+    def capture_begin(self):
+        """Record the following inject/step calls into a launch graph (nothing runs)."""
+        fte_capture_begin(self.ctx, self.stream)
+
+    def capture_end(self):
+        """End the recording: a Graph to launch with graph_launch."""
+        return Graph(fte_capture_end(self.ctx, self.stream))
+
+    def graph_launch(self, graph):
+        fte_graph_launch(self.ctx, graph.handle, self.stream)
 
     def inject(self, inj: dict, n: int, first_pid: int):
         fte_inject(self.ctx, inj, n, first_pid, self.stream)
