@@ -70,6 +70,7 @@ def test_graph_replays_match_direct_calls(F, torch_cuda, precision):
     vb = W.make_raw(g, cfg["wind"], xp=torch, device=torch.device("cuda:0"))
     per = int(g["dt_s"] / p["dt"])
     chunks = [150, per - 150, 2 * per + 37, 90]          # crosses compactions and snapshot intervals
+    torch.cuda.synchronize()                            # the wind was made on the default stream
     side = torch.cuda.Stream()                          # capture needs a stream other than the default
     with torch.cuda.stream(side):
         sim = F.Simulation(p, g, n)
