@@ -440,6 +440,8 @@ def largest_leg(F, W, args, hours=None):
     dev = torch.device("cuda:0")
     c = W.cir_largest(precision=args.precision)
     g = c["grid"]
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()       # this leg's own peak below
     t = time.time()
     raw = W.make_raw(g, c["wind"], xp=torch, device=dev)
     torch.cuda.synchronize()
