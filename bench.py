@@ -185,6 +185,8 @@ def gradient_leg(F, W, raw, args):
     n_steps = cfg["n_steps"]
     chunk = n_steps // 10
     p_grad = cfg["params"]
+    if args.kink_sigma is not None:
+        p_grad = dict(p_grad, kink_sigma=args.kink_sigma)
     p_smooth = dict(p_grad, grad=0)
     p_plain = {k: v for k, v in p_grad.items() if k not in ("smoothing", "grad", "kink_sigma")}
 
@@ -758,6 +760,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--grad-seeds", type=int, default=8, help="seeds of the gradient-vs-differences check")
+    ap.add_argument("--kink-sigma", type=float, default=None,
+                    help="width of the Gaussian mu = 0 term of the gradient leg (default: the workload's)")
     ap.add_argument("--no-largest", action="store_true", help="skip the largest workload")
     ap.add_argument("--largest-hours", type=float, default=None,
                     help="hours of the largest workload to time (default: the whole 95 h run)")
