@@ -21,7 +21,13 @@ def build(verbose: bool = False, defines=(), out: str = None) -> str:
     step kernel); ``out`` another path for the library."""
     lib = out or LIB
     objs = []
+    # -ffp-contract=on: a fused multiply-add only where one source expression
+    # has the a * b + c shape, decided by the front end; the default (fast)
+    # lets the back end fuse a product into a sum of another statement when
+    # both land in one basic block, so that the same arithmetic could round
+    # differently in two kernel instances whose branches differ
     common = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall", "-Wno-unused-result",
+              "-ffp-contract=on",
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics",
               "-I", os.path.join(HERE, "..", "include")]
     for src in SOURCES:
