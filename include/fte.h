@@ -465,6 +465,17 @@ fte_status fte_set_launch(fte_ctx *ctx, int block, int steps_per_launch, int com
 #define FTE_MAX_TILE_BYTES 131072
 fte_status fte_set_record_tile(fte_ctx *ctx, int tile_bytes);
 
+/* LDS-privatised observer histogram: the observer time bins a step launch
+ * can touch (its first to last post-step time) are accumulated in LDS when
+ * their sums fit hist_bytes, and flushed with one global atomic per nonzero
+ * bin at the end of the launch; otherwise every contribution is a global
+ * atomic.  Counts are the same either way, sums equal up to the order of the
+ * additions; the LDS it takes is no longer available to the record tile.
+ * 0 (the default) keeps the sums in global memory.  FTE_EINVAL outside
+ * 0..FTE_MAX_LDS_HIST_BYTES. */
+#define FTE_MAX_LDS_HIST_BYTES 32768
+fte_status fte_set_lds_histogram(fte_ctx *ctx, int hist_bytes);
+
 /* Launch graphs for ensembles and repeated runs (a launch mechanism, not an
  * operation of the method): record what a sequence of fte_inject and
  * fte_step_n calls

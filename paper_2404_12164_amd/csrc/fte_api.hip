@@ -64,6 +64,7 @@ struct fte_ctx {
     uint64_t global_step = 0;
     int block = 256, spl = 32, compact_every = 128;
     size_t tile_bytes = kLdsTileBytes;   // LDS record tile budget of the float step kernels
+    size_t hist_bytes = kLdsHistBytes;   // LDS observer-histogram budget of the step kernels
     uint64_t since_compact = 0;
     bool timing = false;
     std::vector<hipEvent_t> tev;   // pairs: start, stop of each timed launch
@@ -1201,7 +1202,7 @@ fte_status fte_step_n(fte_ctx *c, uint32_t n_steps, void *stream) {
             HIPCHK(c, hipEventRecord(c->tev[c->tev_used], s));
         }
         HIPCHK(c, launch_step(c->dp, c->dg, c->st[c->cur], c->tn[c->cur], c->cnt, c->cur, (double *)c->b.hist, c->sm,
-                              c->global_step, chunk, c->n_upper, c->block, c->p.precision == FTE_MIXED, c->tile_bytes, s));
+                              c->global_step, chunk, c->n_upper, c->block, c->p.precision == FTE_MIXED, c->tile_bytes, c->hist_bytes, s));
         if (timed) {
             HIPCHK(c, hipEventRecord(c->tev[c->tev_used + 1], s));
             c->tev_used += 2;
@@ -1764,6 +1765,15 @@ fte_status fte_set_record_tile(fte_ctx *c, int tile_bytes) {
     if (tile_bytes < 0 || tile_bytes > FTE_MAX_TILE_BYTES)
         return fail(c, FTE_EINVAL, "tile_bytes must be 0.." + std::to_string(FTE_MAX_TILE_BYTES));
     c->tile_bytes = (size_t)tile_bytes;
+    return FTE_OK;
+}
+
+fte_status fte_set_lds_histogram(fte_ctx *c, int hist_bytes) {
+    if (!c) return FTE_EINVAL;
+    NO_CAPTURE(c);
+    if (hist_bytes < 0 || hist_bytes > FTE_MAX_LDS_HIST_BYTES)
+        return fail(c, FTE_EINVAL, "hist_bytes must be 0.." + std::to_string(FTE_MAX_LDS_HIST_BYTES));
+    c->hist_bytes = (size_t)hist_bytes;
     return FTE_OK;
 }
 

@@ -123,8 +123,9 @@ struct DevTan {
 enum : int { kTanLnw = 10, kTanCols = 11 };
 
 // LDS plan of a step launch: observer time bins [it_lo, it_lo + n_tb) can be
-// accumulated in LDS (histograms up to FTE_LDS_HIST_BYTES; n_tb = 0: straight
-// to the global histogram).  Off by default: observer hits are rare enough
+// accumulated in LDS (histograms up to a budget, FTE_LDS_HIST_BYTES by
+// default, fte_set_lds_histogram at run time; n_tb = 0: straight to the
+// global histogram).  Off by default: observer hits are rare enough
 // that the global atomics cost nothing measurable, and the record tile makes
 // better use of the LDS (a fourth k-layer on the CIR workload, +3.5%).  The
 // block index can be staged in LDS too (tables up to FTE_LDS_INDEX_BYTES); on
@@ -211,7 +212,7 @@ hipError_t launch_inject(const DevParams &p, const DevGrid &g, int rec_fp32, con
 hipError_t launch_add_live(DevCounters *cnt, int slot, uint64_t n, hipStream_t s);
 hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
                        double *hist, double *sm, uint64_t n0, uint32_t n_steps, uint64_t n_upper, int block, int fp32,
-                       size_t tile_bytes, hipStream_t s);
+                       size_t tile_bytes, size_t hist_bytes, hipStream_t s);
 hipError_t launch_compact(DevState src, DevState dst, DevTan tsrc, DevTan tdst, DevCounters *cnt, int from,
                           uint64_t n_upper, int block, hipStream_t s);
 hipError_t launch_zero_live(DevCounters *cnt, int slot, hipStream_t s);

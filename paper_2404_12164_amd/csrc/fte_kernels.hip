@@ -1727,9 +1727,10 @@ static void launch_step_t(const DevParams &p, const DevGrid &g, DevState st, Dev
 
 // LDS plan of one launch: the time bins its post-step times fall in (the
 // kernel's own floor of (t + dt - t_ref) / dT at the first and last step),
-// when their histogram fits kLdsHistBytes; the block index when it fits
+// when their histogram fits hist_bytes; the block index when it fits
 // kLdsIndexBytes.
-StepLds plan_step_lds(const DevParams &p, const DevGrid &g, uint64_t n0, uint32_t n_steps, size_t *shmem, bool *lidx) {
+StepLds plan_step_lds(const DevParams &p, const DevGrid &g, uint64_t n0, uint32_t n_steps, size_t hist_bytes,
+                      size_t *shmem, bool *lidx) {
     StepLds ld{0, 0, 0, 0};
     if (p.n_obs > 0 && n_steps > 0) {
         const double t_a = p.t0 + (double)n0 * p.dt, t_b = p.t0 + (double)(n0 + n_steps - 1) * p.dt;
@@ -1739,7 +1740,7 @@ StepLds plan_step_lds(const DevParams &p, const DevGrid &g, uint64_t n0, uint32_
         if (fb >= fa) {
             const int ntb = (int)(fb - fa) + 1;
             const size_t bytes = (size_t)p.n_runs_eff * p.n_obs_bins * p.n_e * ntb * p.n_batch * 8;
-            if (bytes <= kLdsHistBytes) {
+            if (bytes <= hist_bytes) {
                 ld.it_lo = (int)fa;
                 ld.n_tb = ntb;
             }
@@ -1754,13 +1755,13 @@ StepLds plan_step_lds(const DevParams &p, const DevGrid &g, uint64_t n0, uint32_
 
 hipError_t launch_step(const DevParams &p, const DevGrid &g, DevState st, DevTan tn, DevCounters *cnt, int slot,
                        double *hist, double *sm, uint64_t n0, uint32_t n_steps, uint64_t n_upper, int block, int fp32,
-                       size_t tile_bytes, hipStream_t s) {
+                       size_t tile_bytes, size_t hist_bytes, hipStream_t s) {
     if (n_upper == 0 || n_steps == 0) return hipSuccess;
     const bool kp = p.kperp_any != 0;
     dim3 grid(blocks_for(n_upper, block)), blk(block);
     size_t shmem = 0;
     bool lidx = false;
-    StepLds ld = plan_step_lds(p, g, n0, n_steps, &shmem, &lidx);
+    StepLds ld = plan_step_lds(p, g, n0, n_steps, hist_bytes, &shmem, &lidx);
     if (fp32 && !lidx && (g.n_snap >= 2 || !p.grad) && tile_bytes > 0) {
         // as many whole padded k-layers of the live snapshots (two, or the
         // one of a steady grid) as fit, at least two

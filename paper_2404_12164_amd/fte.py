@@ -31,7 +31,8 @@ SYMBOLS = ["fte_create", "fte_destroy", "fte_last_error", "fte_query_sizes", "ft
            "fte_set_launch", "fte_reset", "fte_set_timing", "fte_bin_smoothed", "fte_grad", "fte_read_tangents",
            "fte_state_size", "fte_save_state", "fte_load_state", "fte_autotune", "fte_bin_steady",
            "fte_load_snapshot", "fte_set_record_tile", "fte_plan_snapshot", "fte_bin_observers_static",
-           "fte_capture_begin", "fte_capture_end", "fte_graph_launch", "fte_graph_destroy"]
+           "fte_capture_begin", "fte_capture_end", "fte_graph_launch", "fte_graph_destroy",
+           "fte_set_lds_histogram"]
 TANGENT_COLS = 11         # d(x, y, z, mu, lnp)/d lambda_ref, the same for kperp_ratio, d ln w / d gamma_inj
 
 
@@ -136,6 +137,7 @@ def lib():
         L.fte_autotune.argtypes = [vp, u32, C.POINTER(C.c_int), vp]
         L.fte_bin_steady.argtypes = [vp, dp, dp, vp]
         L.fte_load_snapshot.argtypes = [vp, C.c_int, C.POINTER(vp), vp]
+        L.fte_set_lds_histogram.argtypes = [vp, C.c_int]
         L.fte_capture_begin.argtypes = [vp, vp]
         L.fte_capture_end.argtypes = [vp, vp, C.POINTER(vp)]
         L.fte_graph_launch.argtypes = [vp, vp, vp]
@@ -456,6 +458,10 @@ def fte_set_record_tile(ctx, tile_bytes: int):
     _check(ctx, lib().fte_set_record_tile(ctx, int(tile_bytes)))
 
 
+def fte_set_lds_histogram(ctx, hist_bytes: int):
+    _check(ctx, lib().fte_set_lds_histogram(ctx, int(hist_bytes)))
+
+
 def fte_capture_begin(ctx, stream: int):
     _check(ctx, lib().fte_capture_begin(ctx, C.c_void_p(stream)))
 
@@ -570,6 +576,9 @@ class Simulation:
 
     def set_timing(self, enable=True):
         fte_set_timing(self.ctx, enable)
+
+    def set_lds_histogram(self, hist_bytes):
+        fte_set_lds_histogram(self.ctx, hist_bytes)
 
     def capture_begin(self):
         """Record the following inject/step calls into a launch graph (nothing runs)."""
