@@ -501,7 +501,8 @@ fte_status fte_set_lds_histogram(fte_ctx *ctx, int hist_bytes);
  * after another fte_reset).  The grid, launch shape and record tile are
  * those of the recording.  Afterwards the context is where the recorded
  * calls leave it.  Trajectories and sums are those of the same calls made
- * directly (the kernels are the same; only the launch sizes differ). */
+ * directly (the kernels are the same; only the launch sizes differ).
+ * A graph refers to its context's buffers: destroy it before the context. */
 typedef struct fte_graph fte_graph;
 fte_status fte_capture_begin(fte_ctx *ctx, void *stream);
 fte_status fte_capture_end(fte_ctx *ctx, void *stream, fte_graph **out);
