@@ -465,8 +465,9 @@ fte_status fte_set_launch(fte_ctx *ctx, int block, int steps_per_launch, int com
 #define FTE_MAX_TILE_BYTES 131072
 fte_status fte_set_record_tile(fte_ctx *ctx, int tile_bytes);
 
-/* LDS-privatised observer histogram: the observer time bins a step launch
- * can touch (its first to last post-step time) are accumulated in LDS when
+/* LDS-privatised observer histogram (where the residence-time sums behind
+ * section 2.3's intensities accumulate): the observer time bins a step
+ * launch can touch (its first to last post-step time) are accumulated in LDS when
  * their sums fit hist_bytes, and flushed with one global atomic per nonzero
  * bin at the end of the launch; otherwise every contribution is a global
  * atomic.  Counts are the same either way, sums equal up to the order of the
