@@ -187,6 +187,15 @@ def gradient_leg(F, W, raw, args):
     p_grad = cfg["params"]
     if args.kink_sigma is not None:
         p_grad = dict(p_grad, kink_sigma=args.kink_sigma)
+    if args.grad_dt_scale != 1.0:
+        # the same physical run in steps scaled by grad_dt_scale (the
+        # injection spread over the same time)
+        s = args.grad_dt_scale
+        n_steps = int(round(n_steps / s))
+        chunk = n_steps // 10
+        p_grad = dict(p_grad, dt=p_grad["dt"] * s)
+        inj = dict(cfg["injection"], n_inj_steps=int(round(cfg["injection"]["n_inj_steps"] / s)))
+        cfg = dict(cfg, n_steps=n_steps, injection=inj)
     p_smooth = dict(p_grad, grad=0)
     p_plain = {k: v for k, v in p_grad.items() if k not in ("smoothing", "grad", "kink_sigma")}
 
@@ -197,7 +206,7 @@ def gradient_leg(F, W, raw, args):
         return r, res
 
     out = {"workload": cfg["name"], "particles": cfg["n_particles"], "global_steps": n_steps,
-           "kink_sigma": p_grad["kink_sigma"]}
+           "dt": p_grad["dt"], "kink_sigma": p_grad["kink_sigma"]}
     r, res = run(p_plain)
     r.close()
     # warm the other two modes once, untimed, then time them
@@ -760,6 +769,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--grad-seeds", type=int, default=8, help="seeds of the gradient-vs-differences check")
+    ap.add_argument("--grad-dt-scale", type=float, default=1.0,
+                    help="step of the gradient leg relative to the workload's (same physical run)")
     ap.add_argument("--kink-sigma", type=float, default=None,
                     help="width of the Gaussian mu = 0 term of the gradient leg (default: the workload's)")
     ap.add_argument("--no-largest", action="store_true", help="skip the largest workload")
