@@ -62,7 +62,7 @@ def read_counters(name, kernel):
 class Run:
     """One context on the workload plus its lazy continuous-injection plan."""
 
-    def __init__(self, F, cfg, raw, precision, block, spl, compact, sort=1, load=True, tile=None):
+    def __init__(self, F, cfg, raw, precision, block, spl, compact, sort=1, load=True, tile=None, inj_every=None):
         import torch
         self.torch = torch
         self.cfg = cfg
@@ -80,6 +80,7 @@ class Run:
         if tile is not None:
             self.sim.set_record_tile(tile)
         self.sim.set_timing(True)
+        self.every = int(inj_every or spl)
         self.injected = 0
         self.n0 = 0
 
@@ -89,17 +90,24 @@ class Run:
         self.n0 = 0
 
     def chunk(self, n):
-        """Inject every pid whose first step can fall before n0 + n, then step."""
-        n1 = self.n0 + n
-        if self.S > 0:
-            j_max = min(self.N, int(math.ceil(n1 * self.N / self.S)) + 1)
-        else:
-            j_max = self.N
-        if j_max > self.injected:
-            self.sim.inject(self.inj, j_max - self.injected, self.inj.get("pid0", 0) + self.injected)
-            self.injected = j_max
-        self.sim.step(n)
-        self.n0 = n1
+        """Step n global steps of the continuous injection: before each
+        launch's worth of steps (up to the next multiple of steps_per_launch,
+        or of inj_every), inject every pid whose first step can fall before
+        its end.  A pid injected ahead of its first step holds a lane of the
+        waves that step the others until then, so the injection keeps pace
+        with the launches rather than with the caller's chunks."""
+        end = self.n0 + n
+        while self.n0 < end:
+            n1 = min(end, (self.n0 // self.every + 1) * self.every)
+            if self.S > 0:
+                j_max = min(self.N, int(math.ceil(n1 * self.N / self.S)) + 1)
+            else:
+                j_max = self.N
+            if j_max > self.injected:
+                self.sim.inject(self.inj, j_max - self.injected, self.inj.get("pid0", 0) + self.injected)
+                self.injected = j_max
+            self.sim.step(n1 - self.n0)
+            self.n0 = n1
 
     def close(self):
         self.sim.close()
@@ -333,6 +341,23 @@ def ensemble_leg(F, W, args):
     out = {"workload": cfg["name"], "runs": len(cfg["runs"]), "particles": N,
            "max_steps": cfg["n_steps"], "snapshots": g["n_snap"], "leaves": int(len(g["leaves"]))}
     chunk = 640
+    # one injection call per run per interval: a coarser interval than one
+    # launch trades a few idle lanes for fewer launches of the 64 runs
+    every = args.ens_inj_every
+
+    def advance(sim, injected, n0, n1):
+        """Steps n0..n1 of the ensemble, each run's continuous injection kept
+        `every` steps ahead (as Run.chunk does for one run)."""
+        while n0 < n1:
+            n2 = min(n1, (n0 // every + 1) * every)
+            for r, inj in enumerate(cfg["injections"]):
+                S, Nr = inj["n_inj_steps"], inj["n_total"]
+                j_max = min(Nr, int(math.ceil(n2 * Nr / S)) + 1)
+                if j_max > injected[r]:
+                    sim.inject(inj, j_max - injected[r], inj["pid0"] + injected[r])
+                    injected[r] = j_max
+            sim.step(n2 - n0)
+            n0 = n2
 
     def ensemble(tune):
         sim = F.Simulation(p, g, N)
@@ -352,13 +377,7 @@ def ensemble_leg(F, W, args):
                 best = sim.autotune(4 * args.spl)
                 t_tune = time.time() - t
             e0.record()
-            for r, inj in enumerate(cfg["injections"]):
-                S, Nr = inj["n_inj_steps"], inj["n_total"]
-                j_max = min(Nr, int(math.ceil(n1 * Nr / S)) + 1)
-                if j_max > injected[r]:
-                    sim.inject(inj, j_max - injected[r], inj["pid0"] + injected[r])
-                    injected[r] = j_max
-            sim.step(n1 - n0)
+            advance(sim, injected, n0, n1)
             e1.record()
             torch.cuda.synchronize()
             ms += e0.elapsed_time(e1)
@@ -382,13 +401,7 @@ def ensemble_leg(F, W, args):
             n0 = 0
             while n0 < cfg["n_steps"]:
                 n1 = min(n0 + chunk, cfg["n_steps"])
-                for r, inj in enumerate(cfg["injections"]):
-                    S, Nr = inj["n_inj_steps"], inj["n_total"]
-                    j_max = min(Nr, int(math.ceil(n1 * Nr / S)) + 1)
-                    if j_max > injected[r]:
-                        sim.inject(inj, j_max - injected[r], inj["pid0"] + injected[r])
-                        injected[r] = j_max
-                sim.step(n1 - n0)
+                advance(sim, injected, n0, n1)
                 n0 = n1
         side = torch.cuda.Stream()
         torch.cuda.synchronize()
@@ -430,7 +443,7 @@ def ensemble_leg(F, W, args):
         q.update(run_id=p["run_id"] + r, lambda_ref=run["lambda_ref"], kperp_ratio=run["kperp_ratio"])
         inj = dict(cfg["injections"][r], run=0)
         c1 = dict(cfg, params=q, injection=inj, n_particles=inj["n_total"])
-        rr = Run(F, c1, raw, args.precision, args.block, args.spl, args.compact, args.sort)
+        rr = Run(F, c1, raw, args.precision, args.block, args.spl, args.compact, args.sort, inj_every=every)
         n_chunks = int(math.ceil(run["n_steps"] / chunk))
         ch = int(math.ceil(run["n_steps"] / n_chunks))
         torch.cuda.synchronize()
@@ -545,14 +558,16 @@ def pool_leg(F, W, args, hours=12.0, wind_max=800e3):
         k = done // per
         if k > 0 and done % per == 0 and k + 1 < g["n_snap"]:
             load(k + 1)
-        m = min((k + 1) * per, n_steps) - done
-        n1 = done + m
-        j_max = min(N, int(math.ceil(n1 * N / S)) + 1)
-        if j_max > injected[0]:
-            sim.inject(inj, j_max - injected[0], injected[0])
-            injected[0] = j_max
-        sim.step(m)
-        done = n1
+        n1 = min((k + 1) * per, n_steps)
+        while done < n1:
+            # the injection a launch ahead, as Run.chunk
+            n2 = min(n1, (done // args.spl + 1) * args.spl)
+            j_max = min(N, int(math.ceil(n2 * N / S)) + 1)
+            if j_max > injected[0]:
+                sim.inject(inj, j_max - injected[0], injected[0])
+                injected[0] = j_max
+            sim.step(n2 - done)
+            done = n2
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
@@ -780,6 +795,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--grad-seeds", type=int, default=8, help="seeds of the gradient-vs-differences check")
+    ap.add_argument("--ens-inj-every", type=int, default=256,
+                    help="global steps between the ensemble's injection calls (a multiple of --spl)")
     ap.add_argument("--iso-seeds", type=int, default=2,
                     help="seeds of the same check with ISO scattering (the control)")
     ap.add_argument("--grad-dt-scale", type=float, default=1.0,

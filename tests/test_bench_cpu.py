@@ -43,3 +43,41 @@ def test_counters_apply_only_to_their_kernel(tmp_path, monkeypatch, same_source,
         assert got["hbm_bytes_per_particle_step"] == 250.5 and got["valu_insts_per_particle_step"] == 21.0
     else:
         assert got is None
+
+
+class _Recorder:
+    """Stands in for a Simulation: records the inject and step calls."""
+
+    def __init__(self):
+        self.calls = []
+
+    def inject(self, inj, n, first_pid):
+        self.calls.append(("inject", n, first_pid))
+
+    def step(self, n):
+        self.calls.append(("step", n))
+
+
+@pytest.mark.parametrize("chunks", [[564] * 5, [846, 846, 100], [5640], [1, 63, 64, 65, 700]])
+def test_injection_keeps_pace_with_launches(chunks):
+    """Continuous injection in the bench: every call steps at most up to the
+    next multiple of steps_per_launch, and before it every pid whose first
+    step (pid * S / N) falls before that call's end has been injected, in pid
+    order, whatever chunks the caller asks for."""
+    N, S, spl = 100_000, 16_920, 64
+    r = object.__new__(bench.Run)
+    r.sim, r.inj, r.N, r.S, r.every, r.injected, r.n0 = _Recorder(), {"pid0": 0}, N, S, spl, 0, 0
+    for m in chunks:
+        r.chunk(m)
+    n0, injected = 0, 0
+    for c in r.sim.calls:
+        if c[0] == "inject":
+            assert c[2] == injected and c[1] > 0
+            injected += c[1]
+            continue
+        n1 = n0 + c[1]
+        assert c[1] > 0 and (n1 - 1) // spl == n0 // spl       # within one launch window
+        # every pid whose first step can fall before n1 is there, no more
+        assert injected == min(N, -(-n1 * N // S) + 1)
+        n0 = n1
+    assert n0 == sum(chunks) and r.n0 == n0
