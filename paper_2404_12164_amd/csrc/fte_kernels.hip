@@ -1117,9 +1117,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
     }
     for (int k = threadIdx.x; k < n_lh; k += blockDim.x) lh[k] = 0.0;
     if (LIDX || n_lh > 0) __syncthreads();
-    // record tile (float kernels, time-dependent grid): anchored at the leaf
-    // and k-layer of the workgroup's middle particle, for the snapshot pair of
-    // the launch's first step
+    // record tile (float kernels): anchored at the leaf and k-layer of the
+    // workgroup's middle particle, for the snapshot pair of the launch's
+    // first step (the one snapshot of a steady grid)
     constexpr bool kTile = std::is_same<R, float>::value && !LIDX;
     // each particle's leaf from its previous step (float kernels; the double
     // ones spill more with its registers and lost 4%)
@@ -1143,14 +1143,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_wpe<R,
                 fold_s<R>(G, as);
                 const int aleaf = descend<R>(G, ibase, ichild, as, aS, aB);
                 if (aleaf >= 0) {
+                    // the particles of cell c read padded layers c .. c + 2
+                    // (c + 1 is the cell's own): an odd number of layers is
+                    // centred on the cell, an even number on the middle
+                    // particle's lower corner layer (the half of the cell
+                    // it is in)
+                    const R half = (LD.tile_layers & 1) ? (R)0 : (R)0.5;
                     anchor[0] = aleaf;
-                    anchor[1] = (int)M<R>::floor_(aS[2] - (R)(aB[2] * G.bx[2]) - (R)0.5) + 1;
+                    anchor[1] = (int)M<R>::floor_(aS[2] - (R)(aB[2] * G.bx[2]) - half) + 1;
                 }
             }
             __syncthreads();
             if (anchor[0] >= 0) {
                 const int TL = LD.tile_layers, pz = G.px[2];
-                int k0 = anchor[1] - (TL - 2) / 2;
+                int k0 = anchor[1] - (TL - 1) / 2;
                 k0 = k0 > pz - TL ? pz - TL : k0;
                 k0 = k0 < 0 ? 0 : k0;
                 // the snapshot pair of the launch's first step (one snapshot
