@@ -133,16 +133,17 @@ enum : int { kTanLnw = 10, kTanCols = 11 };
 // it is off unless the limit is raised at build time.
 //
 // Record tile: the float step kernels (histogram, smoothed and tangent
-// modes, single runs and ensembles, with or without cross-field records) on
-// time-dependent grids stage, per workgroup, whole padded k-layers of one leaf
-// for both live snapshots in LDS (as many as fit the budget, at least two;
-// the budget is the LDS that leaves two workgroups per CU, three for the
-// steady-grid kernels, capped by FTE_LDS_TILE_BYTES; 0 turns it off;
-// fte_set_record_tile sets the cap at run time), anchored at the workgroup's
-// middle particle; corners that lie in it are read from LDS, the others
-// through the L1.  After the spatial sort a workgroup's particles sit in few
-// k-layers of one leaf, and LDS serves such divergent reads several times
-// faster than the L1.
+// modes, single runs and ensembles, with or without cross-field records)
+// stage, per workgroup, whole padded k-layers of one leaf in LDS, for both
+// live snapshots of a time-dependent grid or the one of a steady grid (as
+// many as fit the budget, at least two; the budget is the LDS that leaves
+// two workgroups per CU, three for the steady-grid kernels, capped by
+// FTE_LDS_TILE_BYTES; 0 turns it off; fte_set_record_tile sets the cap at run
+// time), anchored at the workgroup's middle particle (an odd number of
+// layers centred on its cell); corners that lie in it are read from LDS, the
+// others through the L1.  After the spatial sort a workgroup's particles sit
+// in few k-layers of one leaf, and LDS serves such divergent reads several
+// times faster than the L1.
 struct StepLds {
     int it_lo, n_tb;
     int tile_layers;  // padded k-layers in the tile (0: no tile)

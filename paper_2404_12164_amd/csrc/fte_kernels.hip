@@ -674,25 +674,27 @@ __device__ __forceinline__ void tile_rec(lds_float *p, R out[NF]) {
     }
 }
 
-// Float kernels with the record tile whose gather loads each lane's corners
-// from its own source (tile or global) and interpolates once: the plain
-// forward kernels with 10-field records, two snapshots (bit 1) or a steady
-// grid (bit 2).  The 13-field records (cross-field diffusion) hold too many
-// values for it; the ensemble and leaf-pool instances would spill.
-// Consecutive particle slices per XCD (see k_step).  Measured on the CIR
-// workload: 1 (the hardware's own order) 2.61, 8 2.65, 32 2.66, 128 2.62,
-// all (one contiguous share per XCD) 2.07 x 10^10 particle-steps/s; FP64
-// 7.35, 32 8.36, 128 8.33 x 10^9.
 // Skip the block-index walk while a particle stays in its leaf (see
 // descend_cached): CIR 2.66 -> 2.72 x 10^10 particle-steps/s, largest
 // workload +2%.
 #ifndef FTE_LEAF_CACHE
 #define FTE_LEAF_CACHE 1
 #endif
+// Consecutive particle slices per XCD (see k_step).  Measured on the CIR
+// workload: 1 (the hardware's own order) 2.61, 8 2.65, 32 2.66, 128 2.62,
+// all (one contiguous share per XCD) 2.07 x 10^10 particle-steps/s; FP64
+// 7.35, 32 8.36, 128 8.33 x 10^9.
 #ifndef FTE_XCD_RUN
 #define FTE_XCD_RUN 32
 #endif
 constexpr uint32_t kXcdRun = FTE_XCD_RUN;
+// Float kernels with the record tile whose gather loads each lane's corners
+// from its own source (tile or global) and interpolates once: the plain
+// forward kernels with 10-field records, two snapshots (bit 1) or a steady
+// grid (bit 2).  With the 13-field records (cross-field diffusion) it
+// spills some 50 registers, even split into two passes over the fields, and
+// runs a third slower; the ensemble instance fits but runs no faster; the
+// leaf-pool instance gathers through its map.
 #ifndef FTE_TILE_UNIFIED
 #define FTE_TILE_UNIFIED 1
 #endif
