@@ -59,6 +59,27 @@ def read_counters(name, kernel):
     return out
 
 
+def advance(sim, injections, injected, n0, n1, every):
+    """Steps n0 .. n1 of continuous injections (one per run) on `sim`.
+    Before each stretch of steps up to the next multiple of `every`, every
+    pid of every injection whose first step can fall before the stretch's end
+    is injected (injected[r] counts run r's pids so far).  A pid injected
+    ahead of its first step holds a lane of the waves that step the others
+    until then, so the injection keeps pace with the launches rather than
+    with the caller's chunks."""
+    while n0 < n1:
+        n2 = min(n1, (n0 // every + 1) * every)
+        for r, inj in enumerate(injections):
+            S, Nr = inj["n_inj_steps"], inj["n_total"]
+            j_max = min(Nr, int(math.ceil(n2 * Nr / S)) + 1) if S > 0 else Nr
+            if j_max > injected[r]:
+                sim.inject(inj, j_max - injected[r], inj.get("pid0", 0) + injected[r])
+                injected[r] = j_max
+        sim.step(n2 - n0)
+        n0 = n2
+    return n0
+
+
 class Run:
     """One context on the workload plus its lazy continuous-injection plan."""
 
@@ -81,33 +102,19 @@ class Run:
             self.sim.set_record_tile(tile)
         self.sim.set_timing(True)
         self.every = int(inj_every or spl)
-        self.injected = 0
+        self.injected = [0]
         self.n0 = 0
 
     def reset(self):
         self.sim.reset()
-        self.injected = 0
+        self.injected = [0]
         self.n0 = 0
 
     def chunk(self, n):
-        """Step n global steps of the continuous injection: before each
-        launch's worth of steps (up to the next multiple of steps_per_launch,
-        or of inj_every), inject every pid whose first step can fall before
-        its end.  A pid injected ahead of its first step holds a lane of the
-        waves that step the others until then, so the injection keeps pace
-        with the launches rather than with the caller's chunks."""
-        end = self.n0 + n
-        while self.n0 < end:
-            n1 = min(end, (self.n0 // self.every + 1) * self.every)
-            if self.S > 0:
-                j_max = min(self.N, int(math.ceil(n1 * self.N / self.S)) + 1)
-            else:
-                j_max = self.N
-            if j_max > self.injected:
-                self.sim.inject(self.inj, j_max - self.injected, self.inj.get("pid0", 0) + self.injected)
-                self.injected = j_max
-            self.sim.step(n1 - self.n0)
-            self.n0 = n1
+        """Step n global steps, the injection a launch (steps_per_launch, or
+        inj_every) ahead (see advance)."""
+        self.n0 = advance(self.sim, [dict(self.inj, n_total=self.N, n_inj_steps=self.S)], self.injected,
+                          self.n0, self.n0 + n, self.every)
 
     def close(self):
         self.sim.close()
@@ -345,20 +352,6 @@ def ensemble_leg(F, W, args):
     # launch trades a few idle lanes for fewer launches of the 64 runs
     every = args.ens_inj_every
 
-    def advance(sim, injected, n0, n1):
-        """Steps n0..n1 of the ensemble, each run's continuous injection kept
-        `every` steps ahead (as Run.chunk does for one run)."""
-        while n0 < n1:
-            n2 = min(n1, (n0 // every + 1) * every)
-            for r, inj in enumerate(cfg["injections"]):
-                S, Nr = inj["n_inj_steps"], inj["n_total"]
-                j_max = min(Nr, int(math.ceil(n2 * Nr / S)) + 1)
-                if j_max > injected[r]:
-                    sim.inject(inj, j_max - injected[r], inj["pid0"] + injected[r])
-                    injected[r] = j_max
-            sim.step(n2 - n0)
-            n0 = n2
-
     def ensemble(tune):
         sim = F.Simulation(p, g, N)
         sim.load_grid(raw)
@@ -377,7 +370,7 @@ def ensemble_leg(F, W, args):
                 best = sim.autotune(4 * args.spl)
                 t_tune = time.time() - t
             e0.record()
-            advance(sim, injected, n0, n1)
+            advance(sim, cfg["injections"], injected, n0, n1, every)
             e1.record()
             torch.cuda.synchronize()
             ms += e0.elapsed_time(e1)
@@ -401,7 +394,7 @@ def ensemble_leg(F, W, args):
             n0 = 0
             while n0 < cfg["n_steps"]:
                 n1 = min(n0 + chunk, cfg["n_steps"])
-                advance(sim, injected, n0, n1)
+                advance(sim, cfg["injections"], injected, n0, n1, every)
                 n0 = n1
         side = torch.cuda.Stream()
         torch.cuda.synchronize()
@@ -558,16 +551,7 @@ def pool_leg(F, W, args, hours=12.0, wind_max=800e3):
         k = done // per
         if k > 0 and done % per == 0 and k + 1 < g["n_snap"]:
             load(k + 1)
-        n1 = min((k + 1) * per, n_steps)
-        while done < n1:
-            # the injection a launch ahead, as Run.chunk
-            n2 = min(n1, (done // args.spl + 1) * args.spl)
-            j_max = min(N, int(math.ceil(n2 * N / S)) + 1)
-            if j_max > injected[0]:
-                sim.inject(inj, j_max - injected[0], injected[0])
-                injected[0] = j_max
-            sim.step(n2 - done)
-            done = n2
+        done = advance(sim, [inj], injected, done, min((k + 1) * per, n_steps), args.spl)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)

@@ -66,7 +66,7 @@ def test_injection_keeps_pace_with_launches(chunks):
     order, whatever chunks the caller asks for."""
     N, S, spl = 100_000, 16_920, 64
     r = object.__new__(bench.Run)
-    r.sim, r.inj, r.N, r.S, r.every, r.injected, r.n0 = _Recorder(), {"pid0": 0}, N, S, spl, 0, 0
+    r.sim, r.inj, r.N, r.S, r.every, r.injected, r.n0 = _Recorder(), {"pid0": 0}, N, S, spl, [0], 0
     for m in chunks:
         r.chunk(m)
     n0, injected = 0, 0
@@ -81,3 +81,32 @@ def test_injection_keeps_pace_with_launches(chunks):
         assert injected == min(N, -(-n1 * N // S) + 1)
         n0 = n1
     assert n0 == sum(chunks) and r.n0 == n0
+
+
+def test_advance_paces_every_run():
+    """Several runs (an ensemble): before each stretch of steps every run has
+    injected exactly its pids whose first step can fall before the
+    stretch's end, from its own first pid; a run injected all at once
+    (n_inj_steps 0) is injected before the first stretch."""
+    injs = [dict(n_total=1000, n_inj_steps=3000, pid0=0), dict(n_total=50, n_inj_steps=700, pid0=1000),
+            dict(n_total=7, n_inj_steps=0, pid0=1050)]
+    sim, injected, every = _Recorder(), [0, 0, 0], 256
+    n0 = 0
+    for n1 in (640, 1280, 1281, 3000):
+        n0 = bench.advance(sim, injs, injected, n0, n1, every)
+        assert n0 == n1
+    done = [0, 0, 0]
+    pos = 0
+    for c in sim.calls:
+        if c[0] == "inject":
+            r = [q for q, inj in enumerate(injs) if inj["pid0"] <= c[2] < inj["pid0"] + inj["n_total"]][0]
+            assert c[2] == injs[r]["pid0"] + done[r]
+            done[r] += c[1]
+            continue
+        end = pos + c[1]
+        assert (end - 1) // every == pos // every
+        for r, inj in enumerate(injs):
+            S, Nr = inj["n_inj_steps"], inj["n_total"]
+            assert done[r] == (min(Nr, -(-end * Nr // S) + 1) if S else Nr)
+        pos = end
+    assert pos == 3000 and done == [1000, 50, 7] and injected == done
