@@ -780,7 +780,8 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--grad-seeds", type=int, default=8, help="seeds of the gradient-vs-differences check")
     ap.add_argument("--ens-inj-every", type=int, default=256,
-                    help="global steps between the ensemble's injection calls (a multiple of --spl)")
+                    help="global steps between the ensemble's injection calls (a multiple of --spl keeps "
+                         "every launch whole)")
     ap.add_argument("--iso-seeds", type=int, default=2,
                     help="seeds of the same check with ISO scattering (the control)")
     ap.add_argument("--grad-dt-scale", type=float, default=1.0,
