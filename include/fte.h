@@ -450,7 +450,7 @@ fte_status fte_set_timing(fte_ctx *ctx, int enable);
  * multiple of steps_per_launch; 0 = never), and whether that removal also
  * regroups the live particles by leaf and cube of cells so that a wavefront
  * gathers from neighbouring records: spatial_sort 0 keeps the storage order,
- * 1, 2, 3 sort by cubes of 1, 2, 4 cells per edge.  Defaults 256 / 32 / 128 / 2. */
+ * 1, 2, 3 sort by cubes of 1, 2, 4 cells per edge.  Defaults 256 / 64 / 64 / 1. */
 fte_status fte_set_launch(fte_ctx *ctx, int block, int steps_per_launch, int compact_every, int spatial_sort);
 
 /* LDS record tile of the float (FTE_MIXED) step kernels on time-dependent

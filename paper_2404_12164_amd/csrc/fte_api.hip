@@ -55,14 +55,16 @@ struct fte_ctx {
     uint64_t sm_n = 0;
     uint32_t *keys = nullptr, *counts = nullptr, *tsum = nullptr;
     uint32_t n_keys = 0;
-    int sort = 2;
+    int sort = 1;
     uint64_t hist_n = 0;
     uint64_t n_upper = 0, injected_since = 0;
     unsigned long long *pinned = nullptr;
     hipEvent_t ev = nullptr;
     bool pending = false;
     uint64_t global_step = 0;
-    int block = 256, spl = 32, compact_every = 128;
+    // the launch shape measured best on every workload (CIR, ensemble autotuner,
+    // largest, paper): 256 threads, 64 steps per launch, a per-cell sort every 64
+    int block = 256, spl = 64, compact_every = 64;
     size_t tile_bytes = kLdsTileBytes;   // LDS record tile budget of the float step kernels
     size_t hist_bytes = kLdsHistBytes;   // LDS observer-histogram budget of the step kernels
     uint64_t since_compact = 0;

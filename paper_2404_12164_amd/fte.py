@@ -565,7 +565,7 @@ class Simulation:
         ptrs = [base + j * step if 0 <= j < ns else 0 for j in range(k - 2, k + 3)]
         fte_load_snapshot(self.ctx, k, ptrs, self.stream)
 
-    def set_launch(self, block=256, steps_per_launch=32, compact_every=128, spatial_sort=2):
+    def set_launch(self, block=256, steps_per_launch=64, compact_every=64, spatial_sort=1):
         fte_set_launch(self.ctx, block, steps_per_launch, compact_every, spatial_sort)
 
     def set_record_tile(self, tile_bytes):
